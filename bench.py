@@ -1,0 +1,135 @@
+#!/usr/bin/env python3
+"""Rand-QLP throughput on one MI355X.
+
+Workload: A = G1 G2 + E, 8000 x 8000 (rank-200 Gaussian product plus iid
+noise at 1e-3 of the signal's RMS), fp64, k = 200, p = 10, q = 2 (d = 210).
+A is resident in HBM before timing starts.  One step = one full
+randqlp_factor call (Gaussian sketch, 2q+3 products with A, 2q+3 panel QRs,
+L = R^T).  Throughput = the Section 4.2 flop model / measured time.
+
+Prints one JSON line with the roofline of the dominant kernel (the product
+kernel that streams A, timed with HIP events on its stream) and the fp64 CPU
+oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Rand-QLP GFLOP/s + % roofline at fixed error; BF16+learned-q vs FP64 plain"
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(A, k, p, q, flops, budget_s=12.0, max_reps=4):
+    """The fp64 oracle on the host cores, on whole factorisations of A."""
+    from threadpoolctl import threadpool_info
+    from oracle import randqlp, rel_error
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+    times, e = [], None
+    t_start = time.perf_counter()
+    while len(times) < max_reps and (time.perf_counter() - t_start) < budget_s:
+        t0 = time.perf_counter()
+        Q, L, P = randqlp(A, k, p, q, seed=0)
+        times.append(time.perf_counter() - t0)
+        if e is None:
+            e = rel_error(A, Q, L, P)
+        log(f"  oracle rep {len(times)}: {times[-1]:.2f} s")
+    t = sorted(times)[len(times) // 2]
+    return {"value": flops / t / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(times)} whole fp64 factorisations of the same {A.shape[0]}x{A.shape[1]} "
+                      f"matrix (median {t:.2f} s each, Omega generation included)"}, e
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--size", type=int, default=8000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the factorisation of one matrix runs on a "
+              "single MI355X (multi-GPU sharding is described, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2110_01011_amd as rq
+    import workloads as W
+    from paper_2110_01011_amd.metrics import PEAK_TFLOPS, randqlp_flops
+
+    m = n = args.size
+    r, k, p, q = 200, 200, 10, 2
+    d = rq.sketch_width(m, n, k, p)
+    log(f"generating {m}x{n} rank-{r} + noise matrix")
+    A64, s = W.rank_plus_noise(m, n, r, 1e-3, seed=0)
+    tdt = torch.float64 if args.precision == "f64" else torch.float32
+    Ad = rq.colmajor(torch.from_numpy(np.ascontiguousarray(A64.T)).to(tdt).cuda().t())
+    torch.cuda.synchronize()
+    flops = randqlp_flops(m, n, d, q)
+
+    log("warmup")
+    for i in range(args.warmup):
+        rq.factor(Ad, k, p, q, seed=i)
+    torch.cuda.synchronize()
+    rq.profile_read()
+    rq.profile_enable(True)
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        Q, L, P = rq.factor(Ad, k, p, q, seed=0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rq.profile_enable(False)
+    kms, launches, kflops, kbytes = rq.profile_read()
+    ms = (t1 - t0) * 1e3 / args.steps
+    value = flops / (ms * 1e-3) / 1e9
+
+    avg_ms = kms / max(launches, 1)
+    achieved = (kflops / max(launches, 1)) / (avg_ms * 1e-3) / 1e12
+    peak = PEAK_TFLOPS[args.precision]
+    roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": "gemm_kernel (products with A)", "avg_ms": round(avg_ms, 4),
+                "flops_per_launch": kflops / max(launches, 1),
+                "bytes_per_launch": kbytes / max(launches, 1)}
+
+    Qn, Ln, Pn = (t.double().cpu().numpy() for t in (Q, L, P))
+    from numpy.linalg import norm
+    e_gpu = float(norm(A64 - Qn @ (Ln @ Pn.T)) / norm(A64))
+    cpu = None
+    e_orc = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu, e_orc = cpu_baseline(A64, k, p, q, flops)
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": f"rank-{r} Gaussian product + 1e-3 noise, {m}x{n}, "
+                               f"k={k} p={p} q={q} (d={d}), {args.precision}",
+                   "m": m, "n": n, "k": k, "p": p, "q": q, "d": d,
+                   "flops_per_step": flops},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "error": {"e_gpu": e_gpu, "e_oracle": e_orc,
+                  "ratio": (e_gpu / e_orc) if e_orc else None},
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

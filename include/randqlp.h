@@ -1,0 +1,153 @@
+/*
+ * randqlp.h -- C ABI of the MI355X (gfx950) randomized QLP library.
+ *
+ * Randomized QLP (Kaloorazi, Liu, Chen, de Lamare, arXiv 2110.01011,
+ * Section 3, Algorithm 1) factors an m x n matrix A as A ~= Q L P^T with Q
+ * (m x d) and P (n x d) orthonormal and L (d x d) lower-triangular whose
+ * diagonal tracks the singular values of A.  This library computes the
+ * generalised form with d = min(k + p, m, n) sketch columns and q power
+ * iterations:
+ *
+ *   Omega (m x d) standard Gaussian                  (the randn step)
+ *   Qbar = orth(A^T Omega)                            (first orth)
+ *   repeat q times: Q = orth(A Qbar); Qbar = orth(A^T Q)
+ *   Q = orth(A Qbar)                                  (range basis)
+ *   P R = A^T Q = (Q^T A)^T,  L = R^T                 (final QR)
+ *
+ * orth() is the reduced, unpivoted QR with a non-negative R diagonal; q = 0
+ * and d = n is Algorithm 1 itself.  Omega is Philox4x64-10 (key = (seed, 0),
+ * counter = (l / 4, 0, 0, 0) for the column-major index l = i + j*m, lane
+ * l % 4) mapped to normals by Box-Muller, so the leading columns of Omega,
+ * Q, P and L do not depend on p.
+ *
+ * Conventions for every entry point:
+ *  - All matrices are column-major with a leading dimension; all matrix
+ *    pointers are DEVICE pointers on the current HIP device.
+ *  - The caller owns A, Q, L, P.  A is read-only.  Q (m x d), L (d x d) and
+ *    P (n x d) are completely overwritten, including the zeros above the
+ *    diagonal of L.
+ *  - Argument errors are reported before any work is enqueued.
+ *  - randqlp_factor returns after the work has completed on opts->stream
+ *    (it reads back a small status word), so the outputs are ready.
+ *  - The last error message is kept per thread (randqlp_last_error).
+ */
+#ifndef RANDQLP_H
+#define RANDQLP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RQLP_OK = 0,
+  RQLP_E_INVALID_ARG = 1,  /* bad size, pointer, leading dimension, option */
+  RQLP_E_NONFINITE = 2,    /* A holds NaN or Inf; outputs are unspecified  */
+  RQLP_E_NOMEM = 3,        /* device allocation failed                     */
+  RQLP_E_WORKSPACE = 4,    /* caller workspace smaller than required       */
+  RQLP_E_HIP = 5,          /* a HIP runtime call or kernel launch failed   */
+  RQLP_E_UNSUPPORTED = 6   /* combination not implemented (see message)    */
+} rqlp_status;
+
+/* Element types:
+ *  RQLP_F64  A, Q, L, P double.
+ *  RQLP_F32  A, Q, P float; L double.  Gram matrices and Cholesky factors
+ *            are always formed in double. */
+typedef enum { RQLP_F64 = 0, RQLP_F32 = 1 } rqlp_precision;
+
+/* Panel QR used for every orth():
+ *  AUTO    Cholesky QR with a second pass; if any pass reports a non-positive
+ *          or unsafe pivot, the whole factorisation is recomputed with ROBUST.
+ *  CHOLQR2 Cholesky QR with a second pass only (no automatic retry).
+ *  ROBUST  shifted Cholesky QR, completion of numerically dependent columns
+ *          by fresh Gaussian directions, then two more Cholesky QR passes:
+ *          an orthonormal Q for any panel, rank-deficient or zero. */
+typedef enum { RQLP_PANEL_AUTO = 0, RQLP_PANEL_CHOLQR2 = 1, RQLP_PANEL_ROBUST = 2 } rqlp_panel;
+
+typedef struct {
+  int32_t d;            /* sketch width used                              */
+  int32_t q_used;       /* power iterations performed                     */
+  int32_t breakdowns;   /* Cholesky passes that flagged an unsafe pivot   */
+  int32_t robust_rerun; /* 1 if the factorisation was redone with ROBUST  */
+  int32_t completed;    /* dependent columns replaced by fresh directions */
+  int32_t reserved;
+} rqlp_info;
+
+typedef struct {
+  int32_t precision;       /* rqlp_precision                               */
+  int32_t panel_qr;        /* rqlp_panel                                   */
+  int64_t lda, ldq, ldl, ldp; /* leading dimensions; 0 means tight (rows)  */
+  void* stream;            /* hipStream_t to run on; NULL = null stream    */
+  void* workspace;         /* device scratch; NULL = library-managed cache */
+  size_t workspace_bytes;  /* size of workspace when given                 */
+  rqlp_info* info;         /* optional host struct filled on return        */
+} rqlp_opts;
+
+/* Fill *opts with defaults: F64, AUTO, tight leading dimensions, null
+ * stream, library-managed workspace, no info. */
+void rqlp_opts_default(rqlp_opts* opts);
+
+/* d = min(k + p, m, n), or -1 for negative or zero sizes / k < 1 / p < 0. */
+int64_t randqlp_sketch_width(int64_t m, int64_t n, int k, int p);
+
+/* Bytes of device workspace randqlp_factor needs for these sizes and
+ * options (opts may be NULL for defaults); 0 for invalid arguments. */
+size_t randqlp_workspace_size(int64_t m, int64_t n, int k, int p, int q,
+                              const rqlp_opts* opts);
+
+/* Generalised Algorithm 1 (Section 3.1): A (m x n, device, lda) ->
+ * Q (m x d, ldq), L (d x d, ldl, lower-triangular, diag >= 0),
+ * P (n x d, ldp).  k >= 1 target rank, p >= 0 oversampling, q >= 0 power
+ * iterations, seed keys the Gaussian sketch.  opts may be NULL.
+ * Returns RQLP_OK, an argument error (nothing enqueued), RQLP_E_NONFINITE
+ * (A holds NaN/Inf), or a HIP / allocation error. */
+rqlp_status randqlp_factor(const void* A, int64_t m, int64_t n, int k, int p, int q,
+                           uint64_t seed, void* Q, void* L, void* P,
+                           const rqlp_opts* opts);
+
+/* ---- Step-level entry points (the individual steps of the method; the
+ * same kernels randqlp_factor runs).  Asynchronous on `stream`. ---- */
+
+/* The randn step of Algorithm 1: Omega (m x d, ld >= m) of precision
+ * RQLP_F64 or RQLP_F32 from (seed, stream_id) as described above. */
+rqlp_status randqlp_gaussian(void* out, int64_t m, int64_t d, int64_t ld, uint64_t seed,
+                             uint64_t stream_id, int precision, void* stream);
+
+/* The sketch / power / projection products of Algorithm 1:
+ * C (rows x d) = op(A) X with op(A) = A^T (trans_a = 1: C is n x d, X is
+ * m x d) or A (trans_a = 0: C is m x d, X is n x d). */
+rqlp_status randqlp_gemm(int trans_a, const void* A, int64_t m, int64_t n, int64_t lda,
+                         const void* X, int64_t d, int64_t ldx, void* C, int64_t ldc,
+                         int precision, void* stream);
+
+/* orth() of Algorithm 1: reduced QR X = Qx R of a rows x d panel with
+ * rows >= d, diag(R) >= 0.  Qx (rows x d, ldq) may not alias X.  R (d x d,
+ * double, ldr) may be NULL.  Synchronous (checks pivots); panel_qr selects
+ * the algorithm as in rqlp_opts. */
+rqlp_status randqlp_orth(const void* X, int64_t rows, int64_t d, int64_t ldx, void* Qx,
+                         int64_t ldq, double* R, int64_t ldr, int precision,
+                         int panel_qr, void* stream);
+
+/* ---- Diagnostics ---- */
+
+/* When on != 0, randqlp_factor records HIP events on its stream around each
+ * launch of the product kernel that streams A (the sketch, power-iteration
+ * and projection products) and accumulates their durations after the call
+ * has synchronised.  Not thread-safe; meant for benchmarks. */
+void randqlp_profile_enable(int on);
+
+/* Totals since the last read: summed kernel time (ms), number of launches,
+ * and the algorithmic flops (2 rows K d) and bytes (A, panel and output
+ * once each) of those launches.  Any pointer may be NULL.  Resets totals. */
+void randqlp_profile_read(double* ms, int64_t* launches, double* flops, double* bytes);
+
+/* Human-readable name of a status, and the calling thread's last error. */
+const char* randqlp_status_string(rqlp_status s);
+const char* randqlp_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RANDQLP_H */

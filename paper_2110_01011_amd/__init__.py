@@ -1,0 +1,250 @@
+"""Randomized QLP decomposition on the AMD Instinct MI355X (gfx950).
+
+Thin binding over librandqlp.so (C ABI in include/randqlp.h).  It only
+marshals arguments: torch provides device memory and the current stream;
+every step of the factorisation runs in the library's HIP kernels.  There is
+no CPU fallback -- importing works without a GPU (for argument checks), but
+any compute call needs the built library and a device.
+
+Matrices are column-major: a tensor of shape (rows, cols) with stride
+(1, ld), ld >= rows.  `colmajor()` makes such a copy of any 2-D tensor.
+"""
+import ctypes
+import os
+
+__all__ = ["factor", "gaussian", "gemm", "orth", "sketch_width", "workspace_size",
+           "colmajor", "empty_colmajor", "lib", "RandQLPError", "F64", "F32",
+           "PANEL_AUTO", "PANEL_CHOLQR2", "PANEL_ROBUST"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librandqlp.so")
+
+F64, F32 = 0, 1
+PANEL_AUTO, PANEL_CHOLQR2, PANEL_ROBUST = 0, 1, 2
+_PANELS = {"auto": PANEL_AUTO, "cholqr2": PANEL_CHOLQR2, "robust": PANEL_ROBUST}
+STATUS = {0: "RQLP_OK", 1: "RQLP_E_INVALID_ARG", 2: "RQLP_E_NONFINITE", 3: "RQLP_E_NOMEM",
+          4: "RQLP_E_WORKSPACE", 5: "RQLP_E_HIP", 6: "RQLP_E_UNSUPPORTED"}
+
+# Every symbol include/randqlp.h declares.
+EXPORTS = ["rqlp_opts_default", "randqlp_sketch_width", "randqlp_workspace_size",
+           "randqlp_factor", "randqlp_gaussian", "randqlp_gemm", "randqlp_orth",
+           "randqlp_profile_enable", "randqlp_profile_read",
+           "randqlp_status_string", "randqlp_last_error"]
+
+
+class RandQLPError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("q_used", ctypes.c_int32),
+                ("breakdowns", ctypes.c_int32), ("robust_rerun", ctypes.c_int32),
+                ("completed", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("panel_qr", ctypes.c_int32),
+                ("lda", ctypes.c_int64), ("ldq", ctypes.c_int64), ("ldl", ctypes.c_int64),
+                ("ldp", ctypes.c_int64), ("stream", ctypes.c_void_p),
+                ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
+                ("info", ctypes.POINTER(Info))]
+
+
+_lib = None
+
+
+def lib():
+    """Load librandqlp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2110_01011_amd.build_lib`")
+    L = ctypes.CDLL(LIB_PATH)
+    i64, i32, u64, vp, sz = ctypes.c_int64, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_size_t
+    L.rqlp_opts_default.argtypes = [ctypes.POINTER(Opts)]
+    L.rqlp_opts_default.restype = None
+    L.randqlp_sketch_width.argtypes = [i64, i64, i32, i32]
+    L.randqlp_sketch_width.restype = i64
+    L.randqlp_workspace_size.argtypes = [i64, i64, i32, i32, i32, ctypes.POINTER(Opts)]
+    L.randqlp_workspace_size.restype = sz
+    L.randqlp_factor.argtypes = [vp, i64, i64, i32, i32, i32, u64, vp, vp, vp, ctypes.POINTER(Opts)]
+    L.randqlp_factor.restype = i32
+    L.randqlp_gaussian.argtypes = [vp, i64, i64, i64, u64, u64, i32, vp]
+    L.randqlp_gaussian.restype = i32
+    L.randqlp_gemm.argtypes = [i32, vp, i64, i64, i64, vp, i64, i64, vp, i64, i32, vp]
+    L.randqlp_gemm.restype = i32
+    L.randqlp_orth.argtypes = [vp, i64, i64, i64, vp, i64, vp, i64, i32, i32, vp]
+    L.randqlp_orth.restype = i32
+    L.randqlp_profile_enable.argtypes = [i32]
+    L.randqlp_profile_enable.restype = None
+    L.randqlp_profile_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.randqlp_profile_read.restype = None
+    L.randqlp_status_string.argtypes = [i32]
+    L.randqlp_status_string.restype = ctypes.c_char_p
+    L.randqlp_last_error.argtypes = []
+    L.randqlp_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != 0:
+        msg = lib().randqlp_last_error().decode(errors="replace")
+        raise RandQLPError(status, msg)
+
+
+def profile_enable(on=True):
+    """Time the A-streaming product kernel with HIP events inside factor()."""
+    lib().randqlp_profile_enable(1 if on else 0)
+
+
+def profile_read():
+    """(total ms, launches, algorithmic flops, algorithmic bytes); resets."""
+    ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    n = ctypes.c_int64()
+    lib().randqlp_profile_read(ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl), ctypes.byref(by))
+    return ms.value, n.value, fl.value, by.value
+
+
+def sketch_width(m, n, k, p):
+    return int(lib().randqlp_sketch_width(m, n, k, p))
+
+
+def default_opts():
+    o = Opts()
+    lib().rqlp_opts_default(ctypes.byref(o))
+    return o
+
+
+def workspace_size(m, n, k, p, q, precision=F64):
+    o = default_opts()
+    o.precision = precision
+    return int(lib().randqlp_workspace_size(m, n, k, p, q, ctypes.byref(o)))
+
+
+# --------------------------------------------------------------- torch glue
+def _torch():
+    import torch
+    return torch
+
+
+def empty_colmajor(rows, cols, dtype, device):
+    torch = _torch()
+    return torch.empty((cols, rows), dtype=dtype, device=device).t()
+
+
+def colmajor(t):
+    """Column-major view or copy of a 2-D tensor (stride (1, ld))."""
+    if t.dim() != 2:
+        raise ValueError("expected a 2-D tensor")
+    if t.stride(0) == 1 and t.stride(1) >= max(1, t.shape[0]):
+        return t
+    return t.t().contiguous().t()
+
+
+def _precision(dtype):
+    torch = _torch()
+    if dtype == torch.float64:
+        return F64
+    if dtype == torch.float32:
+        return F32
+    raise TypeError(f"unsupported dtype {dtype} (float64 or float32)")
+
+
+def _stream_ptr(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ld(t):
+    return max(1, t.stride(1)) if t.shape[1] > 1 else max(1, t.shape[0])
+
+
+def factor(A, k, p, q, seed, panel="auto", return_info=False):
+    """Rand-QLP of a device matrix A (m x n, float64 or float32).
+
+    Returns (Q, L, P): Q (m x d) and P (n x d) in A's dtype, L (d x d)
+    float64, all column-major, with d = min(k + p, m, n).
+    """
+    torch = _torch()
+    if not A.is_cuda:
+        raise ValueError("A must be a device tensor")
+    A = colmajor(A)
+    m, n = A.shape
+    prec = _precision(A.dtype)
+    d = sketch_width(m, n, k, p)
+    if d < 1:
+        _check(lib().randqlp_factor(None, m, n, k, p, q, seed, None, None, None, None))
+    dev = A.device
+    Q = empty_colmajor(m, d, A.dtype, dev)
+    P = empty_colmajor(n, d, A.dtype, dev)
+    L = empty_colmajor(d, d, torch.float64, dev)
+    o = default_opts()
+    o.precision = prec
+    o.panel_qr = _PANELS[panel] if isinstance(panel, str) else int(panel)
+    o.lda, o.ldq, o.ldl, o.ldp = _ld(A), _ld(Q), _ld(L), _ld(P)
+    ws_bytes = lib().randqlp_workspace_size(m, n, k, p, q, ctypes.byref(o))
+    ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+    o.workspace = ctypes.c_void_p(ws.data_ptr())
+    o.workspace_bytes = ws.numel()
+    o.stream = _stream_ptr(dev)
+    info = Info()
+    o.info = ctypes.pointer(info)
+    with torch.cuda.device(dev):
+        _check(lib().randqlp_factor(ctypes.c_void_p(A.data_ptr()), m, n, k, p, q, seed,
+                                    ctypes.c_void_p(Q.data_ptr()), ctypes.c_void_p(L.data_ptr()),
+                                    ctypes.c_void_p(P.data_ptr()), ctypes.byref(o)))
+    del ws
+    if return_info:
+        return Q, L, P, info.as_dict()
+    return Q, L, P
+
+
+def gaussian(m, d, seed, stream_id=0, dtype=None, device="cuda"):
+    """The randn step: Omega (m x d) from (seed, stream_id), column-major."""
+    torch = _torch()
+    dtype = dtype or torch.float64
+    out = empty_colmajor(m, d, dtype, device)
+    _check(lib().randqlp_gaussian(ctypes.c_void_p(out.data_ptr()), m, d, max(1, m), seed,
+                                  stream_id, _precision(dtype), _stream_ptr(out.device)))
+    return out
+
+
+def gemm(A, X, trans_a):
+    """C = A^T X (trans_a) or A X, on the sketch-product kernels."""
+    A = colmajor(A)
+    X = colmajor(X)
+    m, n = A.shape
+    rows = n if trans_a else m
+    if X.shape[0] != (m if trans_a else n) or X.dtype != A.dtype:
+        raise ValueError("shape or dtype mismatch")
+    d = X.shape[1]
+    C = empty_colmajor(rows, d, A.dtype, A.device)
+    _check(lib().randqlp_gemm(1 if trans_a else 0, ctypes.c_void_p(A.data_ptr()), m, n, _ld(A),
+                              ctypes.c_void_p(X.data_ptr()), d, _ld(X),
+                              ctypes.c_void_p(C.data_ptr()), max(1, rows),
+                              _precision(A.dtype), _stream_ptr(A.device)))
+    return C
+
+
+def orth(X, panel="auto"):
+    """Reduced QR X = Qx R (diag R >= 0) of a tall panel; returns (Qx, R)."""
+    torch = _torch()
+    X = colmajor(X)
+    rows, d = X.shape
+    Qx = empty_colmajor(rows, d, X.dtype, X.device)
+    R = empty_colmajor(d, d, torch.float64, X.device)
+    pq = _PANELS[panel] if isinstance(panel, str) else int(panel)
+    _check(lib().randqlp_orth(ctypes.c_void_p(X.data_ptr()), rows, d, _ld(X),
+                              ctypes.c_void_p(Qx.data_ptr()), max(1, rows),
+                              ctypes.c_void_p(R.data_ptr()), max(1, d), _precision(X.dtype), pq,
+                              _stream_ptr(X.device)))
+    return Qx, R

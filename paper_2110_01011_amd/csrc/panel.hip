@@ -1,0 +1,485 @@
+// orth() of Algorithm 1 for tall-skinny panels: Cholesky QR building blocks.
+//
+// For a rows x d panel X with Gram matrix G = X^T X (formed by the GEMM
+// kernels in fp64):
+//   cholesky_kernel  G (+ shift I) = R^T R, R upper with R_jj >= 0, plus the
+//                    inverses of R's 16 x 16 diagonal blocks.  One workgroup
+//                    of 8 waves holds the lower 16 x 16 tiles of G in MFMA
+//                    accumulator registers (d <= 224), factors each diagonal
+//                    tile on one wave, solves the block column with MFMA and
+//                    applies the rank-16 trailing update with MFMA.  A pivot at
+//                    or below tol_dep * (original diagonal) marks its column as
+//                    numerically dependent: that row of R is set to zero.
+//   trsm_kernel      Qx = X R^+ by block forward substitution: each wave owns
+//                    16 rows of X, keeps its finished columns in LDS and uses
+//                    the staged column block of R and the diagonal inverse.
+// plus small kernels: R2 * R1, L = R^T, trace, casts, flag counts, NaN scan.
+#include "rqlp_internal.h"
+
+namespace rqlp {
+namespace {
+
+__device__ __forceinline__ double4_t mma64(double a, double b, double4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+constexpr int kCholWaves = 8;
+constexpr int kCholSlots = 14;  // ceil(105 lower tiles (d <= 224) / 8 waves)
+
+// Factor the 16 x 16 diagonal tile held in dg (row-major) in place into its
+// lower Cholesky factor, and write the (dependent-aware) inverse of that
+// factor into dgi.  Run by one wave; lanes 0..15 each own one row.
+__device__ void factor_diag_tile(double (*dg)[17], double (*dgi)[17], const double* odiag,
+                                 int J, int d, double tol_dep, double tol_warn,
+                                 int* __restrict__ col_flags, double* __restrict__ dinv,
+                                 int* sflag) {
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15;
+  int bits = 0;
+  {
+    double a[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) a[c] = dg[i][c];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const double piv = readlane_d(a[s], s);
+      const int gj = 16 * J + s;
+      const double orig = odiag[gj];
+      const bool nonfinite = !__builtin_isfinite(piv);
+      const bool dep = nonfinite || !(piv > tol_dep * orig);
+      if (gj < d) {
+        if (nonfinite) bits |= FLAG_NONFINITE;
+        if (dep) bits |= FLAG_NONPOS_PIVOT;
+        if (!dep && piv < tol_warn * orig) bits |= FLAG_SECOND_PASS;
+        if (col_flags != nullptr && lane == 0) col_flags[gj] = dep ? 1 : 0;
+      }
+      const double lss = dep ? 0.0 : sqrt(piv);
+      const double inv = dep ? 0.0 : 1.0 / lss;
+      const double lis = (i > s) ? a[s] * inv : ((i == s) ? lss : 0.0);
+      a[s] = lis;
+#pragma unroll
+      for (int j = s + 1; j < 16; ++j) {
+        const double ljs = readlane_d(lis, j);
+        a[j] -= lis * ljs;
+      }
+    }
+    wave_sync_lds();
+    if (lane < 16) {
+#pragma unroll
+      for (int c = 0; c < 16; ++c) dg[i][c] = (c > i) ? 0.0 : a[c];
+    }
+    wave_sync_lds();
+  }
+  // Inverse of the lower factor by forward substitution, one column per
+  // lane: X[i][c] = (delta_ic - sum_{t<i} L[i][t] X[t][c]) / L[i][i]; a zero
+  // pivot gives a zero row (the dependent-column rule).
+  const int c = lane & 15;
+  double x[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    double v = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int t = 0; t < r; ++t) v -= dg[r][t] * x[t];
+    const double lrr = dg[r][r];
+    x[r] = (lrr != 0.0) ? v / lrr : 0.0;
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      dgi[r][c] = x[r];
+      // R_JJ^{-1} = (L_JJ^{-1})^T, column-major block: element (c, r) at c + 16 r.
+      dinv[(int64_t)J * 256 + c + r * 16] = x[r];
+    }
+  }
+  if (lane == 0 && bits) *sflag |= bits;
+}
+
+__global__ __launch_bounds__(512) void cholesky_kernel(
+    const double* __restrict__ G, int d, int64_t ldg, double shift,
+    const double* __restrict__ shift_dev, double tol_dep, double tol_warn,
+    double* __restrict__ R, double* __restrict__ dinv, int* __restrict__ col_flags,
+    int* __restrict__ flags) {
+  __shared__ double dg[16][17];
+  __shared__ double dgi[16][17];
+  __shared__ double pan[CHOL_MAX_D][17];
+  __shared__ double odiag[CHOL_MAX_D];
+  __shared__ int sflag;
+
+  const int nt = (d + 15) / 16;
+  const int T = nt * (nt + 1) / 2;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const double sh = (shift_dev != nullptr) ? *shift_dev : shift;
+
+  double4_t acc[kCholSlots];
+  int tI[kCholSlots], tJ[kCholSlots];
+#pragma unroll
+  for (int s = 0; s < kCholSlots; ++s) {
+    const int t = wave + kCholWaves * s;
+    tI[s] = -1;
+    tJ[s] = -1;
+    acc[s] = double4_t{0, 0, 0, 0};
+    if (t < T) {
+      int I = 0;
+      while ((I + 1) * (I + 2) / 2 <= t) ++I;
+      const int Jt = t - I * (I + 1) / 2;
+      tI[s] = I;
+      tJ[s] = Jt;
+      const int col = 16 * Jt + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * I + acc_row_f64(lane, r);
+        double v;
+        if (row < d && col < d) {
+          v = G[row + (int64_t)col * ldg];
+          if (row == col) v += sh;
+        } else {
+          v = (row == col) ? 1.0 : 0.0;
+        }
+        acc[s][r] = v;
+      }
+    }
+  }
+  for (int j = tid; j < CHOL_MAX_D; j += blockDim.x)
+    odiag[j] = (j < d) ? G[j + (int64_t)j * ldg] + sh : 1.0;
+  if (tid == 0) sflag = 0;
+  __syncthreads();
+
+  for (int J = 0; J < nt; ++J) {
+    const int td = J * (J + 1) / 2 + J;
+    if (wave == td % kCholWaves) {
+#pragma unroll
+      for (int s = 0; s < kCholSlots; ++s)
+        if (s == td / kCholWaves) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) dg[acc_row_f64(lane, r)][lane & 15] = acc[s][r];
+        }
+    }
+    __syncthreads();
+    if (wave == 0) factor_diag_tile(dg, dgi, odiag, J, d, tol_dep, tol_warn, col_flags, dinv, &sflag);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kCholSlots; ++s) {
+      if (tJ[s] != J) continue;
+      const int I = tI[s];
+      if (I == J) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[s][r] = dg[acc_row_f64(lane, r)][lane & 15];
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pan[16 * I + acc_row_f64(lane, r)][lane & 15] = acc[s][r];
+        wave_sync_lds();
+        double4_t res = {0, 0, 0, 0};
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+          const double a = pan[16 * I + (lane & 15)][kq * 4 + (lane >> 4)];
+          const double b = dgi[lane & 15][kq * 4 + (lane >> 4)];
+          res = mma64(a, b, res);
+        }
+        acc[s] = res;
+        wave_sync_lds();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pan[16 * I + acc_row_f64(lane, r)][lane & 15] = res[r];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < kCholSlots; ++s) {
+      const int I = tI[s], K = tJ[s];
+      if (K <= J) continue;
+      double4_t c = acc[s];
+#pragma unroll
+      for (int kq = 0; kq < 4; ++kq) {
+        const double a = pan[16 * I + (lane & 15)][kq * 4 + (lane >> 4)];
+        const double b = pan[16 * K + (lane & 15)][kq * 4 + (lane >> 4)];
+        c = mma64(-a, b, c);
+      }
+      acc[s] = c;
+    }
+  }
+  // R = L^T (upper), with explicit zeros in the lower triangle.
+#pragma unroll
+  for (int s = 0; s < kCholSlots; ++s) {
+    if (tI[s] < 0) continue;
+    const int I = tI[s], Jt = tJ[s];
+    const int col = 16 * Jt + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * I + acc_row_f64(lane, r);
+      if (row < d && col < d) {
+        R[col + (int64_t)row * d] = acc[s][r];
+        if (I > Jt) R[row + (int64_t)col * d] = 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && sflag) atomicOr(flags, sflag);
+}
+
+// Qx = X R^+ by block forward substitution; each wave owns 16 rows.
+template <typename TX, typename TO, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void trsm_kernel(
+    const TX* __restrict__ X, int64_t rows, int d, int64_t ldx, const double* __restrict__ R,
+    const double* __restrict__ dinv, TO* __restrict__ Qx, int64_t ldq) {
+  extern __shared__ double smem[];
+  const int nt = (d + 15) / 16, dp = nt * 16, lq = dp + 1;
+  double* Qs = smem;
+  double* Rb = Qs + WAVES * 16 * lq;
+  double* Tb = Rb + dp * 17;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t r0 = ((int64_t)blockIdx.x * WAVES + wave) * 16;
+  double* Qw = Qs + wave * 16 * lq;
+
+  for (int J = 0; J < nt; ++J) {
+    __syncthreads();
+    const int kk = 16 * J;
+    for (int idx = tid; idx < kk * 16; idx += 64 * WAVES) {
+      const int t = idx % kk, c = idx / kk;
+      const int gc = kk + c;
+      Rb[t * 17 + c] = (gc < d) ? R[t + (int64_t)gc * d] : 0.0;
+    }
+    for (int idx = tid; idx < 256; idx += 64 * WAVES) {
+      const int r = idx & 15, c = idx >> 4;
+      Tb[r * 17 + c] = dinv[(int64_t)J * 256 + r + c * 16];
+    }
+    // stage this wave's 16 x 16 block of X (coalesced down the columns)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = lane + 64 * e;
+      const int rr = idx & 15, cc = idx >> 4;
+      const int64_t row = r0 + rr;
+      const int col = kk + cc;
+      Qw[rr * lq + col] = (row < rows && col < d) ? (double)X[row + (int64_t)col * ldx] : 0.0;
+    }
+    __syncthreads();
+    double4_t acc;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) acc[r] = Qw[(acc_row_f64(lane, r)) * lq + kk + (lane & 15)];
+    for (int kq = 0; kq < 4 * J; ++kq) {
+      const double a = Qw[(lane & 15) * lq + kq * 4 + (lane >> 4)];
+      const double b = Rb[(kq * 4 + (lane >> 4)) * 17 + (lane & 15)];
+      acc = mma64(-a, b, acc);
+    }
+    wave_sync_lds();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Qw[(acc_row_f64(lane, r)) * lq + kk + (lane & 15)] = acc[r];
+    wave_sync_lds();
+    double4_t res = {0, 0, 0, 0};
+#pragma unroll
+    for (int kq = 0; kq < 4; ++kq) {
+      const double a = Qw[(lane & 15) * lq + kk + kq * 4 + (lane >> 4)];
+      const double b = Tb[(kq * 4 + (lane >> 4)) * 17 + (lane & 15)];
+      res = mma64(a, b, res);
+    }
+    wave_sync_lds();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Qw[(acc_row_f64(lane, r)) * lq + kk + (lane & 15)] = res[r];
+    wave_sync_lds();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = lane + 64 * e;
+      const int rr = idx & 15, cc = idx >> 4;
+      const int64_t row = r0 + rr;
+      const int col = kk + cc;
+      if (row < rows && col < d) Qx[row + (int64_t)col * ldq] = (TO)Qw[rr * lq + col];
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void trmm_upper_kernel(const double* __restrict__ R2,
+                                                         const double* __restrict__ R1,
+                                                         double* __restrict__ Ro, int d) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)d * d) return;
+  const int i = (int)(idx % d), j = (int)(idx / d);
+  double s = 0.0;
+  for (int t = i; t <= j; ++t) s += R2[i + (int64_t)t * d] * R1[t + (int64_t)j * d];
+  Ro[i + (int64_t)j * d] = s;
+}
+
+__global__ __launch_bounds__(256) void lower_from_upper_kernel(const double* __restrict__ R,
+                                                               int d, double* __restrict__ L,
+                                                               int64_t ldl) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)d * d) return;
+  const int i = (int)(idx % d), j = (int)(idx / d);
+  L[i + j * ldl] = (i >= j) ? R[j + (int64_t)i * d] : 0.0;
+}
+
+__global__ __launch_bounds__(256) void trace_kernel(const double* __restrict__ G, int d,
+                                                    int64_t ldg, double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int j = threadIdx.x; j < d; j += 256) s += G[j + (int64_t)j * ldg];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+__global__ void scale_scalar_kernel(const double* in, double c, double* out) {
+  // shift = c * trace, or 1 for an all-zero panel (then every column is dependent)
+  const double v = c * in[0];
+  out[0] = (v > 0.0) ? v : 1.0;
+}
+
+template <typename TS, typename TD>
+__global__ __launch_bounds__(256) void copy_panel_kernel(const TS* __restrict__ s, int64_t lds,
+                                                         TD* __restrict__ t, int64_t ldt,
+                                                         int64_t rows, int64_t d) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * d) return;
+  const int64_t i = idx % rows, j = idx / rows;
+  t[i + j * ldt] = (TD)s[i + j * lds];
+}
+
+__global__ __launch_bounds__(256) void count_flags_kernel(const int* __restrict__ f, int d,
+                                                          int* __restrict__ count) {
+  __shared__ int c;
+  if (threadIdx.x == 0) c = 0;
+  __syncthreads();
+  int mine = 0;
+  for (int j = threadIdx.x; j < d; j += 256) mine += f[j] ? 1 : 0;
+  if (mine) atomicAdd(&c, mine);
+  __syncthreads();
+  if (threadIdx.x == 0) count[0] += c;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void check_finite_kernel(const T* __restrict__ A, int64_t m,
+                                                           int64_t n, int64_t lda,
+                                                           int* __restrict__ flags) {
+  const int64_t total = m * n;
+  bool bad = false;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx % m, j = idx / m;
+    if (!__builtin_isfinite((double)A[i + j * lda])) bad = true;
+  }
+  if (bad) atomicOr(flags, FLAG_NONFINITE);
+}
+
+inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_cholesky(const double* G, int64_t d, int64_t ldg, double shift,
+                           const double* shift_dev, double tol_dep, double tol_warn,
+                           double* R, double* dinv, int* col_flags, int* flags,
+                           hipStream_t st) {
+  if (d > CHOL_MAX_D) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(512), 0, st, G, (int)d, ldg, shift,
+                     shift_dev, tol_dep, tol_warn, R, dinv, col_flags, flags);
+  return hipGetLastError();
+}
+
+template <typename TX, typename TO, int WAVES>
+static hipError_t trsm_typed(const void* X, int64_t rows, int64_t d, int64_t ldx,
+                             const double* R, const double* dinv, void* Qx, int64_t ldq,
+                             hipStream_t st) {
+  const int nt = (int)((d + 15) / 16), dp = nt * 16;
+  const size_t lds = sizeof(double) * ((size_t)WAVES * 16 * (dp + 1) + (size_t)dp * 17 + 16 * 17);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)trsm_kernel<TX, TO, WAVES>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    attr_set = true;
+  }
+  const int64_t blocks = (rows + 16 * WAVES - 1) / (16 * WAVES);
+  hipLaunchKernelGGL((trsm_kernel<TX, TO, WAVES>), dim3((unsigned)blocks), dim3(64 * WAVES),
+                     lds, st, (const TX*)X, rows, (int)d, ldx, R, dinv, (TO*)Qx, ldq);
+  return hipGetLastError();
+}
+
+hipError_t launch_trsm(const void* X, int64_t rows, int64_t d, int64_t ldx, const double* R,
+                       const double* dinv, void* Qx, int64_t ldq, Dtype dt, hipStream_t st) {
+  if (d > CHOL_MAX_D) return hipErrorInvalidValue;
+  if (rows <= 0 || d <= 0) return hipSuccess;
+  const int dp = (int)((d + 15) / 16) * 16;
+  const size_t lds4 = sizeof(double) * ((size_t)4 * 16 * (dp + 1) + (size_t)dp * 17 + 16 * 17);
+  const bool four = lds4 <= 160 * 1024;
+  if (dt == DT_F64)
+    return four ? trsm_typed<double, double, 4>(X, rows, d, ldx, R, dinv, Qx, ldq, st)
+                : trsm_typed<double, double, 2>(X, rows, d, ldx, R, dinv, Qx, ldq, st);
+  return four ? trsm_typed<float, float, 4>(X, rows, d, ldx, R, dinv, Qx, ldq, st)
+              : trsm_typed<float, float, 2>(X, rows, d, ldx, R, dinv, Qx, ldq, st);
+}
+
+hipError_t launch_trmm_upper(const double* R2, const double* R1, double* Rout, int64_t d,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(trmm_upper_kernel, dim3(grid_for(d * d)), dim3(256), 0, st, R2, R1, Rout,
+                     (int)d);
+  return hipGetLastError();
+}
+
+hipError_t launch_lower_from_upper(const double* R, int64_t d, double* L, int64_t ldl,
+                                   hipStream_t st) {
+  hipLaunchKernelGGL(lower_from_upper_kernel, dim3(grid_for(d * d)), dim3(256), 0, st, R,
+                     (int)d, L, ldl);
+  return hipGetLastError();
+}
+
+hipError_t launch_trace(const double* G, int64_t d, int64_t ldg, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(256), 0, st, G, (int)d, ldg, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_scalar(const double* in, double c, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(scale_scalar_kernel, dim3(1), dim3(1), 0, st, in, c, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_panel(const void* src, Dtype s_t, int64_t ld_src, void* dst, Dtype d_t,
+                             int64_t ld_dst, int64_t rows, int64_t d, hipStream_t st) {
+  const unsigned g = grid_for(rows * d);
+  if (rows * d <= 0) return hipSuccess;
+  if (s_t == DT_F32 && d_t == DT_F64)
+    hipLaunchKernelGGL((copy_panel_kernel<float, double>), dim3(g), dim3(256), 0, st,
+                       (const float*)src, ld_src, (double*)dst, ld_dst, rows, d);
+  else if (s_t == DT_F64 && d_t == DT_F32)
+    hipLaunchKernelGGL((copy_panel_kernel<double, float>), dim3(g), dim3(256), 0, st,
+                       (const double*)src, ld_src, (float*)dst, ld_dst, rows, d);
+  else if (s_t == DT_F64)
+    hipLaunchKernelGGL((copy_panel_kernel<double, double>), dim3(g), dim3(256), 0, st,
+                       (const double*)src, ld_src, (double*)dst, ld_dst, rows, d);
+  else
+    hipLaunchKernelGGL((copy_panel_kernel<float, float>), dim3(g), dim3(256), 0, st,
+                       (const float*)src, ld_src, (float*)dst, ld_dst, rows, d);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_flags(const int* col_flags, int64_t d, int* count, hipStream_t st) {
+  hipLaunchKernelGGL(count_flags_kernel, dim3(1), dim3(256), 0, st, col_flags, (int)d, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const void* A, int64_t m, int64_t n, int64_t lda, Dtype dt,
+                               int* flags, hipStream_t st) {
+  const int64_t total = m * n;
+  if (total <= 0) return hipSuccess;
+  const unsigned g = (unsigned)std::min<int64_t>(4096, (total + 255) / 256);
+  if (dt == DT_F64)
+    hipLaunchKernelGGL(check_finite_kernel<double>, dim3(g), dim3(256), 0, st,
+                       (const double*)A, m, n, lda, flags);
+  else
+    hipLaunchKernelGGL(check_finite_kernel<float>, dim3(g), dim3(256), 0, st, (const float*)A,
+                       m, n, lda, flags);
+  return hipGetLastError();
+}
+
+}  // namespace rqlp

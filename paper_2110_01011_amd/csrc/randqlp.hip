@@ -1,0 +1,562 @@
+// Host orchestration and C ABI of librandqlp (declared in include/randqlp.h).
+//
+// randqlp_factor runs the generalised Algorithm 1 (Section 3.1) as a
+// stream-ordered sequence of the kernels in philox.hip, gemm.hip and
+// panel.hip:
+//   Omega -> Y = A^T Omega -> Qbar = orth(Y)
+//   q x [ Z = A Qbar -> Q = orth(Z) -> Y = A^T Q -> Qbar = orth(Y) ]
+//   Z = A Qbar -> Q = orth(Z) -> W = A^T Q -> (P, R) = orth(W) -> L = R^T
+// orth() is Cholesky QR run twice (fast path) or the robust sequence
+// (shifted pass, completion of dependent columns, two more passes).  Device
+// kernels raise bits in a status word; the call reads it back once at the
+// end and, in AUTO mode, recomputes everything with the robust orth() if a
+// pass reported an unsafe pivot.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/randqlp.h"
+#include "rqlp_internal.h"
+
+using namespace rqlp;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+rqlp_status fail(rqlp_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                   \
+  do {                                  \
+    hipError_t e_ = (expr);             \
+    if (e_ != hipSuccess) return e_;    \
+  } while (0)
+
+constexpr double kUnit = 1.1102230246251565e-16;  // 2^-53
+// Fast path: a first-pass pivot below this fraction of its column's squared
+// norm is at rounding level -> treat as breakdown.
+constexpr double kTolDepFast = 64.0 * kUnit;
+// Second pass: Q1^T Q1 should be near I; a pivot below this fraction means
+// the first pass lost too much orthogonality for two passes to be enough.
+constexpr double kTolWarnSecond = 0.05;
+// Robust path: after the shifted pass, a pivot below this fraction of the
+// column norm is numerically dependent and the column is completed.
+constexpr double kTolDepRobust = 1e-12;
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  size_t m1, m2, n1, n2, part, part_bytes, G, R[4], Racc[2], Rfin, dinv, colf, scal, flags,
+      total;
+};
+
+size_t elem_size(Dtype dt) { return dt == DT_F64 ? 8 : 4; }
+
+Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt) {
+  Layout L;
+  const size_t es = elem_size(dt);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  L.m1 = take((size_t)m * d * es);
+  L.m2 = take((size_t)m * d * es);
+  L.n1 = take((size_t)n * d * es);
+  L.n2 = take((size_t)n * d * es);
+  size_t part = 0;
+  part = std::max(part, gemm_partial_bytes(1, n, d, m, dt, dt, false));
+  part = std::max(part, gemm_partial_bytes(0, m, d, n, dt, dt, false));
+  part = std::max(part, gemm_partial_bytes(1, d, d, m, dt, DT_F64, true));
+  part = std::max(part, gemm_partial_bytes(1, d, d, n, dt, DT_F64, true));
+  L.part = take(part);
+  L.part_bytes = part;
+  L.G = take((size_t)d * d * 8);
+  for (int i = 0; i < 4; ++i) L.R[i] = take((size_t)d * d * 8);
+  for (int i = 0; i < 2; ++i) L.Racc[i] = take((size_t)d * d * 8);
+  L.Rfin = take((size_t)d * d * 8);
+  L.dinv = take((size_t)((d + 15) / 16) * 256 * 8);
+  L.colf = take((size_t)d * 4);
+  L.scal = take(64);
+  L.flags = take(64);
+  L.total = off;
+  return L;
+}
+
+// Library-managed workspace: one growing buffer per device.
+struct WsCache {
+  std::mutex mu;
+  void* ptr[64] = {};
+  size_t size[64] = {};
+};
+WsCache g_ws;
+
+struct Ctx {
+  hipStream_t st;
+  Dtype dt;
+  char* ws;
+  Layout lay;
+  int64_t d;
+  uint64_t seed;
+  int orth_calls;
+  template <typename T>
+  T* at(size_t off) const {
+    return (T*)(ws + off);
+  }
+  int* flags() const { return at<int>(lay.flags); }
+};
+
+// Optional kernel timing of the products with A (the dominant kernel): HIP
+// events recorded on the call's stream around each launch, read after the
+// call has synchronised.  Diagnostics only; not thread-safe.
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<double> work_flops, work_bytes;
+  size_t used = 0;
+  double ms = 0.0, flops = 0.0, bytes = 0.0;
+  long long launches = 0;
+};
+Prof g_prof;
+
+void prof_collect() {
+  for (size_t i = 0; i < g_prof.used; ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, g_prof.ev[2 * i], g_prof.ev[2 * i + 1]) == hipSuccess) {
+      g_prof.ms += t;
+      g_prof.flops += g_prof.work_flops[i];
+      g_prof.bytes += g_prof.work_bytes[i];
+      g_prof.launches += 1;
+    }
+  }
+  g_prof.used = 0;
+}
+
+hipError_t gemm(Ctx& c, int trans_a, const void* A, int64_t lda, const void* B, int64_t ldb,
+                void* C, int64_t ldc, int64_t M, int64_t N, int64_t K, Dtype in_t, Dtype out_t,
+                bool gram, bool timed = false) {
+  GemmArgs g;
+  g.trans_a = trans_a;
+  g.A = A;
+  g.lda = lda;
+  g.B = B;
+  g.ldb = ldb;
+  g.C = C;
+  g.ldc = ldc;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.in_t = in_t;
+  g.out_t = out_t;
+  g.gram = gram;
+  g.partial = c.ws + c.lay.part;
+  g.partial_bytes = c.lay.part_bytes;
+  if (timed && g_prof.on) {
+    const size_t i = g_prof.used++;
+    while (g_prof.ev.size() < 2 * g_prof.used) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
+      g_prof.ev.push_back(e);
+    }
+    g_prof.work_flops.resize(g_prof.used);
+    g_prof.work_bytes.resize(g_prof.used);
+    const double es = (in_t == DT_F64) ? 8.0 : 4.0;
+    g_prof.work_flops[i] = 2.0 * (double)M * (double)N * (double)K;
+    g_prof.work_bytes[i] = es * ((double)M * K + (double)K * N + (double)M * N);
+    g.ev_begin = g_prof.ev[2 * i];
+    g.ev_end = g_prof.ev[2 * i + 1];
+  }
+  return launch_gemm(g, c.st);
+}
+
+// One Cholesky QR pass: X (rows x d) -> Qx = X R^+, R into Rbuf.
+hipError_t chol_pass(Ctx& c, const void* X, int64_t rows, int64_t ldx, void* Qx, int64_t ldq,
+                     double* Rbuf, const double* shift_dev, double tol_dep, double tol_warn,
+                     int* col_flags) {
+  const int64_t d = c.d;
+  double* G = c.at<double>(c.lay.G);
+  double* dinv = c.at<double>(c.lay.dinv);
+  HIP_TRY(gemm(c, 1, X, ldx, X, ldx, G, d, d, d, rows, c.dt, DT_F64, true));
+  HIP_TRY(launch_cholesky(G, d, d, 0.0, shift_dev, tol_dep, tol_warn, Rbuf, dinv, col_flags,
+                          c.flags(), c.st));
+  return launch_trsm(X, rows, d, ldx, Rbuf, dinv, Qx, ldq, c.dt, c.st);
+}
+
+// orth(): X (rows x d, ldx) -> out (rows x d, ldo), using tmp (rows x d,
+// ld = rows).  out may alias X; tmp may not alias either.  If Rout is given
+// it receives R with X = out * R.
+hipError_t orth(Ctx& c, const void* X, int64_t rows, int64_t ldx, void* out, int64_t ldo,
+                void* tmp, double* Rout, bool robust) {
+  const int64_t d = c.d;
+  double* R[4] = {c.at<double>(c.lay.R[0]), c.at<double>(c.lay.R[1]),
+                  c.at<double>(c.lay.R[2]), c.at<double>(c.lay.R[3])};
+  const int call = c.orth_calls++;
+  if (!robust) {
+    HIP_TRY(chol_pass(c, X, rows, ldx, tmp, rows, R[0], nullptr, kTolDepFast, 0.0, nullptr));
+    HIP_TRY(chol_pass(c, tmp, rows, rows, out, ldo, R[1], nullptr, kTolDepFast, kTolWarnSecond,
+                      nullptr));
+    if (Rout) HIP_TRY(launch_trmm_upper(R[1], R[0], Rout, d, c.st));
+    return hipSuccess;
+  }
+  double* G = c.at<double>(c.lay.G);
+  double* scal = c.at<double>(c.lay.scal);
+  int* colf = c.at<int>(c.lay.colf);
+  // pass 1: shifted Cholesky QR, shift = 11 (rows d + d (d + 1)) u ||X||_F^2
+  HIP_TRY(gemm(c, 1, X, ldx, X, ldx, G, d, d, d, rows, c.dt, DT_F64, true));
+  HIP_TRY(launch_trace(G, d, d, scal, c.st));
+  const double cshift = 11.0 * ((double)rows * d + (double)d * (d + 1)) * kUnit;
+  HIP_TRY(launch_scale_scalar(scal, cshift, scal + 1, c.st));
+  double* dinv = c.at<double>(c.lay.dinv);
+  HIP_TRY(launch_cholesky(G, d, d, 0.0, scal + 1, 0.0, 0.0, R[0], dinv, nullptr, c.flags(),
+                          c.st));
+  HIP_TRY(launch_trsm(X, rows, d, ldx, R[0], dinv, tmp, rows, c.dt, c.st));
+  // pass 2: detect dependent columns (zeroed), then complete them
+  HIP_TRY(chol_pass(c, tmp, rows, rows, out, ldo, R[1], nullptr, kTolDepRobust, 0.0, colf));
+  HIP_TRY(launch_count_flags(colf, d, c.flags() + 2, c.st));
+  HIP_TRY(launch_gaussian_columns(out, rows, ldo, colf, d, c.seed, 0x1000ull + (uint64_t)call,
+                                  c.dt, c.st));
+  // passes 3 and 4: Cholesky QR twice on the completed panel
+  HIP_TRY(chol_pass(c, out, rows, ldo, tmp, rows, R[2], nullptr, 0.0, 0.0, nullptr));
+  HIP_TRY(chol_pass(c, tmp, rows, rows, out, ldo, R[3], nullptr, 0.0, 0.0, nullptr));
+  if (Rout) {
+    double* A0 = c.at<double>(c.lay.Racc[0]);
+    double* A1 = c.at<double>(c.lay.Racc[1]);
+    HIP_TRY(launch_trmm_upper(R[1], R[0], A0, d, c.st));
+    HIP_TRY(launch_trmm_upper(R[2], A0, A1, d, c.st));
+    HIP_TRY(launch_trmm_upper(R[3], A1, Rout, d, c.st));
+  }
+  return hipSuccess;
+}
+
+struct FactorArgs {
+  const void* A;
+  int64_t m, n, lda;
+  int q;
+  void* Q;
+  int64_t ldq;
+  double* L;
+  int64_t ldl;
+  void* P;
+  int64_t ldp;
+};
+
+hipError_t run_pipeline(Ctx& c, const FactorArgs& f, bool robust) {
+  const int64_t m = f.m, n = f.n, d = c.d;
+  void* Zm = c.ws + c.lay.m1;
+  void* Tm = c.ws + c.lay.m2;
+  void* Yn = c.ws + c.lay.n1;
+  void* Tn = c.ws + c.lay.n2;
+  double* Rfin = c.at<double>(c.lay.Rfin);
+  c.orth_calls = 0;
+  HIP_TRY(hipMemsetAsync(c.flags(), 0, 64, c.st));
+  HIP_TRY(launch_gaussian(Zm, m, d, m, c.seed, 0, c.dt, c.st));                // randn
+  HIP_TRY(gemm(c, 1, f.A, f.lda, Zm, m, Yn, n, n, d, m, c.dt, c.dt, false, true));  // A^T Omega
+  HIP_TRY(orth(c, Yn, n, n, Yn, n, Tn, nullptr, robust));                       // Qbar
+  for (int it = 0; it < f.q; ++it) {
+    HIP_TRY(gemm(c, 0, f.A, f.lda, Yn, n, Zm, m, m, d, n, c.dt, c.dt, false, true));  // A Qbar
+    HIP_TRY(orth(c, Zm, m, m, Zm, m, Tm, nullptr, robust));
+    HIP_TRY(gemm(c, 1, f.A, f.lda, Zm, m, Yn, n, n, d, m, c.dt, c.dt, false, true));  // A^T Q
+    HIP_TRY(orth(c, Yn, n, n, Yn, n, Tn, nullptr, robust));
+  }
+  HIP_TRY(gemm(c, 0, f.A, f.lda, Yn, n, Zm, m, m, d, n, c.dt, c.dt, false, true));  // A Qbar
+  HIP_TRY(orth(c, Zm, m, m, f.Q, f.ldq, Tm, nullptr, robust));                  // Q
+  HIP_TRY(gemm(c, 1, f.A, f.lda, f.Q, f.ldq, Yn, n, n, d, m, c.dt, c.dt, false, true));  // A^T Q
+  HIP_TRY(orth(c, Yn, n, n, f.P, f.ldp, Tn, Rfin, robust));                      // P, R
+  HIP_TRY(launch_lower_from_upper(Rfin, d, f.L, f.ldl, c.st));                   // L = R^T
+  return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+void rqlp_opts_default(rqlp_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->precision = RQLP_F64;
+  o->panel_qr = RQLP_PANEL_AUTO;
+}
+
+int64_t randqlp_sketch_width(int64_t m, int64_t n, int k, int p) {
+  if (m < 1 || n < 1 || k < 1 || p < 0) return -1;
+  int64_t d = (int64_t)k + p;
+  if (d > m) d = m;
+  if (d > n) d = n;
+  return d;
+}
+
+const char* randqlp_status_string(rqlp_status s) {
+  switch (s) {
+    case RQLP_OK: return "RQLP_OK";
+    case RQLP_E_INVALID_ARG: return "RQLP_E_INVALID_ARG";
+    case RQLP_E_NONFINITE: return "RQLP_E_NONFINITE";
+    case RQLP_E_NOMEM: return "RQLP_E_NOMEM";
+    case RQLP_E_WORKSPACE: return "RQLP_E_WORKSPACE";
+    case RQLP_E_HIP: return "RQLP_E_HIP";
+    case RQLP_E_UNSUPPORTED: return "RQLP_E_UNSUPPORTED";
+  }
+  return "RQLP_E_UNKNOWN";
+}
+
+const char* randqlp_last_error(void) { return g_last_error.c_str(); }
+
+void randqlp_profile_enable(int on) {
+  g_prof.on = (on != 0);
+  g_prof.used = 0;
+}
+
+void randqlp_profile_read(double* ms, int64_t* launches, double* flops, double* bytes) {
+  if (ms) *ms = g_prof.ms;
+  if (launches) *launches = g_prof.launches;
+  if (flops) *flops = g_prof.flops;
+  if (bytes) *bytes = g_prof.bytes;
+  g_prof.ms = g_prof.flops = g_prof.bytes = 0.0;
+  g_prof.launches = 0;
+}
+
+size_t randqlp_workspace_size(int64_t m, int64_t n, int k, int p, int q, const rqlp_opts* o) {
+  const int64_t d = randqlp_sketch_width(m, n, k, p);
+  if (d < 1 || q < 0) return 0;
+  const int prec = o ? o->precision : RQLP_F64;
+  if (prec != RQLP_F64 && prec != RQLP_F32) return 0;
+  return make_layout(m, n, d, prec == RQLP_F64 ? DT_F64 : DT_F32).total;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Acquire `bytes` of device scratch: the caller's buffer or the per-device
+// cache (grown under the lock; the lock is held for the whole call).
+rqlp_status acquire_ws(const rqlp_opts& o, size_t bytes, char** out,
+                       std::unique_lock<std::mutex>& lk) {
+  if (o.workspace != nullptr) {
+    if (o.workspace_bytes < bytes)
+      return fail(RQLP_E_WORKSPACE, "workspace has %zu bytes, %zu needed", o.workspace_bytes,
+                  bytes);
+    *out = (char*)o.workspace;
+    return RQLP_OK;
+  }
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+    return fail(RQLP_E_HIP, "hipGetDevice failed");
+  lk = std::unique_lock<std::mutex>(g_ws.mu);
+  if (g_ws.size[dev] < bytes) {
+    if (g_ws.ptr[dev]) {
+      (void)hipDeviceSynchronize();
+      (void)hipFree(g_ws.ptr[dev]);
+      g_ws.ptr[dev] = nullptr;
+      g_ws.size[dev] = 0;
+    }
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return fail(RQLP_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
+    }
+    g_ws.ptr[dev] = p;
+    g_ws.size[dev] = bytes;
+  }
+  *out = (char*)g_ws.ptr[dev];
+  return RQLP_OK;
+}
+
+rqlp_status read_flags(Ctx& c, int host[4]) {
+  hipError_t e = hipMemcpyAsync(host, c.flags(), 4 * sizeof(int), hipMemcpyDeviceToHost, c.st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.st);
+  if (e != hipSuccess) return fail(RQLP_E_HIP, "status read-back: %s", hipGetErrorString(e));
+  if (g_prof.on) prof_collect();
+  return RQLP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rqlp_status randqlp_factor(const void* A, int64_t m, int64_t n, int k, int p, int q,
+                           uint64_t seed, void* Q, void* L, void* P, const rqlp_opts* opts) {
+  rqlp_opts o;
+  if (opts)
+    o = *opts;
+  else
+    rqlp_opts_default(&o);
+  if (m < 1 || n < 1) return fail(RQLP_E_INVALID_ARG, "m = %lld, n = %lld must be >= 1", (long long)m, (long long)n);
+  if (k < 1) return fail(RQLP_E_INVALID_ARG, "k = %d must be >= 1", k);
+  if (p < 0) return fail(RQLP_E_INVALID_ARG, "p = %d must be >= 0", p);
+  if (q < 0) return fail(RQLP_E_INVALID_ARG, "q = %d must be >= 0", q);
+  if (!A || !Q || !L || !P) return fail(RQLP_E_INVALID_ARG, "null matrix pointer");
+  if (o.precision != RQLP_F64 && o.precision != RQLP_F32)
+    return fail(RQLP_E_INVALID_ARG, "unknown precision %d", o.precision);
+  if (o.panel_qr < RQLP_PANEL_AUTO || o.panel_qr > RQLP_PANEL_ROBUST)
+    return fail(RQLP_E_INVALID_ARG, "unknown panel_qr %d", o.panel_qr);
+  const int64_t d = randqlp_sketch_width(m, n, k, p);
+  const int64_t lda = o.lda ? o.lda : m, ldq = o.ldq ? o.ldq : m;
+  const int64_t ldl = o.ldl ? o.ldl : d, ldp = o.ldp ? o.ldp : n;
+  if (lda < m || ldq < m || ldl < d || ldp < n)
+    return fail(RQLP_E_INVALID_ARG, "leading dimension smaller than the row count");
+  if (d > CHOL_MAX_D)
+    return fail(RQLP_E_UNSUPPORTED, "sketch width d = %lld exceeds %d", (long long)d, CHOL_MAX_D);
+  const Dtype dt = (o.precision == RQLP_F64) ? DT_F64 : DT_F32;
+
+  Ctx c;
+  c.st = (hipStream_t)o.stream;
+  c.dt = dt;
+  c.lay = make_layout(m, n, d, dt);
+  c.d = d;
+  c.seed = seed;
+  c.orth_calls = 0;
+  std::unique_lock<std::mutex> lk;
+  rqlp_status s = acquire_ws(o, c.lay.total, &c.ws, lk);
+  if (s != RQLP_OK) return s;
+
+  FactorArgs f{A, m, n, lda, q, Q, ldq, (double*)L, ldl, P, ldp};
+  const bool robust_first = (o.panel_qr == RQLP_PANEL_ROBUST);
+  hipError_t e = run_pipeline(c, f, robust_first);
+  if (e != hipSuccess) return fail(RQLP_E_HIP, "launch failed: %s", hipGetErrorString(e));
+  int fl[4] = {0, 0, 0, 0};
+  if ((s = read_flags(c, fl)) != RQLP_OK) return s;
+  int reran = 0, breakdowns = 0;
+  if (fl[0] & FLAG_NONFINITE) {
+    int fin[4] = {0, 0, 0, 0};
+    e = hipMemsetAsync(c.flags(), 0, 64, c.st);
+    if (e == hipSuccess) e = launch_check_finite(A, m, n, lda, dt, c.flags(), c.st);
+    if (e != hipSuccess) return fail(RQLP_E_HIP, "finite check: %s", hipGetErrorString(e));
+    if ((s = read_flags(c, fin)) != RQLP_OK) return s;
+    if (fin[0] & FLAG_NONFINITE) return fail(RQLP_E_NONFINITE, "A holds NaN or Inf");
+    return fail(RQLP_E_NONFINITE, "non-finite intermediate (overflow) in the factorisation");
+  }
+  if (!robust_first && (fl[0] & (FLAG_NONPOS_PIVOT | FLAG_SECOND_PASS))) {
+    breakdowns = 1;
+    if (o.panel_qr == RQLP_PANEL_AUTO) {
+      reran = 1;
+      e = run_pipeline(c, f, true);
+      if (e != hipSuccess) return fail(RQLP_E_HIP, "launch failed: %s", hipGetErrorString(e));
+      if ((s = read_flags(c, fl)) != RQLP_OK) return s;
+      if (fl[0] & FLAG_NONFINITE)
+        return fail(RQLP_E_NONFINITE, "non-finite intermediate in the robust factorisation");
+    }
+  }
+  if (o.info) {
+    o.info->d = (int32_t)d;
+    o.info->q_used = q;
+    o.info->breakdowns = breakdowns;
+    o.info->robust_rerun = reran;
+    o.info->completed = fl[2];
+    o.info->reserved = 0;
+  }
+  g_last_error.clear();
+  return RQLP_OK;
+}
+
+rqlp_status randqlp_gaussian(void* out, int64_t m, int64_t d, int64_t ld, uint64_t seed,
+                             uint64_t stream_id, int precision, void* stream) {
+  if (m < 0 || d < 0 || (m * d > 0 && (!out || ld < m)))
+    return fail(RQLP_E_INVALID_ARG, "bad size, pointer or leading dimension");
+  if (precision != RQLP_F64 && precision != RQLP_F32)
+    return fail(RQLP_E_INVALID_ARG, "unknown precision %d", precision);
+  hipError_t e = launch_gaussian(out, m, d, ld, seed, stream_id,
+                                 precision == RQLP_F64 ? DT_F64 : DT_F32, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RQLP_E_HIP, "gaussian launch: %s", hipGetErrorString(e));
+  return RQLP_OK;
+}
+
+rqlp_status randqlp_gemm(int trans_a, const void* A, int64_t m, int64_t n, int64_t lda,
+                         const void* X, int64_t d, int64_t ldx, void* C, int64_t ldc,
+                         int precision, void* stream) {
+  if (m < 1 || n < 1 || d < 1 || !A || !X || !C || lda < m)
+    return fail(RQLP_E_INVALID_ARG, "bad size, pointer or leading dimension");
+  const int64_t rows = trans_a ? n : m, K = trans_a ? m : n;
+  if (ldx < K || ldc < rows) return fail(RQLP_E_INVALID_ARG, "bad leading dimension");
+  if (precision != RQLP_F64 && precision != RQLP_F32)
+    return fail(RQLP_E_INVALID_ARG, "unknown precision %d", precision);
+  const Dtype dt = precision == RQLP_F64 ? DT_F64 : DT_F32;
+  rqlp_opts o;
+  rqlp_opts_default(&o);
+  const size_t part = gemm_partial_bytes(trans_a, rows, d, K, dt, dt, false);
+  std::unique_lock<std::mutex> lk;
+  char* ws = nullptr;
+  rqlp_status s = acquire_ws(o, part > 0 ? part : 256, &ws, lk);
+  if (s != RQLP_OK) return s;
+  GemmArgs g;
+  g.trans_a = trans_a ? 1 : 0;
+  g.A = A;
+  g.lda = lda;
+  g.B = X;
+  g.ldb = ldx;
+  g.C = C;
+  g.ldc = ldc;
+  g.M = rows;
+  g.N = d;
+  g.K = K;
+  g.in_t = dt;
+  g.out_t = dt;
+  g.gram = false;
+  g.partial = ws;
+  g.partial_bytes = part;
+  hipError_t e = launch_gemm(g, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);  // cache may be reused
+  if (e != hipSuccess) return fail(RQLP_E_HIP, "gemm: %s", hipGetErrorString(e));
+  return RQLP_OK;
+}
+
+rqlp_status randqlp_orth(const void* X, int64_t rows, int64_t d, int64_t ldx, void* Qx,
+                         int64_t ldq, double* R, int64_t ldr, int precision, int panel_qr,
+                         void* stream) {
+  if (rows < 1 || d < 1 || rows < d || !X || !Qx || ldx < rows || ldq < rows)
+    return fail(RQLP_E_INVALID_ARG, "bad size, pointer or leading dimension");
+  if (R && ldr < d) return fail(RQLP_E_INVALID_ARG, "ldr < d");
+  if (precision != RQLP_F64 && precision != RQLP_F32)
+    return fail(RQLP_E_INVALID_ARG, "unknown precision %d", precision);
+  if (panel_qr < RQLP_PANEL_AUTO || panel_qr > RQLP_PANEL_ROBUST)
+    return fail(RQLP_E_INVALID_ARG, "unknown panel_qr %d", panel_qr);
+  if (d > CHOL_MAX_D)
+    return fail(RQLP_E_UNSUPPORTED, "d = %lld exceeds %d", (long long)d, CHOL_MAX_D);
+  const Dtype dt = precision == RQLP_F64 ? DT_F64 : DT_F32;
+  Ctx c;
+  c.st = (hipStream_t)stream;
+  c.dt = dt;
+  // a panel of `rows` rows uses the m-side buffers of a rows x d layout
+  c.lay = make_layout(rows, d, d, dt);
+  c.d = d;
+  c.seed = 0x5eedull;
+  c.orth_calls = 0;
+  rqlp_opts o;
+  rqlp_opts_default(&o);
+  std::unique_lock<std::mutex> lk;
+  rqlp_status s = acquire_ws(o, c.lay.total, &c.ws, lk);
+  if (s != RQLP_OK) return s;
+  double* Rfin = c.at<double>(c.lay.Rfin);
+  bool robust = (panel_qr == RQLP_PANEL_ROBUST);
+  int fl[4] = {0, 0, 0, 0};
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    c.orth_calls = 0;
+    hipError_t e = hipMemsetAsync(c.flags(), 0, 64, c.st);
+    if (e == hipSuccess) e = orth(c, X, rows, ldx, Qx, ldq, c.ws + c.lay.m2, Rfin, robust);
+    if (e == hipSuccess && R)
+      e = hipMemcpy2DAsync(R, ldr * sizeof(double), Rfin, d * sizeof(double),
+                           d * sizeof(double), d, hipMemcpyDeviceToDevice, c.st);
+    if (e != hipSuccess) return fail(RQLP_E_HIP, "orth: %s", hipGetErrorString(e));
+    if ((s = read_flags(c, fl)) != RQLP_OK) return s;
+    if (fl[0] & FLAG_NONFINITE) return fail(RQLP_E_NONFINITE, "non-finite panel");
+    const bool bad = (fl[0] & (FLAG_NONPOS_PIVOT | FLAG_SECOND_PASS)) != 0;
+    if (robust || !bad || panel_qr != RQLP_PANEL_AUTO) break;
+    robust = true;
+  }
+  return RQLP_OK;
+}
+
+}  // extern "C"

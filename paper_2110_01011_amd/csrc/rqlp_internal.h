@@ -1,0 +1,105 @@
+// Internal declarations shared by the HIP translation units of librandqlp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace rqlp {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// Row (within a 16 x 16 block) of accumulator element r held by `lane` for
+// the 16x16x4 MFMAs; the column is lane % 16.  The fp64 instruction spreads
+// a lane's four values over rows lane/16 + 4r; the fp32 one keeps them in
+// four consecutive rows 4 (lane/16) + r.
+__device__ __forceinline__ int acc_row_f64(int lane, int r) { return (lane >> 4) + 4 * r; }
+__device__ __forceinline__ int acc_row_f32(int lane, int r) { return 4 * (lane >> 4) + r; }
+template <typename T>
+__device__ __forceinline__ int acc_row(int lane, int r);
+template <>
+__device__ __forceinline__ int acc_row<double>(int lane, int r) { return acc_row_f64(lane, r); }
+template <>
+__device__ __forceinline__ int acc_row<float>(int lane, int r) { return acc_row_f32(lane, r); }
+
+// Flag bits written by device kernels into the per-call status word.
+enum : int {
+  FLAG_NONPOS_PIVOT = 1,   // Cholesky pivot <= tolerance (panel numerically dependent)
+  FLAG_NONFINITE = 2,      // NaN/Inf met in a Gram matrix or pivot
+  FLAG_SECOND_PASS = 4,    // second Cholesky pass far from identity (unsafe)
+};
+
+// Element type tags for the launchers.
+enum Dtype : int { DT_F64 = 0, DT_F32 = 1 };
+
+constexpr int CHOL_MAX_D = 224;  // single-workgroup Cholesky limit (14 x 14 tiles of 16)
+
+// ---- philox.hip ----
+hipError_t launch_gaussian(void* out, int64_t m, int64_t d, int64_t ld, uint64_t seed,
+                           uint64_t stream_id, Dtype dt, hipStream_t st);
+// Fill columns listed in cols[0..ncols) of X (rows x ?, ldx) with Gaussian
+// values from (seed, stream_id); used to complete dependent panel columns.
+hipError_t launch_gaussian_columns(void* X, int64_t rows, int64_t ldx, const int* col_flags,
+                                   int64_t d, uint64_t seed, uint64_t stream_id, Dtype dt,
+                                   hipStream_t st);
+
+// ---- gemm.hip ----
+// C[s] (M x N) = sum over k in split s of op(A)(i,k) * B(k,j);
+// op(A)(i,k) = trans_a ? A[k + i*lda] : A[i + k*lda]; B(k,j) = B[k + j*ldb].
+// If splits == 1 the result goes straight to C (ldc); otherwise partial sums
+// go to `partial` and a fixed-order reduction writes C.
+struct GemmArgs {
+  int trans_a;
+  const void* A; int64_t lda;
+  const void* B; int64_t ldb;
+  void* C; int64_t ldc;
+  int64_t M, N, K;
+  Dtype in_t;     // type of A and B
+  Dtype out_t;    // type of C
+  bool gram;      // C = A^T A (B == A, trans_a): compute only upper tiles, mirror
+  void* partial;  // workspace for split-K partials (may be null if splits == 1)
+  size_t partial_bytes;
+  void* ev_begin = nullptr;  // optional hipEvent_t recorded around the main kernel
+  void* ev_end = nullptr;
+};
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
+size_t gemm_partial_bytes(int trans_a, int64_t M, int64_t N, int64_t K, Dtype in_t,
+                          Dtype out_t, bool gram);
+
+// ---- panel.hip ----
+// Cholesky of G + shift*I (d x d, double, ldg; d <= CHOL_MAX_D) into R
+// (upper, d x d, double, tight) and the inverses of its 16 x 16 diagonal
+// blocks (dinv, ceil(d/16)*256 doubles, each block column-major).  The shift
+// is *shift_dev when shift_dev is non-null, else `shift`.  A pivot <= tol_dep
+// * (original diagonal) marks its column dependent: that row of R is zeroed,
+// col_flags[j] = 1 (col_flags may be null) and FLAG_NONPOS_PIVOT is raised.
+// A kept pivot below tol_warn * (original diagonal) raises FLAG_SECOND_PASS.
+hipError_t launch_cholesky(const double* G, int64_t d, int64_t ldg, double shift,
+                           const double* shift_dev, double tol_dep, double tol_warn,
+                           double* R, double* dinv, int* col_flags, int* flags,
+                           hipStream_t st);
+// Qx (rows x d) = X R^+ with R upper (d x d) and its diagonal-block inverses.
+hipError_t launch_trsm(const void* X, int64_t rows, int64_t d, int64_t ldx, const double* R,
+                       const double* dinv, void* Qx, int64_t ldq, Dtype dt, hipStream_t st);
+// Rout = R2 * R1 (upper-triangular d x d, double, tight).
+hipError_t launch_trmm_upper(const double* R2, const double* R1, double* Rout, int64_t d,
+                             hipStream_t st);
+// L (d x d, ldl) = R^T with exact zeros above the diagonal.
+hipError_t launch_lower_from_upper(const double* R, int64_t d, double* L, int64_t ldl,
+                                   hipStream_t st);
+// trace of G (d x d) into *out (device double) -- used for the shift.
+hipError_t launch_trace(const double* G, int64_t d, int64_t ldg, double* out, hipStream_t st);
+// *shift_out = c * (*trace) with c chosen from the panel size (shifted Cholesky QR).
+hipError_t launch_scale_scalar(const double* in, double c, double* out, hipStream_t st);
+// Convert a float panel to double or back (rows x d, strided).
+hipError_t launch_copy_panel(const void* src, Dtype st_t, int64_t ld_src, void* dst,
+                             Dtype dt_t, int64_t ld_dst, int64_t rows, int64_t d,
+                             hipStream_t st);
+// Flags: any nonzero in col_flags[0..d) -> count into *count (device int).
+hipError_t launch_count_flags(const int* col_flags, int64_t d, int* count, hipStream_t st);
+// Scan A (m x n, lda) for NaN / Inf; raise FLAG_NONFINITE in *flags.
+hipError_t launch_check_finite(const void* A, int64_t m, int64_t n, int64_t lda, Dtype dt,
+                               int* flags, hipStream_t st);
+
+}  // namespace rqlp

@@ -1,0 +1,163 @@
+"""GPU parity of the whole factorisation (randqlp_factor) against the oracle.
+
+fp64: the sign-invariant quantities -- relative error ||A - Q L P^T||_F /
+||A||_F, the diagonal of L (relative to its first entry) and the subspace
+sines of Q and P (leading k columns and all d) -- agree with the oracle to
+1e-10.  fp32: the error stays within 1.05x the fp64 oracle's.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import jacobi_singular_values, randqlp, rel_error
+from tests.gpu_util import compare, invariants, log, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def rq():
+    import paper_2110_01011_amd as rq
+    rq.lib()
+    return rq
+
+
+def _run(rq, A, k, p, q, seed, dtype=None, panel="auto"):
+    import torch
+    dt = dtype or torch.float64
+    Q, L, P, info = rq.factor(to_dev(A, dt), k, p, q, seed, panel=panel, return_info=True)
+    return to_np(Q), to_np(L), to_np(P), info
+
+
+def _check_f64(rq, A, k, p, q, seed, tol=TOL, panel="auto"):
+    Qg, Lg, Pg, info = _run(rq, A, k, p, q, seed, panel=panel)
+    Qo, Lo, Po = randqlp(A, k, p, q, seed)
+    c = compare(A, Qg, Lg, Pg, Qo, Lo, Po, min(k, Lo.shape[0]))
+    inv = invariants(A, Qg, Lg, Pg)
+    log(f"  {c} {inv} {info}")
+    assert c["de"] <= tol and c["dsigma"] <= tol
+    assert c["sinQk"] <= tol and c["sinPk"] <= tol
+    assert c["sinQ"] <= tol and c["sinP"] <= tol
+    assert inv["orthQ"] < 1e-12 and inv["orthP"] < 1e-12
+    assert inv["upper_max"] == 0.0 and inv["min_diag"] >= 0.0
+    assert inv["L_vs_QtAP"] < 1e-12
+    return Qg, Lg, Pg, info
+
+
+def test_c1_fast_decay_parity(rq):
+    """1000 x 1000, sigma_i = i^-2, k = 20, p = 5, q = 1 (Section 5.2 family)."""
+    log("factor C1 1000x1000 k=20 p=5 q=1")
+    A, U, s, V = W.fast_decay(1000, 1000, seed=0)
+    for seed in (0, 1):
+        _check_f64(rq, A, 20, 5, 1, seed)
+
+
+@pytest.mark.parametrize("m,n,k,p,q", [(777, 555, 30, 7, 2), (300, 900, 12, 4, 1),
+                                       (640, 640, 60, 4, 0), (2049, 1500, 100, 10, 1),
+                                       (100, 80, 1, 0, 3), (4000, 3000, 200, 10, 2)])
+def test_ragged_shapes_parity(rq, m, n, k, p, q):
+    log(f"factor ragged m={m} n={n} k={k} p={p} q={q}")
+    sig = np.concatenate([np.linspace(3.0, 1.0, k), 0.5 * 0.97 ** np.arange(min(m, n) - k)])
+    A, U, s, V = W.svd_matrix(m, n, sig, seed=m + n)
+    _check_f64(rq, A, k, p, q, seed=7)
+
+
+def test_rank_plus_noise_parity(rq):
+    """The 8000 x 8000 workload's family at 2000 x 2000: rank 50 + noise."""
+    log("factor rank+noise 2000x2000 r=50 k=50 p=10 q=2")
+    A, s = W.rank_plus_noise(2000, 2000, 50, 1e-3, seed=1)
+    _check_f64(rq, A, 50, 10, 2, seed=3)
+
+
+def test_f32_error_within_5_percent(rq):
+    import torch
+    log("factor f32 1000x1000 fast decay")
+    A, U, s, V = W.fast_decay(1000, 1000, seed=0)
+    Qo, Lo, Po = randqlp(A, 20, 5, 1, 0)
+    e_o = rel_error(A, Qo, Lo, Po)
+    Qg, Lg, Pg, info = _run(rq, A, 20, 5, 1, 0, dtype=torch.float32)
+    e_g = rel_error(A, Qg, Lg, Pg)
+    inv = invariants(A.astype(np.float32).astype(np.float64), Qg, Lg, Pg)
+    log(f"  e_gpu={e_g} e_orc={e_o} {inv}")
+    assert e_g <= 1.05 * e_o
+    assert inv["orthQ"] < 1e-5 and inv["orthP"] < 1e-5
+    assert inv["upper_max"] == 0.0 and inv["min_diag"] >= 0.0
+
+
+def test_full_width_reconstructs(rq):
+    """d = min(m, n): A = Q L P^T exactly (Gaussian sketches are square)."""
+    for (m, n) in [(60, 60), (200, 120)]:
+        log(f"factor full width {m}x{n}")
+        A = W.uniform01(m, n, seed=m)
+        Qg, Lg, Pg, info = _run(rq, A, min(m, n), 0, 0, 4)
+        assert rel_error(A, Qg, Lg, Pg) < 1e-11
+        inv = invariants(A, Qg, Lg, Pg)
+        assert inv["orthQ"] < 1e-12 and inv["orthP"] < 1e-12
+        if m == n:
+            assert np.allclose(jacobi_singular_values(Lg), jacobi_singular_values(A), rtol=1e-9)
+
+
+def test_scaled_orthonormal_gives_scaled_identity(rq):
+    Uo = W.haar(300, 40, seed=4, stream=9)
+    Qg, Lg, Pg, info = _run(rq, 2.5 * Uo, 30, 10, 1, 8)
+    assert np.abs(Lg - 2.5 * np.eye(40)).max() < 1e-12
+
+
+def test_exact_low_rank_and_zero_matrix(rq):
+    sig = np.array([4.0, 2.0, 1.0, 0.5, 0.25, 0.1])
+    A, U, s, V = W.svd_matrix(200, 150, sig, seed=6)
+    Qg, Lg, Pg, info = _run(rq, A, 8, 4, 1, 3)
+    log(f"  low rank info={info}")
+    assert rel_error(A, Qg, Lg, Pg) < 1e-13
+    assert np.allclose(jacobi_singular_values(Lg[:6, :6]), sig, rtol=1e-10)
+    inv = invariants(A, Qg, Lg, Pg)
+    assert inv["orthQ"] < 1e-12 and inv["orthP"] < 1e-12
+    Z = np.zeros((120, 90))
+    Qg, Lg, Pg, info = _run(rq, Z, 10, 2, 1, 0)
+    log(f"  zero info={info}")
+    assert np.all(Lg == 0.0)
+    inv = invariants(Z, Qg, Lg, Pg)
+    assert inv["orthQ"] < 1e-12 and inv["orthP"] < 1e-12
+
+
+def test_nonfinite_input_is_reported(rq):
+    A = np.random.default_rng(0).standard_normal((100, 80))
+    A[17, 33] = np.nan
+    with pytest.raises(rq.RandQLPError) as ei:
+        _run(rq, np.asfortranarray(A), 5, 2, 1, 0)
+    assert ei.value.status == 2
+    A[17, 33] = np.inf
+    with pytest.raises(rq.RandQLPError):
+        _run(rq, np.asfortranarray(A), 5, 2, 1, 0)
+
+
+def test_bitwise_repeatable_and_prefix_property(rq):
+    A, U, s, V = W.fast_decay(900, 700, seed=2)
+    a = _run(rq, A, 10, 12, 1, 7)
+    b = _run(rq, A, 10, 12, 1, 7)
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
+    c = _run(rq, A, 10, 0, 1, 7)
+    assert np.abs(np.abs(c[0]) - np.abs(a[0][:, :10])).max() < 1e-12
+    assert np.abs(c[1] - a[1][:10, :10]).max() < 1e-12 * a[1][0, 0]
+
+
+def test_robust_panel_mode_parity(rq):
+    A, U, s, V = W.fast_decay(500, 400, seed=3)
+    _check_f64(rq, A, 20, 5, 1, 2, panel="robust")
+
+
+@pytest.mark.slow
+def test_c2_full_size_parity(rq):
+    """8000 x 8000 rank-200 + noise, k = 200, p = 10, q = 2: fp64 and fp32."""
+    import torch
+    log("factor C2 8000x8000 k=200 p=10 q=2")
+    A, s = W.rank_plus_noise(8000, 8000, 200, 1e-3, seed=0)
+    Qg, Lg, Pg, info = _check_f64(rq, A, 200, 10, 2, 0)
+    Qo, Lo, Po = randqlp(A, 200, 10, 2, 0)
+    e_o = rel_error(A, Qo, Lo, Po)
+    Q32, L32, P32, info32 = _run(rq, A, 200, 10, 2, 0, dtype=torch.float32)
+    e32 = rel_error(A, Q32, L32, P32)
+    log(f"  C2 f32 e={e32} oracle e={e_o}")
+    assert e32 <= 1.05 * e_o

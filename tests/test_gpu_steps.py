@@ -1,0 +1,141 @@
+"""GPU parity of the individual steps: the Gaussian sketch matrix, the
+sketch/power/projection products, and the panel QR (orth)."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import qr_pos
+from oracle.philox import gaussian_matrix
+from tests.gpu_util import log, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def rq():
+    import paper_2110_01011_amd as rq
+    rq.lib()
+    return rq
+
+
+@pytest.mark.parametrize("m,d,seed,sid", [(1000, 37, 0, 0), (257, 5, 123456789, 0),
+                                           (3, 7, 2 ** 63 + 5, 3), (4096, 64, 9, 0)])
+def test_gaussian_matches_oracle(rq, m, d, seed, sid):
+    import torch
+    log(f"gaussian m={m} d={d} seed={seed}")
+    ref = gaussian_matrix(m, d, seed, sid)
+    g = to_np(rq.gaussian(m, d, seed, sid, torch.float64))
+    # same Philox words; log/sqrt/cos/sin may differ from the host libm by an ulp
+    assert np.max(np.abs(g - ref)) <= 64 * U64 * max(1.0, np.abs(ref).max())
+    g32 = to_np(rq.gaussian(m, d, seed, sid, torch.float32))
+    close = np.abs(g32 - ref.astype(np.float32).astype(np.float64))
+    assert np.all(close <= 2 * U32 * np.abs(ref) + 1e-30)
+
+
+SHAPES = [(1000, 700, 25), (333, 517, 210), (64, 64, 1), (2000, 50, 130), (5, 7, 3),
+          (129, 1100, 17), (4000, 3000, 210)]
+
+
+@pytest.mark.parametrize("m,n,d", SHAPES)
+@pytest.mark.parametrize("trans", [1, 0])
+def test_gemm_f64_within_rounding_bound(rq, m, n, d, trans):
+    log(f"gemm f64 trans={trans} m={m} n={n} d={d}")
+    r = np.random.default_rng(m * 7 + n + d)
+    A = np.asfortranarray(r.standard_normal((m, n)))
+    X = r.standard_normal((m if trans else n, d))
+    C = to_np(rq.gemm(to_dev(A), to_dev(X), trans))
+    Aop = A.T if trans else A
+    ref = Aop @ X
+    K = Aop.shape[1]
+    bound = 2 * K * U64 * (np.abs(Aop) @ np.abs(X)) + 1e-300
+    assert C.shape == ref.shape
+    assert np.all(np.abs(C - ref) <= bound)
+
+
+@pytest.mark.parametrize("m,n,d", [(1000, 700, 25), (333, 517, 210), (5, 7, 3)])
+@pytest.mark.parametrize("trans", [1, 0])
+def test_gemm_f32_within_rounding_bound(rq, m, n, d, trans):
+    import torch
+    log(f"gemm f32 trans={trans} m={m} n={n} d={d}")
+    r = np.random.default_rng(m + n * 3 + d)
+    A = np.asfortranarray(r.standard_normal((m, n)).astype(np.float32))
+    X = r.standard_normal((m if trans else n, d)).astype(np.float32)
+    C = to_np(rq.gemm(to_dev(A, torch.float32), to_dev(X, torch.float32), trans))
+    Aop = (A.T if trans else A).astype(np.float64)
+    ref = Aop @ X.astype(np.float64)
+    K = Aop.shape[1]
+    bound = 2 * (K + 2) * U32 * (np.abs(Aop) @ np.abs(X.astype(np.float64)))
+    assert np.all(np.abs(C - ref) <= bound)
+
+
+def _panel(rows, d, kappa, seed):
+    r = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(r.standard_normal((rows, d)))
+    V, _ = np.linalg.qr(r.standard_normal((d, d)))
+    s = np.logspace(0, -np.log10(kappa), d)
+    return np.asfortranarray((U * s) @ V.T)
+
+
+@pytest.mark.parametrize("rows,d,kappa", [(1000, 25, 10.0), (8000, 210, 5e3), (333, 17, 1e6),
+                                          (500, 224, 1e2), (16, 16, 3.0), (20, 1, 1.0)])
+def test_orth_f64_matches_lapack(rq, rows, d, kappa):
+    log(f"orth f64 rows={rows} d={d} kappa={kappa}")
+    X = _panel(rows, d, kappa, rows + d)
+    Qo, Ro = qr_pos(X)
+    Qg, Rg = rq.orth(to_dev(X))
+    Qg, Rg = to_np(Qg), to_np(Rg)
+    assert np.abs(Qg.T @ Qg - np.eye(d)).max() < 1e-13
+    assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) >= 0)
+    assert np.abs(Qg @ Rg - X).max() <= 1e-14 * np.abs(X).max() * d
+    # QR with a positive diagonal is unique: elementwise agreement to O(u kappa)
+    assert np.abs(Qg - Qo).max() <= 1e-13 * kappa
+    assert np.abs(Rg - Ro).max() <= 1e-13 * kappa * np.abs(Ro).max()
+
+
+def test_orth_f32_orthonormal(rq):
+    import torch
+    X = _panel(3000, 64, 1e3, 5).astype(np.float32)
+    Qg, Rg = rq.orth(to_dev(X, torch.float32))
+    Qg, Rg = to_np(Qg), to_np(Rg)
+    assert np.abs(Qg.T @ Qg - np.eye(64)).max() < 2e-5
+    assert np.abs(Qg @ Rg - X).max() <= 1e-5 * np.abs(X).max()
+
+
+@pytest.mark.parametrize("case", ["duplicate", "zero_col", "zero", "low_rank"])
+def test_orth_robust_rank_deficient(rq, case):
+    log(f"orth robust {case}")
+    r = np.random.default_rng(3)
+    rows, d = 400, 20
+    X = r.standard_normal((rows, d))
+    if case == "duplicate":
+        X[:, 7] = X[:, 2]
+        dep = [7]
+    elif case == "zero_col":
+        X[:, 0] = 0.0
+        X[:, 11] = 0.0
+        dep = [0, 11]
+    elif case == "zero":
+        X[:] = 0.0
+        dep = list(range(d))
+    else:
+        X = r.standard_normal((rows, 5)) @ r.standard_normal((5, d))
+        dep = list(range(5, d))
+    X = np.asfortranarray(X)
+    for panel in ("auto", "robust"):
+        Qg, Rg = rq.orth(to_dev(X), panel=panel)
+        Qg, Rg = to_np(Qg), to_np(Rg)
+        assert np.abs(Qg.T @ Qg - np.eye(d)).max() < 1e-12
+        assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) >= 0)
+        scale = max(np.abs(X).max(), 1.0)
+        assert np.abs(Qg @ Rg - X).max() <= 1e-12 * scale
+        # Unique parts: R's diagonal before the first dependent column, and a
+        # zero pivot at each dependent column.  (After a dependent column the
+        # remaining diagonal depends on the completion direction chosen, for
+        # LAPACK as for any other QR.)
+        Ro = qr_pos(X)[1]
+        first = dep[0]
+        assert np.abs(np.diag(Rg)[:first] - np.diag(Ro)[:first]).max(initial=0.0) <= 1e-12 * scale
+        assert np.abs(np.diag(Rg)[dep]).max() <= 1e-12 * scale

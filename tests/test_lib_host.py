@@ -1,0 +1,100 @@
+"""Host-side checks of librandqlp: it loads, exports every declared symbol,
+and validates arguments before touching the GPU (no device needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2110_01011_amd as rq
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(rq.LIB_PATH):
+        from paper_2110_01011_amd.build_lib import build
+        build()
+    return rq.lib()
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "randqlp.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return set(re.findall(r"\b((?:randqlp|rqlp)_[a-z_]+)\s*\(", text))
+
+
+def test_every_declared_symbol_is_exported(L):
+    declared = _declared()
+    assert declared == set(rq.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_sketch_width(L):
+    assert rq.sketch_width(1000, 1000, 20, 5) == 25
+    assert rq.sketch_width(8000, 8000, 200, 10) == 210
+    assert rq.sketch_width(30, 100, 40, 5) == 30
+    assert rq.sketch_width(100, 12, 10, 5) == 12
+    assert rq.sketch_width(10, 10, 0, 5) == -1
+    assert rq.sketch_width(10, 10, 3, -1) == -1
+    assert rq.sketch_width(0, 10, 3, 1) == -1
+
+
+def test_workspace_size_grows(L):
+    a = rq.workspace_size(1000, 1000, 20, 5, 1)
+    b = rq.workspace_size(2000, 1000, 20, 5, 1)
+    c = rq.workspace_size(1000, 1000, 20, 5, 1, rq.F32)
+    assert 0 < a < b and 0 < c < a
+    assert rq.workspace_size(10, 10, 0, 1, 1) == 0
+    assert rq.workspace_size(10, 10, 2, 1, -1) == 0
+
+
+@pytest.mark.parametrize("args,what", [
+    ((0, 10, 3, 1, 0), "m"), ((10, 0, 3, 1, 0), "n"), ((10, 10, 0, 1, 0), "k"),
+    ((10, 10, 3, -1, 0), "p"), ((10, 10, 3, 1, -1), "q"),
+])
+def test_factor_rejects_bad_sizes(L, args, what):
+    m, n, k, p, q = args
+    dummy = ctypes.c_void_p(16)
+    st = L.randqlp_factor(dummy, m, n, k, p, q, 0, dummy, dummy, dummy, None)
+    assert st == 1
+    assert what in L.randqlp_last_error().decode()
+
+
+def test_factor_rejects_null_and_bad_ld_and_options(L):
+    dummy = ctypes.c_void_p(16)
+    assert L.randqlp_factor(None, 10, 10, 3, 1, 0, 0, dummy, dummy, dummy, None) == 1
+    o = rq.default_opts()
+    o.lda = 5
+    assert L.randqlp_factor(dummy, 10, 10, 3, 1, 0, 0, dummy, dummy, dummy, ctypes.byref(o)) == 1
+    o = rq.default_opts()
+    o.precision = 7
+    assert L.randqlp_factor(dummy, 10, 10, 3, 1, 0, 0, dummy, dummy, dummy, ctypes.byref(o)) == 1
+    o = rq.default_opts()
+    o.panel_qr = 9
+    assert L.randqlp_factor(dummy, 10, 10, 3, 1, 0, 0, dummy, dummy, dummy, ctypes.byref(o)) == 1
+
+
+def test_undersized_workspace_is_reported(L):
+    dummy = ctypes.c_void_p(256)
+    o = rq.default_opts()
+    o.workspace = ctypes.c_void_p(4096)
+    o.workspace_bytes = 16
+    st = L.randqlp_factor(dummy, 100, 80, 5, 2, 1, 0, dummy, dummy, dummy, ctypes.byref(o))
+    assert st == 4
+    assert "workspace" in L.randqlp_last_error().decode()
+
+
+def test_step_entry_points_validate(L):
+    dummy = ctypes.c_void_p(16)
+    assert L.randqlp_gaussian(dummy, 10, 3, 5, 0, 0, 0, None) == 1          # ld < m
+    assert L.randqlp_gaussian(dummy, 10, 3, 10, 0, 0, 5, None) == 1         # precision
+    assert L.randqlp_gemm(1, dummy, 10, 8, 4, dummy, 3, 10, dummy, 8, 0, None) == 1  # lda < m
+    assert L.randqlp_orth(dummy, 5, 8, 5, dummy, 5, None, 0, 0, 0, None) == 1      # rows < d
+
+
+def test_status_strings(L):
+    for code, name in rq.STATUS.items():
+        assert L.randqlp_status_string(code).decode() == name
