@@ -180,13 +180,16 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const TP* __restrict
   }
   const int64_t off = si + sj * M, stride = M * N;
   TP s = (TP)0;
+#pragma unroll 8
   for (int t = 0; t < S; ++t) s += P[off + t * stride];
   C[i + j * ldc] = (TO)s;
 }
 
 constexpr int kWavesM = 2, kWavesN = 2, kWM = 2, kBK = 16;
 constexpr int kBM = 16 * kWM * kWavesM;  // 64
-constexpr int kTargetWG = 512;
+constexpr int kGramWM = 1;               // Gram products: 32 x 32 tiles
+constexpr int kGramBM = 16 * kGramWM * kWavesM;
+constexpr int kTargetWG = 1024;
 
 struct Plan {
   int wn;          // 16-column blocks per wave along N (BN = 32 * wn)
@@ -195,23 +198,34 @@ struct Plan {
   int64_t kchunk;
 };
 
-Plan make_plan(int64_t M, int64_t N, int64_t K, bool gram) {
+// Tile and split choice.  The A-streaming products (K = m or n, long) get
+// one N tile covering d when d <= 256 (A is then read once), except that
+// the A-row-major product (trans_a = 0) keeps at most 4 blocks per wave so
+// it stays at two waves per SIMD; split-K brings the grid to ~1024
+// workgroups.  Short contractions cannot split, so they narrow the N tiles
+// instead.  Gram products use 32 x 32 tiles (upper ones only).
+Plan make_plan(int trans_a, int64_t M, int64_t N, int64_t K, bool gram) {
   Plan p;
   if (gram) {
-    p.wn = 2;  // BN = 64 = BM: square tiles, upper ones only
+    p.wn = 1;  // 32 x 32 tiles (kGramWM = 1)
   } else {
-    const int64_t ntn = (N + 255) / 256;
+    const int cap = trans_a ? 8 : 4;
+    const int64_t ntn = (N + 32 * cap - 1) / (32 * cap);
     const int64_t per = (N + ntn - 1) / ntn;
-    p.wn = (int)std::max<int64_t>(1, std::min<int64_t>(8, (per + 31) / 32));
+    p.wn = (int)std::max<int64_t>(1, std::min<int64_t>(cap, (per + 31) / 32));
+  }
+  p.tiles_m = gram ? (M + kGramBM - 1) / kGramBM : (M + kBM - 1) / kBM;
+  const int64_t max_s = std::max<int64_t>(1, K / (kBK * 8));
+  if (!gram && max_s == 1) {
+    while (p.wn > 1 && p.tiles_m * ((N + 32 * p.wn - 1) / (32 * p.wn)) < kTargetWG / 2)
+      p.wn = (p.wn + 1) / 2;
   }
   const int64_t BN = 32 * p.wn;
-  p.tiles_m = (M + kBM - 1) / kBM;
   p.tiles_n = (N + BN - 1) / BN;
   const int64_t tiles = gram ? p.tiles_m * (p.tiles_m + 1) / 2 : p.tiles_m * p.tiles_n;
   int64_t s = (kTargetWG + tiles - 1) / tiles;
-  const int64_t max_s = std::max<int64_t>(1, K / (kBK * 8));
   s = std::max<int64_t>(1, std::min(s, max_s));
-  if (gram) s = std::min<int64_t>(s, 64);
+  if (gram) s = std::min<int64_t>(s, 48);
   int64_t chunk = (K + s - 1) / s;
   chunk = (chunk + kBK - 1) / kBK * kBK;
   s = (K + chunk - 1) / chunk;
@@ -248,7 +262,7 @@ void dispatch_wn(const GemmArgs& g, const Plan& p, TO* dst, int64_t lddst, int64
 
 template <typename TI, typename TC, typename TO>
 hipError_t gemm_typed(const GemmArgs& g, hipStream_t st) {
-  const Plan p = make_plan(g.M, g.N, g.K, g.gram);
+  const Plan p = make_plan(g.trans_a, g.M, g.N, g.K, g.gram);
   const bool direct = (p.splits == 1) && !g.gram;
   TO* dst = direct ? (TO*)g.C : (TO*)g.partial;
   const int64_t lddst = direct ? g.ldc : g.M;
@@ -258,7 +272,10 @@ hipError_t gemm_typed(const GemmArgs& g, hipStream_t st) {
     return hipErrorInvalidValue;
   if (g.ev_begin) (void)hipEventRecord((hipEvent_t)g.ev_begin, st);
   if (g.gram) {
-    run_gemm<TI, TC, TO, true, 2>(g, p, dst, lddst, strideS, st);
+    dim3 grid((unsigned)p.tiles_m, (unsigned)p.tiles_n, (unsigned)p.splits);
+    hipLaunchKernelGGL((gemm_kernel<TI, TC, TO, true, kWavesM, kWavesN, kGramWM, 1, kBK>), grid,
+                       dim3(64 * kWavesM * kWavesN), 0, st, (const TI*)g.A, g.lda,
+                       (const TI*)g.B, g.ldb, dst, lddst, strideS, g.M, g.N, g.K, p.kchunk, 1);
   } else if (g.trans_a) {
     dispatch_wn<TI, TC, TO, true>(g, p, dst, lddst, strideS, st);
   } else {
@@ -270,17 +287,21 @@ hipError_t gemm_typed(const GemmArgs& g, hipStream_t st) {
   const int64_t total = g.M * g.N;
   hipLaunchKernelGGL((splitk_reduce_kernel<TO, TO>), dim3((unsigned)((total + 255) / 256)),
                      dim3(256), 0, st, (const TO*)g.partial, g.M, g.N, p.splits, (TO*)g.C,
-                     g.ldc, g.gram ? kBM : 0);
+                     g.ldc, g.gram ? kGramBM : 0);
   return hipGetLastError();
 }
 
 }  // namespace
 
+int64_t gemm_tile_count(int trans_a, int64_t M, int64_t N, int64_t K, bool gram) {
+  const Plan p = make_plan(trans_a, M, N, K, gram);
+  return p.tiles_m * p.tiles_n;
+}
+
 size_t gemm_partial_bytes(int trans_a, int64_t M, int64_t N, int64_t K, Dtype in_t,
                           Dtype out_t, bool gram) {
-  (void)trans_a;
   (void)in_t;
-  const Plan p = make_plan(M, N, K, gram);
+  const Plan p = make_plan(trans_a, M, N, K, gram);
   if (p.splits == 1 && !gram) return 0;
   return (size_t)p.splits * (size_t)M * (size_t)N * (out_t == DT_F64 ? 8 : 4);
 }

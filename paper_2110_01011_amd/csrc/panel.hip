@@ -35,16 +35,28 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Cholesky workgroup: wave 0 factors the diagonal tiles; wave 4 (which
+// shares wave 0's SIMD) holds nothing, so no MFMA work competes with the
+// pivot chain; the six other waves hold the lower tiles.
 constexpr int kCholWaves = 8;
-constexpr int kCholSlots = 14;  // ceil(105 lower tiles (d <= 224) / 8 waves)
+constexpr int kTileWaves = 6;
+constexpr int kCholSlots = 18;  // ceil(105 lower tiles (d <= 224) / 6 waves)
 
-// Factor the 16 x 16 diagonal tile held in dg (row-major) in place into its
-// lower Cholesky factor, and write the (dependent-aware) inverse of that
-// factor into dgi.  Run by one wave; lanes 0..15 each own one row.
-__device__ void factor_diag_tile(double (*dg)[17], double (*dgi)[17], const double* odiag,
-                                 int J, int d, double tol_dep, double tol_warn,
-                                 int* __restrict__ col_flags, double* __restrict__ dinv,
-                                 int* sflag) {
+__device__ __forceinline__ int tile_wave_id(int idx) { return idx < 3 ? idx + 1 : idx + 2; }
+__device__ __forceinline__ int tile_wave_idx(int wave) { return wave < 4 ? wave - 1 : wave - 2; }
+
+// Factor the 16 x 16 diagonal tile held in dg (row-major, full symmetric) in
+// place into its lower Cholesky factor L_JJ, and write the inverse of that
+// factor into dgi (and R_JJ^{-1} = L_JJ^{-T} into dinv).  Run by one wave:
+// lanes 0..15 own one row each; pivots travel by readlane, so the chain of
+// 16 pivots needs no LDS round trips.  1/l_ss comes from rsqrt (no divide on
+// the chain).  A dependent pivot (<= tol_dep of the column's original
+// diagonal, or non-finite) gives a zero column of L and a zero row of the
+// inverse.
+__device__ __forceinline__ void factor_diag_tile(double (*dg)[17], double (*dgi)[17], double* invd,
+                                 const double* odiag, int J, int d, double tol_dep,
+                                 double tol_warn, int* __restrict__ col_flags,
+                                 double* __restrict__ dinv, int* sflag) {
   const int lane = threadIdx.x & 63;
   const int i = lane & 15;
   int bits = 0;
@@ -65,69 +77,62 @@ __device__ void factor_diag_tile(double (*dg)[17], double (*dgi)[17], const doub
         if (!dep && piv < tol_warn * orig) bits |= FLAG_SECOND_PASS;
         if (col_flags != nullptr && lane == 0) col_flags[gj] = dep ? 1 : 0;
       }
-      const double lss = dep ? 0.0 : sqrt(piv);
-      const double inv = dep ? 0.0 : 1.0 / lss;
-      const double lis = (i > s) ? a[s] * inv : ((i == s) ? lss : 0.0);
+      const double y = dep ? 0.0 : rsqrt(piv);  // 1 / l_ss
+      const double lss = piv * y;
+      if (lane == 0) invd[s] = y;
+      const double lis = (i > s) ? a[s] * y : ((i == s) ? lss : 0.0);
       a[s] = lis;
 #pragma unroll
       for (int j = s + 1; j < 16; ++j) {
         const double ljs = readlane_d(lis, j);
-        a[j] -= lis * ljs;
+        a[j] = fma(-lis, ljs, a[j]);
       }
     }
-    wave_sync_lds();
     if (lane < 16) {
 #pragma unroll
       for (int c = 0; c < 16; ++c) dg[i][c] = (c > i) ? 0.0 : a[c];
     }
     wave_sync_lds();
   }
-  // Inverse of the lower factor by forward substitution, one column per
-  // lane: X[i][c] = (delta_ic - sum_{t<i} L[i][t] X[t][c]) / L[i][i]; a zero
-  // pivot gives a zero row (the dependent-column rule).
+  // Inverse by forward substitution, one column per lane:
+  // X[r][c] = (delta_rc - sum_{t<r} L[r][t] X[t][c]) / L[r][r]  (0 if dependent).
   const int c = lane & 15;
   double x[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
-    double v = (r == c) ? 1.0 : 0.0;
+    double v0 = (r == c) ? 1.0 : 0.0, v1 = 0.0;
 #pragma unroll
-    for (int t = 0; t < r; ++t) v -= dg[r][t] * x[t];
-    const double lrr = dg[r][r];
-    x[r] = (lrr != 0.0) ? v / lrr : 0.0;
+    for (int t = 0; t < r; t += 2) {
+      v0 = fma(-dg[r][t], x[t], v0);
+      if (t + 1 < r) v1 = fma(-dg[r][t + 1], x[t + 1], v1);
+    }
+    x[r] = (v0 + v1) * invd[r];
   }
   if (lane < 16) {
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
       dgi[r][c] = x[r];
-      // R_JJ^{-1} = (L_JJ^{-1})^T, column-major block: element (c, r) at c + 16 r.
-      dinv[(int64_t)J * 256 + c + r * 16] = x[r];
+      dinv[(int64_t)J * 256 + c + r * 16] = x[r];  // (L^{-1})^T, column-major block
     }
   }
   if (lane == 0 && bits) *sflag |= bits;
 }
 
-__global__ __launch_bounds__(512) void cholesky_kernel(
-    const double* __restrict__ G, int d, int64_t ldg, double shift,
-    const double* __restrict__ shift_dev, double tol_dep, double tol_warn,
-    double* __restrict__ R, double* __restrict__ dinv, int* __restrict__ col_flags,
-    int* __restrict__ flags) {
-  __shared__ double dg[16][17];
-  __shared__ double dgi[16][17];
-  __shared__ double pan[CHOL_MAX_D][17];
-  __shared__ double odiag[CHOL_MAX_D];
-  __shared__ int sflag;
-
+// Tile-wave part of the Cholesky kernel: holds its lower tiles of G in MFMA
+// layout, applies panel solves and trailing updates, hands each updated
+// diagonal tile to the factor wave, and finally writes its part of R.
+__device__ __forceinline__ void chol_tile_wave(
+    const double* __restrict__ G, int d, int64_t ldg, double sh, double (*dg)[17],
+    double (*dgi)[17], double (*pan)[17], int* ready, int wave, double* __restrict__ R) {
+  const int lane = threadIdx.x & 63;
   const int nt = (d + 15) / 16;
   const int T = nt * (nt + 1) / 2;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const double sh = (shift_dev != nullptr) ? *shift_dev : shift;
-
+  const int twi = tile_wave_idx(wave);
   double4_t acc[kCholSlots];
   int tI[kCholSlots], tJ[kCholSlots];
 #pragma unroll
   for (int s = 0; s < kCholSlots; ++s) {
-    const int t = wave + kCholWaves * s;
+    const int t = twi + kTileWaves * s;
     tI[s] = -1;
     tJ[s] = -1;
     acc[s] = double4_t{0, 0, 0, 0};
@@ -152,24 +157,24 @@ __global__ __launch_bounds__(512) void cholesky_kernel(
       }
     }
   }
-  for (int j = tid; j < CHOL_MAX_D; j += blockDim.x)
-    odiag[j] = (j < d) ? G[j + (int64_t)j * ldg] + sh : 1.0;
-  if (tid == 0) sflag = 0;
-  __syncthreads();
-
+  // Diagonal tile J lives at t = J (J + 3) / 2.
+  auto owner = [&](int J) { return tile_wave_id((J * (J + 3) / 2) % kTileWaves); };
+  auto slot = [&](int J) { return (J * (J + 3) / 2) / kTileWaves; };
+  auto publish = [&](int J, double4_t c) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dg[acc_row_f64(lane, r)][lane & 15] = c[r];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane == 0) __hip_atomic_store(ready, J, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
+  __syncthreads();  // odiag and the flags are initialised
+  if (wave == owner(0)) {
+#pragma unroll
+    for (int s = 0; s < kCholSlots; ++s)
+      if (s == slot(0)) publish(0, acc[s]);
+  }
   for (int J = 0; J < nt; ++J) {
-    const int td = J * (J + 1) / 2 + J;
-    if (wave == td % kCholWaves) {
-#pragma unroll
-      for (int s = 0; s < kCholSlots; ++s)
-        if (s == td / kCholWaves) {
-#pragma unroll
-          for (int r = 0; r < 4; ++r) dg[acc_row_f64(lane, r)][lane & 15] = acc[s][r];
-        }
-    }
-    __syncthreads();
-    if (wave == 0) factor_diag_tile(dg, dgi, odiag, J, d, tol_dep, tol_warn, col_flags, dinv, &sflag);
-    __syncthreads();
+    __syncthreads();  // L_JJ and its inverse are ready
+    // Panel: L_IJ = G_IJ L_JJ^{-T} for the tiles below the diagonal.
 #pragma unroll
     for (int s = 0; s < kCholSlots; ++s) {
       if (tJ[s] != J) continue;
@@ -194,11 +199,30 @@ __global__ __launch_bounds__(512) void cholesky_kernel(
         for (int r = 0; r < 4; ++r) pan[16 * I + acc_row_f64(lane, r)][lane & 15] = res[r];
       }
     }
-    __syncthreads();
+    __syncthreads();  // panel J is ready
+    // Lookahead: bring tile (J+1, J+1) up to date and hand it to wave 0,
+    // then apply the rest of the trailing update.
+    const bool ahead = (J + 1 < nt) && (wave == owner(J + 1));
+    if (ahead) {
+#pragma unroll
+      for (int s = 0; s < kCholSlots; ++s) {
+        if (s != slot(J + 1)) continue;
+        double4_t c = acc[s];
+        const int I = J + 1;
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+          const double a = pan[16 * I + (lane & 15)][kq * 4 + (lane >> 4)];
+          c = mma64(-a, a, c);
+        }
+        acc[s] = c;
+        publish(J + 1, c);
+      }
+    }
 #pragma unroll
     for (int s = 0; s < kCholSlots; ++s) {
       const int I = tI[s], K = tJ[s];
       if (K <= J) continue;
+      if (ahead && I == J + 1 && K == J + 1) continue;
       double4_t c = acc[s];
 #pragma unroll
       for (int kq = 0; kq < 4; ++kq) {
@@ -224,37 +248,88 @@ __global__ __launch_bounds__(512) void cholesky_kernel(
       }
     }
   }
+}
+
+// Cholesky of G + shift I (d <= 224) on one workgroup of 8 waves.  Wave 0
+// factors each 16 x 16 diagonal tile as soon as its owner publishes it
+// (an LDS flag; the owner never waits on wave 0, so the wait always ends);
+// wave 4 shares wave 0's SIMD and stays idle so no MFMA issue competes with
+// the pivot chain; the six other waves hold the tiles.
+__global__ __launch_bounds__(512) void cholesky_kernel(
+    const double* __restrict__ G, int d, int64_t ldg, double shift,
+    const double* __restrict__ shift_dev, double tol_dep, double tol_warn,
+    double* __restrict__ R, double* __restrict__ dinv, int* __restrict__ col_flags,
+    int* __restrict__ flags) {
+  __shared__ double dg[16][17];
+  __shared__ double dgi[16][17];
+  __shared__ double invd[16];
+  __shared__ double pan[CHOL_MAX_D][17];
+  __shared__ double odiag[CHOL_MAX_D];
+  __shared__ int sflag;
+  __shared__ int ready;  // index of the last diagonal tile published in dg
+
+  const int nt = (d + 15) / 16;
+  const int tid = threadIdx.x;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const double sh = (shift_dev != nullptr) ? *shift_dev : shift;
+  for (int j = tid; j < CHOL_MAX_D; j += blockDim.x)
+    odiag[j] = (j < d) ? G[j + (int64_t)j * ldg] + sh : 1.0;
+  if (tid == 0) {
+    sflag = 0;
+    ready = -1;
+  }
+  if (wave == 0) {
+    __syncthreads();
+    for (int J = 0; J < nt; ++J) {
+      while (__hip_atomic_load(&ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < J)
+        __builtin_amdgcn_s_sleep(1);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      factor_diag_tile(dg, dgi, invd, odiag, J, d, tol_dep, tol_warn, col_flags, dinv, &sflag);
+      __syncthreads();  // L_JJ and its inverse are ready
+      __syncthreads();  // panel J is ready
+    }
+  } else if (wave == 4) {
+    __syncthreads();
+    for (int J = 0; J < nt; ++J) {
+      __syncthreads();
+      __syncthreads();
+    }
+  } else {
+    chol_tile_wave(G, d, ldg, sh, dg, dgi, pan, &ready, wave, R);
+  }
   __syncthreads();
   if (tid == 0 && sflag) atomicOr(flags, sflag);
 }
 
-// Qx = X R^+ by block forward substitution; each wave owns 16 rows.
-template <typename TX, typename TO, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void trsm_kernel(
-    const TX* __restrict__ X, int64_t rows, int d, int64_t ldx, const double* __restrict__ R,
-    const double* __restrict__ dinv, TO* __restrict__ Qx, int64_t ldq) {
-  extern __shared__ double smem[];
+// Qx = X R^+ by block forward substitution.  One wave (one workgroup) owns 16
+// rows: for each 16-column block J it forms V_J = X_J - sum_{K<J} Q_K R_KJ
+// with MFMA (A fragments from its finished columns kept in LDS, B fragments
+// of R read from L2), then Q_J = V_J R_JJ^{-1}.  The k-steps run in batches
+// of 16 whose next batch of fragments is loaded while the current batch's
+// MFMAs execute (two accumulator chains).  No workgroup barriers; X and Q
+// move through the wave's LDS panel so global accesses stay coalesced.  X
+// and Qx may be the same array (each wave reads a block of its rows before
+// overwriting it).
+template <typename TX, typename TO>
+__global__ __launch_bounds__(64) void trsm_kernel(const TX* X, int64_t rows, int d, int64_t ldx,
+                                                  const double* __restrict__ R,
+                                                  const double* __restrict__ dinv, TO* Qx,
+                                                  int64_t ldq) {
+  extern __shared__ double Qw[];
+  constexpr int B = 16;
   const int nt = (d + 15) / 16, dp = nt * 16, lq = dp + 1;
-  double* Qs = smem;
-  double* Rb = Qs + WAVES * 16 * lq;
-  double* Tb = Rb + dp * 17;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t r0 = ((int64_t)blockIdx.x * WAVES + wave) * 16;
-  double* Qw = Qs + wave * 16 * lq;
-
+  const int lane = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * 16;
+  const int li = lane & 15, lk = lane >> 4;
   for (int J = 0; J < nt; ++J) {
-    __syncthreads();
     const int kk = 16 * J;
-    for (int idx = tid; idx < kk * 16; idx += 64 * WAVES) {
-      const int t = idx % kk, c = idx / kk;
-      const int gc = kk + c;
-      Rb[t * 17 + c] = (gc < d) ? R[t + (int64_t)gc * d] : 0.0;
-    }
-    for (int idx = tid; idx < 256; idx += 64 * WAVES) {
-      const int r = idx & 15, c = idx >> 4;
-      Tb[r * 17 + c] = dinv[(int64_t)J * 256 + r + c * 16];
-    }
-    // stage this wave's 16 x 16 block of X (coalesced down the columns)
+    const int colR = kk + li;
+    const bool colok = colR < d;
+    const double* Rc = R + (int64_t)(colok ? colR : 0) * d + lk;
+    const int nk = 4 * J;
+    double bc[B], bn[B];
+#pragma unroll
+    for (int q = 0; q < B; ++q) bc[q] = (q < nk && colok) ? Rc[q * 4] : 0.0;
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int idx = lane + 64 * e;
@@ -263,29 +338,39 @@ __global__ __launch_bounds__(64 * WAVES) void trsm_kernel(
       const int col = kk + cc;
       Qw[rr * lq + col] = (row < rows && col < d) ? (double)X[row + (int64_t)col * ldx] : 0.0;
     }
-    __syncthreads();
-    double4_t acc;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) acc[r] = Qw[(acc_row_f64(lane, r)) * lq + kk + (lane & 15)];
-    for (int kq = 0; kq < 4 * J; ++kq) {
-      const double a = Qw[(lane & 15) * lq + kq * 4 + (lane >> 4)];
-      const double b = Rb[(kq * 4 + (lane >> 4)) * 17 + (lane & 15)];
-      acc = mma64(-a, b, acc);
-    }
     wave_sync_lds();
+    double4_t acc0, acc1 = {0, 0, 0, 0};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Qw[(acc_row_f64(lane, r)) * lq + kk + (lane & 15)] = acc[r];
+    for (int r = 0; r < 4; ++r) acc0[r] = Qw[acc_row_f64(lane, r) * lq + kk + li];
+    for (int base = 0; base < nk; base += B) {
+      const int nb = base + B;
+#pragma unroll
+      for (int q = 0; q < B; ++q) bn[q] = (nb + q < nk && colok) ? Rc[(nb + q) * 4] : 0.0;
+      double ac[B];
+#pragma unroll
+      for (int q = 0; q < B; ++q) ac[q] = (base + q < nk) ? Qw[li * lq + (base + q) * 4 + lk] : 0.0;
+#pragma unroll
+      for (int q = 0; q < B; q += 2) {
+        acc0 = mma64(-ac[q], bc[q], acc0);
+        acc1 = mma64(-ac[q + 1], bc[q + 1], acc1);
+      }
+#pragma unroll
+      for (int q = 0; q < B; ++q) bc[q] = bn[q];
+    }
+    acc0 += acc1;
+    double tb[4];
+    const double* T = dinv + (int64_t)J * 256;
+#pragma unroll
+    for (int q4 = 0; q4 < 4; ++q4) tb[q4] = T[q4 * 4 + lk + li * 16];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Qw[acc_row_f64(lane, r) * lq + kk + li] = acc0[r];
     wave_sync_lds();
     double4_t res = {0, 0, 0, 0};
 #pragma unroll
-    for (int kq = 0; kq < 4; ++kq) {
-      const double a = Qw[(lane & 15) * lq + kk + kq * 4 + (lane >> 4)];
-      const double b = Tb[(kq * 4 + (lane >> 4)) * 17 + (lane & 15)];
-      res = mma64(a, b, res);
-    }
+    for (int q4 = 0; q4 < 4; ++q4) res = mma64(Qw[li * lq + kk + q4 * 4 + lk], tb[q4], res);
     wave_sync_lds();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Qw[(acc_row_f64(lane, r)) * lq + kk + (lane & 15)] = res[r];
+    for (int r = 0; r < 4; ++r) Qw[acc_row_f64(lane, r) * lq + kk + li] = res[r];
     wave_sync_lds();
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -296,6 +381,28 @@ __global__ __launch_bounds__(64 * WAVES) void trsm_kernel(
       if (row < rows && col < d) Qx[row + (int64_t)col * ldq] = (TO)Qw[rr * lq + col];
     }
   }
+}
+
+// Second Cholesky QR pass to first order.  For a nearly orthonormal Q1 the
+// Gram matrix is G2 = I + E with small E, and chol(I + E) = I + F + O(|E|^2)
+// with F = (strict upper part of E) + diag(E) / 2.  Writes B = I - F (so
+// Q = Q1 B = Q1 R2^{-1} + O(|E|^2)), R2 = I + F, and raises FLAG_SECOND_PASS
+// when max |E| exceeds tol (then the expansion is not accurate enough).
+__global__ __launch_bounds__(256) void first_order_pass_kernel(const double* __restrict__ G2,
+                                                               int d, double tol,
+                                                               double* __restrict__ B,
+                                                               double* __restrict__ R2,
+                                                               int* __restrict__ flags) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)d * d) return;
+  const int i = (int)(idx % d), j = (int)(idx / d);
+  const double e = G2[idx] - (i == j ? 1.0 : 0.0);
+  double f = 0.0;
+  if (i < j) f = e;
+  else if (i == j) f = 0.5 * e;
+  B[idx] = (i == j ? 1.0 : 0.0) - f;
+  R2[idx] = (i == j ? 1.0 : 0.0) + f;
+  if (!(fabs(e) <= tol)) atomicOr(flags, FLAG_SECOND_PASS);
 }
 
 __global__ __launch_bounds__(256) void trmm_upper_kernel(const double* __restrict__ R2,
@@ -388,21 +495,15 @@ hipError_t launch_cholesky(const double* G, int64_t d, int64_t ldg, double shift
   return hipGetLastError();
 }
 
-template <typename TX, typename TO, int WAVES>
+template <typename TX, typename TO>
 static hipError_t trsm_typed(const void* X, int64_t rows, int64_t d, int64_t ldx,
                              const double* R, const double* dinv, void* Qx, int64_t ldq,
                              hipStream_t st) {
   const int nt = (int)((d + 15) / 16), dp = nt * 16;
-  const size_t lds = sizeof(double) * ((size_t)WAVES * 16 * (dp + 1) + (size_t)dp * 17 + 16 * 17);
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipFuncSetAttribute((const void*)trsm_kernel<TX, TO, WAVES>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    attr_set = true;
-  }
-  const int64_t blocks = (rows + 16 * WAVES - 1) / (16 * WAVES);
-  hipLaunchKernelGGL((trsm_kernel<TX, TO, WAVES>), dim3((unsigned)blocks), dim3(64 * WAVES),
-                     lds, st, (const TX*)X, rows, (int)d, ldx, R, dinv, (TO*)Qx, ldq);
+  const size_t lds = sizeof(double) * (size_t)16 * (dp + 1);
+  const int64_t blocks = (rows + 15) / 16;
+  hipLaunchKernelGGL((trsm_kernel<TX, TO>), dim3((unsigned)blocks), dim3(64), lds, st,
+                     (const TX*)X, rows, (int)d, ldx, R, dinv, (TO*)Qx, ldq);
   return hipGetLastError();
 }
 
@@ -410,14 +511,15 @@ hipError_t launch_trsm(const void* X, int64_t rows, int64_t d, int64_t ldx, cons
                        const double* dinv, void* Qx, int64_t ldq, Dtype dt, hipStream_t st) {
   if (d > CHOL_MAX_D) return hipErrorInvalidValue;
   if (rows <= 0 || d <= 0) return hipSuccess;
-  const int dp = (int)((d + 15) / 16) * 16;
-  const size_t lds4 = sizeof(double) * ((size_t)4 * 16 * (dp + 1) + (size_t)dp * 17 + 16 * 17);
-  const bool four = lds4 <= 160 * 1024;
-  if (dt == DT_F64)
-    return four ? trsm_typed<double, double, 4>(X, rows, d, ldx, R, dinv, Qx, ldq, st)
-                : trsm_typed<double, double, 2>(X, rows, d, ldx, R, dinv, Qx, ldq, st);
-  return four ? trsm_typed<float, float, 4>(X, rows, d, ldx, R, dinv, Qx, ldq, st)
-              : trsm_typed<float, float, 2>(X, rows, d, ldx, R, dinv, Qx, ldq, st);
+  if (dt == DT_F64) return trsm_typed<double, double>(X, rows, d, ldx, R, dinv, Qx, ldq, st);
+  return trsm_typed<float, float>(X, rows, d, ldx, R, dinv, Qx, ldq, st);
+}
+
+hipError_t launch_first_order_pass(const double* G2, int64_t d, double tol, double* B,
+                                   double* R2, int* flags, hipStream_t st) {
+  hipLaunchKernelGGL(first_order_pass_kernel, dim3(grid_for(d * d)), dim3(256), 0, st, G2,
+                     (int)d, tol, B, R2, flags);
+  return hipGetLastError();
 }
 
 hipError_t launch_trmm_upper(const double* R2, const double* R1, double* Rout, int64_t d,

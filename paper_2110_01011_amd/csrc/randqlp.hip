@@ -62,6 +62,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 struct Layout {
   size_t m1, m2, n1, n2, part, part_bytes, G, R[4], Racc[2], Rfin, dinv, colf, scal, flags,
       total;
+  size_t flags_bytes;  // status words cleared at the start of a call
 };
 
 size_t elem_size(Dtype dt) { return dt == DT_F64 ? 8 : 4; }
@@ -94,6 +95,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt) {
   L.colf = take((size_t)d * 4);
   L.scal = take(64);
   L.flags = take(64);
+  L.flags_bytes = 64;
   L.total = off;
   return L;
 }
@@ -197,23 +199,54 @@ hipError_t chol_pass(Ctx& c, const void* X, int64_t rows, int64_t ldx, void* Qx,
   return launch_trsm(X, rows, d, ldx, Rbuf, dinv, Qx, ldq, c.dt, c.st);
 }
 
+// Panel QR strategies, cheapest first.
+//  FAST     intermediate panels (whose range is all the next product uses):
+//           one Cholesky QR pass, in place.  Final panels (Q and P): one
+//           pass, then the second pass to first order in E = Q1^T Q1 - I.
+//  CHOLQR2  two full Cholesky QR passes on every panel.
+//  ROBUST   shifted pass, completion of dependent columns, two more passes.
+enum PanelMode { PM_FAST = 0, PM_CHOLQR2 = 1, PM_ROBUST = 2 };
+
+// max |E| for which the first-order second pass is accurate to the
+// precision's rounding level (the neglected terms are O(|E|^2)).
+double first_order_tol(Dtype dt) { return dt == DT_F64 ? 1e-8 : 1e-3; }
+
 // orth(): X (rows x d, ldx) -> out (rows x d, ldo), using tmp (rows x d,
-// ld = rows).  out may alias X; tmp may not alias either.  If Rout is given
-// it receives R with X = out * R.
+// ld = rows).  out may alias X (same ld); tmp may alias neither.  If Rout is
+// given it receives R with X = out * R.  final_panel selects the two-pass
+// treatment in FAST mode.
 hipError_t orth(Ctx& c, const void* X, int64_t rows, int64_t ldx, void* out, int64_t ldo,
-                void* tmp, double* Rout, bool robust) {
+                void* tmp, double* Rout, PanelMode mode, bool final_panel) {
   const int64_t d = c.d;
   double* R[4] = {c.at<double>(c.lay.R[0]), c.at<double>(c.lay.R[1]),
                   c.at<double>(c.lay.R[2]), c.at<double>(c.lay.R[3])};
   const int call = c.orth_calls++;
-  if (!robust) {
+  double* G = c.at<double>(c.lay.G);
+  if (mode == PM_FAST) {
+    if (!final_panel) {
+      // out = X R^{-1}; the TRSM may run in place (each wave reads a block
+      // of its own rows before overwriting it).
+      return chol_pass(c, X, rows, ldx, out, ldo, R[0], nullptr, kTolDepFast, 0.0, nullptr);
+    }
+    HIP_TRY(chol_pass(c, X, rows, ldx, tmp, rows, R[0], nullptr, kTolDepFast, 0.0, nullptr));
+    HIP_TRY(gemm(c, 1, tmp, rows, tmp, rows, G, d, d, d, rows, c.dt, DT_F64, true));
+    HIP_TRY(launch_first_order_pass(G, d, first_order_tol(c.dt), R[2], R[1], c.flags(), c.st));
+    const void* B = R[2];
+    if (c.dt == DT_F32) {
+      HIP_TRY(launch_copy_panel(R[2], DT_F64, d, R[3], DT_F32, d, d, d, c.st));
+      B = R[3];
+    }
+    HIP_TRY(gemm(c, 0, tmp, rows, B, d, out, ldo, rows, d, d, c.dt, c.dt, false));
+    if (Rout) HIP_TRY(gemm(c, 0, R[1], d, R[0], d, Rout, d, d, d, d, DT_F64, DT_F64, false));
+    return hipSuccess;
+  }
+  if (mode == PM_CHOLQR2) {
     HIP_TRY(chol_pass(c, X, rows, ldx, tmp, rows, R[0], nullptr, kTolDepFast, 0.0, nullptr));
     HIP_TRY(chol_pass(c, tmp, rows, rows, out, ldo, R[1], nullptr, kTolDepFast, kTolWarnSecond,
                       nullptr));
-    if (Rout) HIP_TRY(launch_trmm_upper(R[1], R[0], Rout, d, c.st));
+    if (Rout) HIP_TRY(gemm(c, 0, R[1], d, R[0], d, Rout, d, d, d, d, DT_F64, DT_F64, false));
     return hipSuccess;
   }
-  double* G = c.at<double>(c.lay.G);
   double* scal = c.at<double>(c.lay.scal);
   int* colf = c.at<int>(c.lay.colf);
   // pass 1: shifted Cholesky QR, shift = 11 (rows d + d (d + 1)) u ||X||_F^2
@@ -236,9 +269,9 @@ hipError_t orth(Ctx& c, const void* X, int64_t rows, int64_t ldx, void* out, int
   if (Rout) {
     double* A0 = c.at<double>(c.lay.Racc[0]);
     double* A1 = c.at<double>(c.lay.Racc[1]);
-    HIP_TRY(launch_trmm_upper(R[1], R[0], A0, d, c.st));
-    HIP_TRY(launch_trmm_upper(R[2], A0, A1, d, c.st));
-    HIP_TRY(launch_trmm_upper(R[3], A1, Rout, d, c.st));
+    HIP_TRY(gemm(c, 0, R[1], d, R[0], d, A0, d, d, d, d, DT_F64, DT_F64, false));
+    HIP_TRY(gemm(c, 0, R[2], d, A0, d, A1, d, d, d, d, DT_F64, DT_F64, false));
+    HIP_TRY(gemm(c, 0, R[3], d, A1, d, Rout, d, d, d, d, DT_F64, DT_F64, false));
   }
   return hipSuccess;
 }
@@ -255,7 +288,7 @@ struct FactorArgs {
   int64_t ldp;
 };
 
-hipError_t run_pipeline(Ctx& c, const FactorArgs& f, bool robust) {
+hipError_t run_pipeline(Ctx& c, const FactorArgs& f, PanelMode mode) {
   const int64_t m = f.m, n = f.n, d = c.d;
   void* Zm = c.ws + c.lay.m1;
   void* Tm = c.ws + c.lay.m2;
@@ -263,21 +296,21 @@ hipError_t run_pipeline(Ctx& c, const FactorArgs& f, bool robust) {
   void* Tn = c.ws + c.lay.n2;
   double* Rfin = c.at<double>(c.lay.Rfin);
   c.orth_calls = 0;
-  HIP_TRY(hipMemsetAsync(c.flags(), 0, 64, c.st));
-  HIP_TRY(launch_gaussian(Zm, m, d, m, c.seed, 0, c.dt, c.st));                // randn
+  HIP_TRY(hipMemsetAsync(c.flags(), 0, c.lay.flags_bytes, c.st));
+  HIP_TRY(launch_gaussian(Zm, m, d, m, c.seed, 0, c.dt, c.st));                     // randn
   HIP_TRY(gemm(c, 1, f.A, f.lda, Zm, m, Yn, n, n, d, m, c.dt, c.dt, false, true));  // A^T Omega
-  HIP_TRY(orth(c, Yn, n, n, Yn, n, Tn, nullptr, robust));                       // Qbar
+  HIP_TRY(orth(c, Yn, n, n, Yn, n, Tn, nullptr, mode, false));                       // Qbar
   for (int it = 0; it < f.q; ++it) {
     HIP_TRY(gemm(c, 0, f.A, f.lda, Yn, n, Zm, m, m, d, n, c.dt, c.dt, false, true));  // A Qbar
-    HIP_TRY(orth(c, Zm, m, m, Zm, m, Tm, nullptr, robust));
+    HIP_TRY(orth(c, Zm, m, m, Zm, m, Tm, nullptr, mode, false));
     HIP_TRY(gemm(c, 1, f.A, f.lda, Zm, m, Yn, n, n, d, m, c.dt, c.dt, false, true));  // A^T Q
-    HIP_TRY(orth(c, Yn, n, n, Yn, n, Tn, nullptr, robust));
+    HIP_TRY(orth(c, Yn, n, n, Yn, n, Tn, nullptr, mode, false));
   }
   HIP_TRY(gemm(c, 0, f.A, f.lda, Yn, n, Zm, m, m, d, n, c.dt, c.dt, false, true));  // A Qbar
-  HIP_TRY(orth(c, Zm, m, m, f.Q, f.ldq, Tm, nullptr, robust));                  // Q
+  HIP_TRY(orth(c, Zm, m, m, f.Q, f.ldq, Tm, nullptr, mode, true));                   // Q
   HIP_TRY(gemm(c, 1, f.A, f.lda, f.Q, f.ldq, Yn, n, n, d, m, c.dt, c.dt, false, true));  // A^T Q
-  HIP_TRY(orth(c, Yn, n, n, f.P, f.ldp, Tn, Rfin, robust));                      // P, R
-  HIP_TRY(launch_lower_from_upper(Rfin, d, f.L, f.ldl, c.st));                   // L = R^T
+  HIP_TRY(orth(c, Yn, n, n, f.P, f.ldp, Tn, Rfin, mode, true));                      // P, R
+  HIP_TRY(launch_lower_from_upper(Rfin, d, f.L, f.ldl, c.st));                      // L = R^T
   return hipSuccess;
 }
 
@@ -424,31 +457,34 @@ rqlp_status randqlp_factor(const void* A, int64_t m, int64_t n, int k, int p, in
   if (s != RQLP_OK) return s;
 
   FactorArgs f{A, m, n, lda, q, Q, ldq, (double*)L, ldl, P, ldp};
-  const bool robust_first = (o.panel_qr == RQLP_PANEL_ROBUST);
-  hipError_t e = run_pipeline(c, f, robust_first);
-  if (e != hipSuccess) return fail(RQLP_E_HIP, "launch failed: %s", hipGetErrorString(e));
+  PanelMode mode = (o.panel_qr == RQLP_PANEL_ROBUST)    ? PM_ROBUST
+                   : (o.panel_qr == RQLP_PANEL_CHOLQR2) ? PM_CHOLQR2
+                                                        : PM_FAST;
   int fl[4] = {0, 0, 0, 0};
-  if ((s = read_flags(c, fl)) != RQLP_OK) return s;
   int reran = 0, breakdowns = 0;
-  if (fl[0] & FLAG_NONFINITE) {
-    int fin[4] = {0, 0, 0, 0};
-    e = hipMemsetAsync(c.flags(), 0, 64, c.st);
-    if (e == hipSuccess) e = launch_check_finite(A, m, n, lda, dt, c.flags(), c.st);
-    if (e != hipSuccess) return fail(RQLP_E_HIP, "finite check: %s", hipGetErrorString(e));
-    if ((s = read_flags(c, fin)) != RQLP_OK) return s;
-    if (fin[0] & FLAG_NONFINITE) return fail(RQLP_E_NONFINITE, "A holds NaN or Inf");
-    return fail(RQLP_E_NONFINITE, "non-finite intermediate (overflow) in the factorisation");
-  }
-  if (!robust_first && (fl[0] & (FLAG_NONPOS_PIVOT | FLAG_SECOND_PASS))) {
-    breakdowns = 1;
-    if (o.panel_qr == RQLP_PANEL_AUTO) {
-      reran = 1;
-      e = run_pipeline(c, f, true);
-      if (e != hipSuccess) return fail(RQLP_E_HIP, "launch failed: %s", hipGetErrorString(e));
-      if ((s = read_flags(c, fl)) != RQLP_OK) return s;
-      if (fl[0] & FLAG_NONFINITE)
-        return fail(RQLP_E_NONFINITE, "non-finite intermediate in the robust factorisation");
+  for (;;) {
+    hipError_t e = run_pipeline(c, f, mode);
+    if (e != hipSuccess) return fail(RQLP_E_HIP, "launch failed: %s", hipGetErrorString(e));
+    if ((s = read_flags(c, fl)) != RQLP_OK) return s;
+    if (fl[0] & FLAG_NONFINITE) {
+      int fin[4] = {0, 0, 0, 0};
+      e = hipMemsetAsync(c.flags(), 0, 64, c.st);
+      if (e == hipSuccess) e = launch_check_finite(A, m, n, lda, dt, c.flags(), c.st);
+      if (e != hipSuccess) return fail(RQLP_E_HIP, "finite check: %s", hipGetErrorString(e));
+      if ((s = read_flags(c, fin)) != RQLP_OK) return s;
+      if (fin[0] & FLAG_NONFINITE) return fail(RQLP_E_NONFINITE, "A holds NaN or Inf");
+      if (mode == PM_ROBUST)
+        return fail(RQLP_E_NONFINITE, "non-finite intermediate (overflow) in the factorisation");
     }
+    const bool pivot_bad = (fl[0] & (FLAG_NONPOS_PIVOT | FLAG_NONFINITE)) != 0;
+    const bool second_bad = (fl[0] & FLAG_SECOND_PASS) != 0;
+    if (mode == PM_ROBUST || (!pivot_bad && !second_bad)) break;
+    ++breakdowns;
+    if (o.panel_qr != RQLP_PANEL_AUTO) break;  // explicit strategy: no retry
+    // A second pass that was not accurate enough: two full passes suffice
+    // unless a pivot itself was unsafe, which needs the robust panels.
+    mode = (!pivot_bad && mode == PM_FAST) ? PM_CHOLQR2 : PM_ROBUST;
+    reran = 1;
   }
   if (o.info) {
     o.info->d = (int32_t)d;
@@ -540,21 +576,26 @@ rqlp_status randqlp_orth(const void* X, int64_t rows, int64_t d, int64_t ldx, vo
   rqlp_status s = acquire_ws(o, c.lay.total, &c.ws, lk);
   if (s != RQLP_OK) return s;
   double* Rfin = c.at<double>(c.lay.Rfin);
-  bool robust = (panel_qr == RQLP_PANEL_ROBUST);
+  PanelMode mode = (panel_qr == RQLP_PANEL_ROBUST)    ? PM_ROBUST
+                   : (panel_qr == RQLP_PANEL_CHOLQR2) ? PM_CHOLQR2
+                                                      : PM_FAST;
   int fl[4] = {0, 0, 0, 0};
-  for (int attempt = 0; attempt < 2; ++attempt) {
+  for (;;) {
     c.orth_calls = 0;
-    hipError_t e = hipMemsetAsync(c.flags(), 0, 64, c.st);
-    if (e == hipSuccess) e = orth(c, X, rows, ldx, Qx, ldq, c.ws + c.lay.m2, Rfin, robust);
+    hipError_t e = hipMemsetAsync(c.flags(), 0, c.lay.flags_bytes, c.st);
+    if (e == hipSuccess)
+      e = orth(c, X, rows, ldx, Qx, ldq, c.ws + c.lay.m2, Rfin, mode, true);
     if (e == hipSuccess && R)
       e = hipMemcpy2DAsync(R, ldr * sizeof(double), Rfin, d * sizeof(double),
                            d * sizeof(double), d, hipMemcpyDeviceToDevice, c.st);
     if (e != hipSuccess) return fail(RQLP_E_HIP, "orth: %s", hipGetErrorString(e));
     if ((s = read_flags(c, fl)) != RQLP_OK) return s;
-    if (fl[0] & FLAG_NONFINITE) return fail(RQLP_E_NONFINITE, "non-finite panel");
-    const bool bad = (fl[0] & (FLAG_NONPOS_PIVOT | FLAG_SECOND_PASS)) != 0;
-    if (robust || !bad || panel_qr != RQLP_PANEL_AUTO) break;
-    robust = true;
+    const bool pivot_bad = (fl[0] & (FLAG_NONPOS_PIVOT | FLAG_NONFINITE)) != 0;
+    const bool second_bad = (fl[0] & FLAG_SECOND_PASS) != 0;
+    if (mode == PM_ROBUST && (fl[0] & FLAG_NONFINITE))
+      return fail(RQLP_E_NONFINITE, "non-finite panel");
+    if (mode == PM_ROBUST || (!pivot_bad && !second_bad) || panel_qr != RQLP_PANEL_AUTO) break;
+    mode = (!pivot_bad && mode == PM_FAST) ? PM_CHOLQR2 : PM_ROBUST;
   }
   return RQLP_OK;
 }

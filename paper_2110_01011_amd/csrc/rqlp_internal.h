@@ -66,6 +66,7 @@ struct GemmArgs {
 hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
 size_t gemm_partial_bytes(int trans_a, int64_t M, int64_t N, int64_t K, Dtype in_t,
                           Dtype out_t, bool gram);
+int64_t gemm_tile_count(int trans_a, int64_t M, int64_t N, int64_t K, bool gram);
 
 // ---- panel.hip ----
 // Cholesky of G + shift*I (d x d, double, ldg; d <= CHOL_MAX_D) into R
@@ -82,6 +83,11 @@ hipError_t launch_cholesky(const double* G, int64_t d, int64_t ldg, double shift
 // Qx (rows x d) = X R^+ with R upper (d x d) and its diagonal-block inverses.
 hipError_t launch_trsm(const void* X, int64_t rows, int64_t d, int64_t ldx, const double* R,
                        const double* dinv, void* Qx, int64_t ldq, Dtype dt, hipStream_t st);
+// Second Cholesky QR pass to first order from G2 = Q1^T Q1 = I + E:
+// B = I - F, R2 = I + F with F = triu(E, 1) + diag(E) / 2 (d x d, tight);
+// raises FLAG_SECOND_PASS if max |E| > tol.
+hipError_t launch_first_order_pass(const double* G2, int64_t d, double tol, double* B,
+                                   double* R2, int* flags, hipStream_t st);
 // Rout = R2 * R1 (upper-triangular d x d, double, tight).
 hipError_t launch_trmm_upper(const double* R2, const double* R1, double* Rout, int64_t d,
                              hipStream_t st);

@@ -143,9 +143,10 @@ def test_bitwise_repeatable_and_prefix_property(rq):
     assert np.abs(c[1] - a[1][:10, :10]).max() < 1e-12 * a[1][0, 0]
 
 
-def test_robust_panel_mode_parity(rq):
+@pytest.mark.parametrize("panel", ["robust", "cholqr2"])
+def test_explicit_panel_modes_parity(rq, panel):
     A, U, s, V = W.fast_decay(500, 400, seed=3)
-    _check_f64(rq, A, 20, 5, 1, 2, panel="robust")
+    _check_f64(rq, A, 20, 5, 1, 2, panel=panel)
 
 
 @pytest.mark.slow
