@@ -52,10 +52,16 @@ typedef enum {
 } rqlp_status;
 
 /* Element types:
- *  RQLP_F64  A, Q, L, P double.
- *  RQLP_F32  A, Q, P float; L double.  Gram matrices and Cholesky factors
- *            are always formed in double. */
-typedef enum { RQLP_F64 = 0, RQLP_F32 = 1 } rqlp_precision;
+ *  RQLP_F64         A, Q, L, P double.
+ *  RQLP_F32         A, Q, P float; L double.
+ *  RQLP_MIXED_BF16  A, Q, P float; L double.  A is copied once to bfloat16
+ *  RQLP_MIXED_F16   (resp. half), both as A and as A^T, rounded to nearest
+ *                   even; the sketch and power-iteration products run on the
+ *                   16-bit copies with fp32 accumulation (panels rounded to
+ *                   16 bits as they are read); the final projection A^T Q
+ *                   uses the fp32 A.  Panels are fp32.
+ * In every mode the Gram matrices, Cholesky factors and R are double. */
+typedef enum { RQLP_F64 = 0, RQLP_F32 = 1, RQLP_MIXED_BF16 = 2, RQLP_MIXED_F16 = 3 } rqlp_precision;
 
 /* Panel QR used for every orth():
  *  AUTO    Cholesky QR with a second pass; if any pass reports a non-positive

@@ -13,13 +13,15 @@ import ctypes
 import os
 
 __all__ = ["factor", "gaussian", "gemm", "orth", "sketch_width", "workspace_size",
-           "colmajor", "empty_colmajor", "lib", "RandQLPError", "F64", "F32",
+           "colmajor", "empty_colmajor", "lib", "RandQLPError", "F64", "F32", "MIXED_BF16",
+           "MIXED_F16",
            "PANEL_AUTO", "PANEL_CHOLQR2", "PANEL_ROBUST"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librandqlp.so")
 
-F64, F32 = 0, 1
+F64, F32, MIXED_BF16, MIXED_F16 = 0, 1, 2, 3
+_PRECISIONS = {"f64": F64, "f32": F32, "bf16": MIXED_BF16, "f16": MIXED_F16}
 PANEL_AUTO, PANEL_CHOLQR2, PANEL_ROBUST = 0, 1, 2
 _PANELS = {"auto": PANEL_AUTO, "cholqr2": PANEL_CHOLQR2, "robust": PANEL_ROBUST}
 STATUS = {0: "RQLP_OK", 1: "RQLP_E_INVALID_ARG", 2: "RQLP_E_NONFINITE", 3: "RQLP_E_NOMEM",
@@ -168,9 +170,11 @@ def _ld(t):
     return max(1, t.stride(1)) if t.shape[1] > 1 else max(1, t.shape[0])
 
 
-def factor(A, k, p, q, seed, panel="auto", return_info=False):
+def factor(A, k, p, q, seed, panel="auto", precision=None, return_info=False):
     """Rand-QLP of a device matrix A (m x n, float64 or float32).
 
+    precision: None (from A's dtype), "f64", "f32", or the precision forms
+    "bf16" / "f16" (A float32; the products with A run on a 16-bit copy).
     Returns (Q, L, P): Q (m x d) and P (n x d) in A's dtype, L (d x d)
     float64, all column-major, with d = min(k + p, m, n).
     """
@@ -180,6 +184,11 @@ def factor(A, k, p, q, seed, panel="auto", return_info=False):
     A = colmajor(A)
     m, n = A.shape
     prec = _precision(A.dtype)
+    if precision is not None:
+        prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        if (prec == F64) != (A.dtype == torch.float64):
+            raise TypeError("precision does not match A's dtype (f64 needs float64, "
+                            "f32/bf16/f16 need float32)")
     d = sketch_width(m, n, k, p)
     if d < 1:
         _check(lib().randqlp_factor(None, m, n, k, p, q, seed, None, None, None, None))

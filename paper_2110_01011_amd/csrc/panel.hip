@@ -123,7 +123,8 @@ __device__ __forceinline__ void factor_diag_tile(double (*dg)[17], double (*dgi)
 // diagonal tile to the factor wave, and finally writes its part of R.
 __device__ __forceinline__ void chol_tile_wave(
     const double* __restrict__ G, int d, int64_t ldg, double sh, double (*dg)[17],
-    double (*dgi)[17], double (*pan)[17], int* ready, int wave, double* __restrict__ R) {
+    double (*dgi)[17], double (*pan)[17], int* ready, int wave, double* __restrict__ R,
+    int64_t ldr) {
   const int lane = threadIdx.x & 63;
   const int nt = (d + 15) / 16;
   const int T = nt * (nt + 1) / 2;
@@ -243,8 +244,8 @@ __device__ __forceinline__ void chol_tile_wave(
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * I + acc_row_f64(lane, r);
       if (row < d && col < d) {
-        R[col + (int64_t)row * d] = acc[s][r];
-        if (I > Jt) R[row + (int64_t)col * d] = 0.0;
+        R[col + (int64_t)row * ldr] = acc[s][r];
+        if (I > Jt) R[row + (int64_t)col * ldr] = 0.0;
       }
     }
   }
@@ -258,8 +259,9 @@ __device__ __forceinline__ void chol_tile_wave(
 __global__ __launch_bounds__(512) void cholesky_kernel(
     const double* __restrict__ G, int d, int64_t ldg, double shift,
     const double* __restrict__ shift_dev, double tol_dep, double tol_warn,
-    double* __restrict__ R, double* __restrict__ dinv, int* __restrict__ col_flags,
-    int* __restrict__ flags) {
+    double* __restrict__ R, int64_t ldr, double* __restrict__ dinv,
+    int* __restrict__ col_flags, int* __restrict__ flags,
+    const double* __restrict__ odiag_src, int64_t odiag_stride) {
   __shared__ double dg[16][17];
   __shared__ double dgi[16][17];
   __shared__ double invd[16];
@@ -272,8 +274,12 @@ __global__ __launch_bounds__(512) void cholesky_kernel(
   const int tid = threadIdx.x;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const double sh = (shift_dev != nullptr) ? *shift_dev : shift;
+  // Pivots are judged against the original diagonal (of the whole matrix
+  // when this call factors a trailing Schur complement).
   for (int j = tid; j < CHOL_MAX_D; j += blockDim.x)
-    odiag[j] = (j < d) ? G[j + (int64_t)j * ldg] + sh : 1.0;
+    odiag[j] = (j >= d) ? 1.0
+               : (odiag_src ? odiag_src[(int64_t)j * odiag_stride] + sh
+                            : G[j + (int64_t)j * ldg] + sh);
   if (tid == 0) {
     sflag = 0;
     ready = -1;
@@ -295,7 +301,7 @@ __global__ __launch_bounds__(512) void cholesky_kernel(
       __syncthreads();
     }
   } else {
-    chol_tile_wave(G, d, ldg, sh, dg, dgi, pan, &ready, wave, R);
+    chol_tile_wave(G, d, ldg, sh, dg, dgi, pan, &ready, wave, R, ldr);
   }
   __syncthreads();
   if (tid == 0 && sflag) atomicOr(flags, sflag);
@@ -312,7 +318,7 @@ __global__ __launch_bounds__(512) void cholesky_kernel(
 // overwriting it).
 template <typename TX, typename TO>
 __global__ __launch_bounds__(64) void trsm_kernel(const TX* X, int64_t rows, int d, int64_t ldx,
-                                                  const double* __restrict__ R,
+                                                  const double* __restrict__ R, int64_t ldr,
                                                   const double* __restrict__ dinv, TO* Qx,
                                                   int64_t ldq) {
   extern __shared__ double Qw[];
@@ -325,7 +331,7 @@ __global__ __launch_bounds__(64) void trsm_kernel(const TX* X, int64_t rows, int
     const int kk = 16 * J;
     const int colR = kk + li;
     const bool colok = colR < d;
-    const double* Rc = R + (int64_t)(colok ? colR : 0) * d + lk;
+    const double* Rc = R + (int64_t)(colok ? colR : 0) * ldr + lk;
     const int nk = 4 * J;
     double bc[B], bn[B];
 #pragma unroll
@@ -403,6 +409,36 @@ __global__ __launch_bounds__(256) void first_order_pass_kernel(const double* __r
   B[idx] = (i == j ? 1.0 : 0.0) - f;
   R2[idx] = (i == j ? 1.0 : 0.0) + f;
   if (!(fabs(e) <= tol)) atomicOr(flags, FLAG_SECOND_PASS);
+}
+
+// T (cols x rows, ldt) = S^T for S (rows x cols, lds).
+__global__ __launch_bounds__(256) void transpose_kernel(const double* __restrict__ S, int64_t rows,
+                                                        int64_t cols, int64_t lds,
+                                                        double* __restrict__ T, int64_t ldt) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t i = idx % rows, j = idx / rows;
+  T[j + i * ldt] = S[i + j * lds];
+}
+
+// S (n x n, tight) = G22 (+ shift on the diagonal) - C, and the zero block
+// Z (n rows x m cols, ldz) below a factored leading block.
+__global__ __launch_bounds__(256) void schur_kernel(const double* __restrict__ G22, int64_t ldg,
+                                                    const double* __restrict__ C, int64_t n,
+                                                    double shift, const double* shift_dev,
+                                                    double* __restrict__ S) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n) return;
+  const int64_t i = idx % n, j = idx / n;
+  const double sh = shift_dev ? *shift_dev : shift;
+  S[idx] = G22[i + j * ldg] + (i == j ? sh : 0.0) - C[idx];
+}
+
+__global__ __launch_bounds__(256) void zero_block_kernel(double* __restrict__ Z, int64_t rows,
+                                                         int64_t cols, int64_t ldz) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  Z[idx % rows + (idx / rows) * ldz] = 0.0;
 }
 
 __global__ __launch_bounds__(256) void trmm_upper_kernel(const double* __restrict__ R2,
@@ -485,34 +521,60 @@ inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace
 
-hipError_t launch_cholesky(const double* G, int64_t d, int64_t ldg, double shift,
-                           const double* shift_dev, double tol_dep, double tol_warn,
-                           double* R, double* dinv, int* col_flags, int* flags,
-                           hipStream_t st) {
+hipError_t launch_cholesky_tile(const double* G, int64_t d, int64_t ldg, double shift,
+                                const double* shift_dev, double tol_dep, double tol_warn,
+                                double* R, int64_t ldr, double* dinv, int* col_flags,
+                                int* flags, const double* odiag_src, int64_t odiag_stride,
+                                hipStream_t st) {
   if (d > CHOL_MAX_D) return hipErrorInvalidValue;
   hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(512), 0, st, G, (int)d, ldg, shift,
-                     shift_dev, tol_dep, tol_warn, R, dinv, col_flags, flags);
+                     shift_dev, tol_dep, tol_warn, R, ldr, dinv, col_flags, flags, odiag_src,
+                     odiag_stride);
+  return hipGetLastError();
+}
+
+hipError_t launch_transpose(const double* S, int64_t rows, int64_t cols, int64_t lds, double* T,
+                            int64_t ldt, hipStream_t st) {
+  if (rows * cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(transpose_kernel, dim3(grid_for(rows * cols)), dim3(256), 0, st, S, rows,
+                     cols, lds, T, ldt);
+  return hipGetLastError();
+}
+
+hipError_t launch_schur(const double* G22, int64_t ldg, const double* C, int64_t n, double shift,
+                        const double* shift_dev, double* S, hipStream_t st) {
+  hipLaunchKernelGGL(schur_kernel, dim3(grid_for(n * n)), dim3(256), 0, st, G22, ldg, C, n,
+                     shift, shift_dev, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_block(double* Z, int64_t rows, int64_t cols, int64_t ldz, hipStream_t st) {
+  if (rows * cols <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_block_kernel, dim3(grid_for(rows * cols)), dim3(256), 0, st, Z, rows,
+                     cols, ldz);
   return hipGetLastError();
 }
 
 template <typename TX, typename TO>
 static hipError_t trsm_typed(const void* X, int64_t rows, int64_t d, int64_t ldx,
-                             const double* R, const double* dinv, void* Qx, int64_t ldq,
-                             hipStream_t st) {
+                             const double* R, int64_t ldr, const double* dinv, void* Qx,
+                             int64_t ldq, hipStream_t st) {
   const int nt = (int)((d + 15) / 16), dp = nt * 16;
   const size_t lds = sizeof(double) * (size_t)16 * (dp + 1);
   const int64_t blocks = (rows + 15) / 16;
   hipLaunchKernelGGL((trsm_kernel<TX, TO>), dim3((unsigned)blocks), dim3(64), lds, st,
-                     (const TX*)X, rows, (int)d, ldx, R, dinv, (TO*)Qx, ldq);
+                     (const TX*)X, rows, (int)d, ldx, R, ldr, dinv, (TO*)Qx, ldq);
   return hipGetLastError();
 }
 
 hipError_t launch_trsm(const void* X, int64_t rows, int64_t d, int64_t ldx, const double* R,
-                       const double* dinv, void* Qx, int64_t ldq, Dtype dt, hipStream_t st) {
-  if (d > CHOL_MAX_D) return hipErrorInvalidValue;
+                       int64_t ldr, const double* dinv, void* Qx, int64_t ldq, Dtype dt,
+                       hipStream_t st) {
+  if (d > TRSM_MAX_D) return hipErrorInvalidValue;
   if (rows <= 0 || d <= 0) return hipSuccess;
-  if (dt == DT_F64) return trsm_typed<double, double>(X, rows, d, ldx, R, dinv, Qx, ldq, st);
-  return trsm_typed<float, float>(X, rows, d, ldx, R, dinv, Qx, ldq, st);
+  if (dt == DT_F64)
+    return trsm_typed<double, double>(X, rows, d, ldx, R, ldr, dinv, Qx, ldq, st);
+  return trsm_typed<float, float>(X, rows, d, ldx, R, ldr, dinv, Qx, ldq, st);
 }
 
 hipError_t launch_first_order_pass(const double* G2, int64_t d, double tol, double* B,

@@ -61,13 +61,14 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
   size_t m1, m2, n1, n2, part, part_bytes, G, R[4], Racc[2], Rfin, dinv, colf, scal, flags,
-      total;
+      chs, a16, at16, total;
+  int64_t ld16, ldt16;  // leading dimensions of the 16-bit copies of A and A^T
   size_t flags_bytes;  // status words cleared at the start of a call
 };
 
 size_t elem_size(Dtype dt) { return dt == DT_F64 ? 8 : 4; }
 
-Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt) {
+Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false) {
   Layout L;
   const size_t es = elem_size(dt);
   size_t off = 0;
@@ -85,14 +86,31 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt) {
   part = std::max(part, gemm_partial_bytes(0, m, d, n, dt, dt, false));
   part = std::max(part, gemm_partial_bytes(1, d, d, m, dt, DT_F64, true));
   part = std::max(part, gemm_partial_bytes(1, d, d, n, dt, DT_F64, true));
+  for (int64_t dd = d; dd > CHOL_MAX_D; dd -= CHOL_MAX_D)  // Schur-complement Grams
+    part = std::max(part, gemm_partial_bytes(1, dd - CHOL_MAX_D, dd - CHOL_MAX_D, CHOL_MAX_D,
+                                             DT_F64, DT_F64, true));
+  if (mixed) {
+    part = std::max(part, gemm16_partial_bytes(n, d, m));
+    part = std::max(part, gemm16_partial_bytes(m, d, n));
+  }
   L.part = take(part);
   L.part_bytes = part;
   L.G = take((size_t)d * d * 8);
   for (int i = 0; i < 4; ++i) L.R[i] = take((size_t)d * d * 8);
   for (int i = 0; i < 2; ++i) L.Racc[i] = take((size_t)d * d * 8);
   L.Rfin = take((size_t)d * d * 8);
+  L.chs = take((size_t)4 * d * d * 8);  // blocked Cholesky: off-diagonal solve + Schur blocks
   L.dinv = take((size_t)((d + 15) / 16) * 256 * 8);
   L.colf = take((size_t)d * 4);
+  if (mixed) {
+    L.ld16 = (m + 7) / 8 * 8;
+    L.ldt16 = (n + 7) / 8 * 8;
+    L.a16 = take((size_t)L.ld16 * n * 2);
+    L.at16 = take((size_t)L.ldt16 * m * 2);
+  } else {
+    L.ld16 = L.ldt16 = 0;
+    L.a16 = L.at16 = 0;
+  }
   L.scal = take(64);
   L.flags = take(64);
   L.flags_bytes = 64;
@@ -111,6 +129,7 @@ WsCache g_ws;
 struct Ctx {
   hipStream_t st;
   Dtype dt;
+  int mixed = 0;  // 0: no; 1: bf16 products; 2: fp16 products
   char* ws;
   Layout lay;
   int64_t d;
@@ -186,6 +205,73 @@ hipError_t gemm(Ctx& c, int trans_a, const void* A, int64_t lda, const void* B, 
   return launch_gemm(g, c.st);
 }
 
+// Precision-form product C (rows x d, fp32) = op(A) X on the 16-bit copies:
+// trans_a = 1 uses A16 (C = A^T X, rows = n, K = m), trans_a = 0 uses the
+// copy of A^T (C = A X, rows = m, K = n).
+hipError_t gemm16(Ctx& c, int trans_a, int64_t m, int64_t n, const float* X, int64_t ldx,
+                  float* C, int64_t ldc, int64_t d) {
+  Gemm16Args g;
+  g.f16 = (c.mixed == 2);
+  g.A = trans_a ? (const void*)(c.ws + c.lay.a16) : (const void*)(c.ws + c.lay.at16);
+  g.lda = trans_a ? c.lay.ld16 : c.lay.ldt16;
+  g.B = X;
+  g.ldb = ldx;
+  g.C = C;
+  g.ldc = ldc;
+  g.M = trans_a ? n : m;
+  g.N = d;
+  g.K = trans_a ? m : n;
+  g.partial = c.ws + c.lay.part;
+  g.partial_bytes = c.lay.part_bytes;
+  if (g_prof.on) {
+    const size_t i = g_prof.used++;
+    while (g_prof.ev.size() < 2 * g_prof.used) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
+      g_prof.ev.push_back(e);
+    }
+    g_prof.work_flops.resize(g_prof.used);
+    g_prof.work_bytes.resize(g_prof.used);
+    g_prof.work_flops[i] = 2.0 * (double)g.M * (double)g.N * (double)g.K;
+    g_prof.work_bytes[i] = 2.0 * (double)g.M * g.K + 4.0 * ((double)g.K * g.N + (double)g.M * g.N);
+    g.ev_begin = g_prof.ev[2 * i];
+    g.ev_end = g_prof.ev[2 * i + 1];
+  }
+  return launch_gemm16(g, c.st);
+}
+
+// Cholesky of G + shift I for any d <= RQLP_MAX_D into R (ldr) and the
+// diagonal-block inverses.  Blocked right-looking: the leading CHOL_MAX_D
+// columns on the one-workgroup kernel; R12 = R11^{-T} G12, computed as the
+// TRSM of G21 = G12^T; the Schur complement G22 - R12^T R12 through the Gram
+// product; then the same on the complement.  Pivot tolerances stay relative
+// to the original diagonal.  scratch holds 4 d^2 doubles.
+hipError_t chol_any(Ctx& c, const double* G, int64_t d, int64_t ldg, double shift,
+                    const double* shift_dev, double tol_dep, double tol_warn, double* R,
+                    int64_t ldr, double* dinv, int* col_flags, const double* odiag_src,
+                    int64_t odiag_stride, double* scratch) {
+  if (d <= CHOL_MAX_D)
+    return launch_cholesky_tile(G, d, ldg, shift, shift_dev, tol_dep, tol_warn, R, ldr, dinv,
+                                col_flags, c.flags(), odiag_src, odiag_stride, c.st);
+  const int64_t d1 = CHOL_MAX_D, d2 = d - d1;
+  HIP_TRY(launch_cholesky_tile(G, d1, ldg, shift, shift_dev, tol_dep, tol_warn, R, ldr, dinv,
+                               col_flags, c.flags(), odiag_src, odiag_stride, c.st));
+  double* Xs = scratch;          // G21 R11^{-1} = R12^T, d2 x d1
+  double* C = Xs + d2 * d1;      // R12^T R12, d2 x d2
+  double* S = C + d2 * d2;       // Schur complement, d2 x d2
+  HIP_TRY(launch_trsm(G + d1, d2, d1, ldg, R, ldr, dinv, Xs, d2, DT_F64, c.st));
+  double* R12 = R + d1 * ldr;
+  HIP_TRY(launch_transpose(Xs, d2, d1, d2, R12, ldr, c.st));
+  HIP_TRY(launch_zero_block(R + d1, d2, d1, ldr, c.st));
+  HIP_TRY(gemm(c, 1, R12, ldr, R12, ldr, C, d2, d2, d2, d1, DT_F64, DT_F64, true));
+  HIP_TRY(launch_schur(G + d1 + d1 * ldg, ldg, C, d2, shift, shift_dev, S, c.st));
+  const double* od = odiag_src ? odiag_src + d1 * odiag_stride : G + d1 + d1 * ldg;
+  const int64_t ods = odiag_src ? odiag_stride : ldg + 1;
+  return chol_any(c, S, d2, d2, 0.0, nullptr, tol_dep, tol_warn, R + d1 + d1 * ldr, ldr,
+                  dinv + (d1 / 16) * 256, col_flags ? col_flags + d1 : nullptr, od, ods,
+                  S + d2 * d2);
+}
+
 // One Cholesky QR pass: X (rows x d) -> Qx = X R^+, R into Rbuf.
 hipError_t chol_pass(Ctx& c, const void* X, int64_t rows, int64_t ldx, void* Qx, int64_t ldq,
                      double* Rbuf, const double* shift_dev, double tol_dep, double tol_warn,
@@ -194,9 +280,9 @@ hipError_t chol_pass(Ctx& c, const void* X, int64_t rows, int64_t ldx, void* Qx,
   double* G = c.at<double>(c.lay.G);
   double* dinv = c.at<double>(c.lay.dinv);
   HIP_TRY(gemm(c, 1, X, ldx, X, ldx, G, d, d, d, rows, c.dt, DT_F64, true));
-  HIP_TRY(launch_cholesky(G, d, d, 0.0, shift_dev, tol_dep, tol_warn, Rbuf, dinv, col_flags,
-                          c.flags(), c.st));
-  return launch_trsm(X, rows, d, ldx, Rbuf, dinv, Qx, ldq, c.dt, c.st);
+  HIP_TRY(chol_any(c, G, d, d, 0.0, shift_dev, tol_dep, tol_warn, Rbuf, d, dinv, col_flags,
+                   nullptr, 0, c.at<double>(c.lay.chs)));
+  return launch_trsm(X, rows, d, ldx, Rbuf, d, dinv, Qx, ldq, c.dt, c.st);
 }
 
 // Panel QR strategies, cheapest first.
@@ -255,9 +341,9 @@ hipError_t orth(Ctx& c, const void* X, int64_t rows, int64_t ldx, void* out, int
   const double cshift = 11.0 * ((double)rows * d + (double)d * (d + 1)) * kUnit;
   HIP_TRY(launch_scale_scalar(scal, cshift, scal + 1, c.st));
   double* dinv = c.at<double>(c.lay.dinv);
-  HIP_TRY(launch_cholesky(G, d, d, 0.0, scal + 1, 0.0, 0.0, R[0], dinv, nullptr, c.flags(),
-                          c.st));
-  HIP_TRY(launch_trsm(X, rows, d, ldx, R[0], dinv, tmp, rows, c.dt, c.st));
+  HIP_TRY(chol_any(c, G, d, d, 0.0, scal + 1, 0.0, 0.0, R[0], d, dinv, nullptr, nullptr, 0,
+                   c.at<double>(c.lay.chs)));
+  HIP_TRY(launch_trsm(X, rows, d, ldx, R[0], d, dinv, tmp, rows, c.dt, c.st));
   // pass 2: detect dependent columns (zeroed), then complete them
   HIP_TRY(chol_pass(c, tmp, rows, rows, out, ldo, R[1], nullptr, kTolDepRobust, 0.0, colf));
   HIP_TRY(launch_count_flags(colf, d, c.flags() + 2, c.st));
@@ -288,7 +374,38 @@ struct FactorArgs {
   int64_t ldp;
 };
 
+// Precision form of the pipeline: products with A on the 16-bit copies,
+// final projection in fp32.
+hipError_t run_pipeline_mixed(Ctx& c, const FactorArgs& f, PanelMode mode) {
+  const int64_t m = f.m, n = f.n, d = c.d;
+  float* Zm = c.at<float>(c.lay.m1);
+  void* Tm = c.ws + c.lay.m2;
+  float* Yn = c.at<float>(c.lay.n1);
+  void* Tn = c.ws + c.lay.n2;
+  double* Rfin = c.at<double>(c.lay.Rfin);
+  c.orth_calls = 0;
+  HIP_TRY(hipMemsetAsync(c.flags(), 0, c.lay.flags_bytes, c.st));
+  HIP_TRY(launch_convert16((const float*)f.A, m, n, f.lda, c.ws + c.lay.a16, c.lay.ld16,
+                           c.ws + c.lay.at16, c.lay.ldt16, c.mixed == 2, c.st));
+  HIP_TRY(launch_gaussian(Zm, m, d, m, c.seed, 0, DT_F32, c.st));             // randn
+  HIP_TRY(gemm16(c, 1, m, n, Zm, m, Yn, n, d));                                // A^T Omega
+  HIP_TRY(orth(c, Yn, n, n, Yn, n, Tn, nullptr, mode, false));
+  for (int it = 0; it < f.q; ++it) {
+    HIP_TRY(gemm16(c, 0, m, n, Yn, n, Zm, m, d));                              // A Qbar
+    HIP_TRY(orth(c, Zm, m, m, Zm, m, Tm, nullptr, mode, false));
+    HIP_TRY(gemm16(c, 1, m, n, Zm, m, Yn, n, d));                              // A^T Q
+    HIP_TRY(orth(c, Yn, n, n, Yn, n, Tn, nullptr, mode, false));
+  }
+  HIP_TRY(gemm16(c, 0, m, n, Yn, n, Zm, m, d));                                // A Qbar
+  HIP_TRY(orth(c, Zm, m, m, f.Q, f.ldq, Tm, nullptr, mode, true));             // Q
+  HIP_TRY(gemm(c, 1, f.A, f.lda, f.Q, f.ldq, Yn, n, n, d, m, DT_F32, DT_F32, false, true));
+  HIP_TRY(orth(c, Yn, n, n, f.P, f.ldp, Tn, Rfin, mode, true));                // P, R
+  HIP_TRY(launch_lower_from_upper(Rfin, d, f.L, f.ldl, c.st));                // L = R^T
+  return hipSuccess;
+}
+
 hipError_t run_pipeline(Ctx& c, const FactorArgs& f, PanelMode mode) {
+  if (c.mixed) return run_pipeline_mixed(c, f, mode);
   const int64_t m = f.m, n = f.n, d = c.d;
   void* Zm = c.ws + c.lay.m1;
   void* Tm = c.ws + c.lay.m2;
@@ -366,8 +483,8 @@ size_t randqlp_workspace_size(int64_t m, int64_t n, int k, int p, int q, const r
   const int64_t d = randqlp_sketch_width(m, n, k, p);
   if (d < 1 || q < 0) return 0;
   const int prec = o ? o->precision : RQLP_F64;
-  if (prec != RQLP_F64 && prec != RQLP_F32) return 0;
-  return make_layout(m, n, d, prec == RQLP_F64 ? DT_F64 : DT_F32).total;
+  if (prec < RQLP_F64 || prec > RQLP_MIXED_F16) return 0;
+  return make_layout(m, n, d, prec == RQLP_F64 ? DT_F64 : DT_F32, prec >= RQLP_MIXED_BF16).total;
 }
 
 }  // extern "C"
@@ -432,7 +549,7 @@ rqlp_status randqlp_factor(const void* A, int64_t m, int64_t n, int k, int p, in
   if (p < 0) return fail(RQLP_E_INVALID_ARG, "p = %d must be >= 0", p);
   if (q < 0) return fail(RQLP_E_INVALID_ARG, "q = %d must be >= 0", q);
   if (!A || !Q || !L || !P) return fail(RQLP_E_INVALID_ARG, "null matrix pointer");
-  if (o.precision != RQLP_F64 && o.precision != RQLP_F32)
+  if (o.precision < RQLP_F64 || o.precision > RQLP_MIXED_F16)
     return fail(RQLP_E_INVALID_ARG, "unknown precision %d", o.precision);
   if (o.panel_qr < RQLP_PANEL_AUTO || o.panel_qr > RQLP_PANEL_ROBUST)
     return fail(RQLP_E_INVALID_ARG, "unknown panel_qr %d", o.panel_qr);
@@ -441,14 +558,16 @@ rqlp_status randqlp_factor(const void* A, int64_t m, int64_t n, int k, int p, in
   const int64_t ldl = o.ldl ? o.ldl : d, ldp = o.ldp ? o.ldp : n;
   if (lda < m || ldq < m || ldl < d || ldp < n)
     return fail(RQLP_E_INVALID_ARG, "leading dimension smaller than the row count");
-  if (d > CHOL_MAX_D)
-    return fail(RQLP_E_UNSUPPORTED, "sketch width d = %lld exceeds %d", (long long)d, CHOL_MAX_D);
+  if (d > RQLP_MAX_D)
+    return fail(RQLP_E_UNSUPPORTED, "sketch width d = %lld exceeds %d", (long long)d, RQLP_MAX_D);
   const Dtype dt = (o.precision == RQLP_F64) ? DT_F64 : DT_F32;
+  const int mixed = (o.precision == RQLP_MIXED_BF16) ? 1 : (o.precision == RQLP_MIXED_F16) ? 2 : 0;
 
   Ctx c;
   c.st = (hipStream_t)o.stream;
   c.dt = dt;
-  c.lay = make_layout(m, n, d, dt);
+  c.mixed = mixed;
+  c.lay = make_layout(m, n, d, dt, mixed != 0);
   c.d = d;
   c.seed = seed;
   c.orth_calls = 0;
@@ -559,8 +678,8 @@ rqlp_status randqlp_orth(const void* X, int64_t rows, int64_t d, int64_t ldx, vo
     return fail(RQLP_E_INVALID_ARG, "unknown precision %d", precision);
   if (panel_qr < RQLP_PANEL_AUTO || panel_qr > RQLP_PANEL_ROBUST)
     return fail(RQLP_E_INVALID_ARG, "unknown panel_qr %d", panel_qr);
-  if (d > CHOL_MAX_D)
-    return fail(RQLP_E_UNSUPPORTED, "d = %lld exceeds %d", (long long)d, CHOL_MAX_D);
+  if (d > RQLP_MAX_D)
+    return fail(RQLP_E_UNSUPPORTED, "d = %lld exceeds %d", (long long)d, RQLP_MAX_D);
   const Dtype dt = precision == RQLP_F64 ? DT_F64 : DT_F32;
   Ctx c;
   c.st = (hipStream_t)stream;

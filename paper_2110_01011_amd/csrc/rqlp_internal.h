@@ -33,7 +33,9 @@ enum : int {
 // Element type tags for the launchers.
 enum Dtype : int { DT_F64 = 0, DT_F32 = 1 };
 
-constexpr int CHOL_MAX_D = 224;  // single-workgroup Cholesky limit (14 x 14 tiles of 16)
+constexpr int CHOL_MAX_D = 224;   // single-workgroup Cholesky tile limit (14 x 14 tiles of 16)
+constexpr int TRSM_MAX_D = 1024;  // TRSM keeps a 16 x d panel per wave in LDS
+constexpr int RQLP_MAX_D = 1024;  // largest sketch width (blocked Cholesky above CHOL_MAX_D)
 
 // ---- philox.hip ----
 hipError_t launch_gaussian(void* out, int64_t m, int64_t d, int64_t ld, uint64_t seed,
@@ -68,21 +70,53 @@ size_t gemm_partial_bytes(int trans_a, int64_t M, int64_t N, int64_t K, Dtype in
                           Dtype out_t, bool gram);
 int64_t gemm_tile_count(int trans_a, int64_t M, int64_t N, int64_t K, bool gram);
 
+// Precision form: C (M x N fp32) = A16^T X, A16 a 16-bit matrix with the
+// contraction index contiguous (A16[k + i*lda]), X fp32 (X[k + j*ldb]) rounded
+// to 16 bits on load; split-K partials in `partial` (fixed-order reduction).
+struct Gemm16Args {
+  bool f16;  // false: bf16, true: fp16
+  const void* A; int64_t lda;
+  const float* B; int64_t ldb;
+  float* C; int64_t ldc;
+  int64_t M, N, K;
+  void* partial;
+  size_t partial_bytes;
+  void* ev_begin = nullptr;
+  void* ev_end = nullptr;
+};
+hipError_t launch_gemm16(const Gemm16Args& g, hipStream_t st);
+size_t gemm16_partial_bytes(int64_t M, int64_t N, int64_t K);
+// A (m x n fp32) -> A16 (m x n, ld16) and At16 = A^T (n x m, ldt16), 16-bit.
+hipError_t launch_convert16(const float* A, int64_t m, int64_t n, int64_t lda, void* A16,
+                            int64_t ld16, void* At16, int64_t ldt16, bool f16, hipStream_t st);
+
 // ---- panel.hip ----
-// Cholesky of G + shift*I (d x d, double, ldg; d <= CHOL_MAX_D) into R
-// (upper, d x d, double, tight) and the inverses of its 16 x 16 diagonal
-// blocks (dinv, ceil(d/16)*256 doubles, each block column-major).  The shift
-// is *shift_dev when shift_dev is non-null, else `shift`.  A pivot <= tol_dep
-// * (original diagonal) marks its column dependent: that row of R is zeroed,
-// col_flags[j] = 1 (col_flags may be null) and FLAG_NONPOS_PIVOT is raised.
-// A kept pivot below tol_warn * (original diagonal) raises FLAG_SECOND_PASS.
-hipError_t launch_cholesky(const double* G, int64_t d, int64_t ldg, double shift,
-                           const double* shift_dev, double tol_dep, double tol_warn,
-                           double* R, double* dinv, int* col_flags, int* flags,
-                           hipStream_t st);
-// Qx (rows x d) = X R^+ with R upper (d x d) and its diagonal-block inverses.
+// One-workgroup Cholesky of G + shift*I (d x d, double, ldg; d <= CHOL_MAX_D)
+// into R (upper, ldr) and the inverses of its 16 x 16 diagonal blocks (dinv,
+// ceil(d/16)*256 doubles, each block column-major).  The shift is *shift_dev
+// when shift_dev is non-null, else `shift`.  A pivot <= tol_dep * (original
+// diagonal) marks its column dependent: that row of R is zeroed,
+// col_flags[j] = 1 (col_flags may be null) and FLAG_NONPOS_PIVOT is raised;
+// a kept pivot below tol_warn * (original diagonal) raises FLAG_SECOND_PASS.
+// The original diagonal is odiag_src[j * odiag_stride] + shift when
+// odiag_src is given (trailing Schur complements), else G's own diagonal.
+hipError_t launch_cholesky_tile(const double* G, int64_t d, int64_t ldg, double shift,
+                                const double* shift_dev, double tol_dep, double tol_warn,
+                                double* R, int64_t ldr, double* dinv, int* col_flags,
+                                int* flags, const double* odiag_src, int64_t odiag_stride,
+                                hipStream_t st);
+// T (cols x rows, ldt) = S^T.
+hipError_t launch_transpose(const double* S, int64_t rows, int64_t cols, int64_t lds, double* T,
+                            int64_t ldt, hipStream_t st);
+// S (n x n, tight) = G22 (+ shift I) - C (n x n, tight).
+hipError_t launch_schur(const double* G22, int64_t ldg, const double* C, int64_t n, double shift,
+                        const double* shift_dev, double* S, hipStream_t st);
+hipError_t launch_zero_block(double* Z, int64_t rows, int64_t cols, int64_t ldz, hipStream_t st);
+// Qx (rows x d) = X R^+ with R upper (d x d, ldr) and its diagonal-block
+// inverses; Qx may be X itself (same ld).
 hipError_t launch_trsm(const void* X, int64_t rows, int64_t d, int64_t ldx, const double* R,
-                       const double* dinv, void* Qx, int64_t ldq, Dtype dt, hipStream_t st);
+                       int64_t ldr, const double* dinv, void* Qx, int64_t ldq, Dtype dt,
+                       hipStream_t st);
 // Second Cholesky QR pass to first order from G2 = Q1^T Q1 = I + E:
 // B = I - F, R2 = I + F with F = triu(E, 1) + diag(E) / 2 (d x d, tight);
 // raises FLAG_SECOND_PASS if max |E| > tol.

@@ -23,10 +23,11 @@ def rq():
     return rq
 
 
-def _run(rq, A, k, p, q, seed, dtype=None, panel="auto"):
+def _run(rq, A, k, p, q, seed, dtype=None, panel="auto", precision=None):
     import torch
     dt = dtype or torch.float64
-    Q, L, P, info = rq.factor(to_dev(A, dt), k, p, q, seed, panel=panel, return_info=True)
+    Q, L, P, info = rq.factor(to_dev(A, dt), k, p, q, seed, panel=panel, precision=precision,
+                              return_info=True)
     return to_np(Q), to_np(L), to_np(P), info
 
 
@@ -147,6 +148,35 @@ def test_bitwise_repeatable_and_prefix_property(rq):
 def test_explicit_panel_modes_parity(rq, panel):
     A, U, s, V = W.fast_decay(500, 400, seed=3)
     _check_f64(rq, A, 20, 5, 1, 2, panel=panel)
+
+
+@pytest.fixture(scope="module")
+def exp_decay_matrix():
+    """The precision-form workload's family at 1/4 scale: sigma_i = exp(-i/100)."""
+    return W.exp_decay(5000, 4000, 1000, 100.0, seed=3)
+
+
+def test_wide_sketch_blocked_cholesky_parity(rq, exp_decay_matrix):
+    """d = 520 > 224 exercises the blocked Cholesky (tile kernel + Schur steps)."""
+    log("factor exp-decay 5000x4000 k=500 p=20 q=2 (d=520) fp64")
+    A, U, s, V = exp_decay_matrix
+    _check_f64(rq, A, 500, 20, 2, seed=1)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "f16"])
+def test_precision_form_error_within_5_percent(rq, exp_decay_matrix, precision):
+    import torch
+    log(f"factor exp-decay 5000x4000 d=520 precision={precision}")
+    A, U, s, V = exp_decay_matrix
+    Qo, Lo, Po = randqlp(A, 500, 20, 2, 1)
+    e_o = rel_error(A, Qo, Lo, Po)
+    Qg, Lg, Pg, info = _run(rq, A, 500, 20, 2, 1, dtype=torch.float32, precision=precision)
+    e_g = rel_error(A, Qg, Lg, Pg)
+    inv = invariants(A, Qg, Lg, Pg)
+    log(f"  e_gpu={e_g:.6e} e_orc={e_o:.6e} ratio={e_g / e_o:.5f} {inv} {info}")
+    assert e_g <= 1.05 * e_o
+    assert inv["orthQ"] < 1e-5 and inv["orthP"] < 1e-5
+    assert inv["upper_max"] == 0.0 and inv["min_diag"] >= 0.0
 
 
 @pytest.mark.slow

@@ -80,7 +80,8 @@ def _panel(rows, d, kappa, seed):
 
 
 @pytest.mark.parametrize("rows,d,kappa", [(1000, 25, 10.0), (8000, 210, 5e3), (333, 17, 1e6),
-                                          (500, 224, 1e2), (16, 16, 3.0), (20, 1, 1.0)])
+                                          (500, 224, 1e2), (16, 16, 3.0), (20, 1, 1.0),
+                                          (3000, 300, 1e3), (4000, 520, 1e2), (1200, 449, 10.0)])
 def test_orth_f64_matches_lapack(rq, rows, d, kappa):
     log(f"orth f64 rows={rows} d={d} kappa={kappa}")
     X = _panel(rows, d, kappa, rows + d)
