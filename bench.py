@@ -12,6 +12,7 @@ kernel that streams A, timed with HIP events on its stream) and the fp64 CPU
 oracle timed on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -27,7 +28,54 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(A, k, p, q, flops, budget_s=12.0, max_reps=4):
+# Sources of the product kernel: a traffic measurement is only reported
+# while they are unchanged since the counters were taken.
+KERNEL_SOURCES = ["paper_2110_01011_amd/csrc/gemm.hip", "paper_2110_01011_amd/csrc/rqlp_internal.h"]
+
+
+def kernel_source_sha():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def read_traffic(path):
+    """HBM bytes per product launch from a counter summary (key: value lines),
+    or None when it is missing or taken on other kernel sources."""
+    full = os.path.join(ROOT, path)
+    if not os.path.exists(full):
+        return None
+    kv = {}
+    with open(full) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib):
+    """A plain device copy of known size (for scaling the HBM byte counters)."""
+    import torch
+    nbytes = mib << 20
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 copies of {nbytes} bytes (read {nbytes}, write {nbytes} each)")
+    del src, dst
+
+
+def cpu_baseline(A, k, p, q, flops, budget_s=15.0, max_reps=40):
     """The fp64 oracle on the host cores, on whole factorisations of A."""
     from threadpoolctl import threadpool_info
     from oracle import randqlp, rel_error
@@ -55,6 +103,8 @@ def main():
     ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
     ap.add_argument("--size", type=int, default=8000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run a plain copy of this size first (for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the factorisation of one matrix runs on a "
@@ -77,6 +127,8 @@ def main():
     Ad = rq.colmajor(torch.from_numpy(np.ascontiguousarray(A64.T)).to(tdt).cuda().t())
     torch.cuda.synchronize()
     flops = randqlp_flops(m, n, d, q)
+    if args.copy_calibration_mib > 0:
+        copy_calibration(args.copy_calibration_mib)
 
     log("warmup")
     for i in range(args.warmup):
@@ -99,8 +151,11 @@ def main():
     avg_ms = kms / max(launches, 1)
     achieved = (kflops / max(launches, 1)) / (avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
+    traffic = None
+    if args.size == 8000:
+        traffic = read_traffic(f"profiles/gemm_kernel_rank200_8000_{args.precision}_traffic.txt")
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(achieved / peak, 4), "traffic": None,
+                "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": "gemm_kernel (products with A)", "avg_ms": round(avg_ms, 4),
                 "flops_per_launch": kflops / max(launches, 1),
                 "bytes_per_launch": kbytes / max(launches, 1)}
