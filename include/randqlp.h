@@ -123,7 +123,11 @@ rqlp_status randqlp_gaussian(void* out, int64_t m, int64_t d, int64_t ld, uint64
 
 /* The sketch / power / projection products of Algorithm 1:
  * C (rows x d) = op(A) X with op(A) = A^T (trans_a = 1: C is n x d, X is
- * m x d) or A (trans_a = 0: C is m x d, X is n x d). */
+ * m x d) or A (trans_a = 0: C is m x d, X is n x d).  precision RQLP_F64 /
+ * RQLP_F32: A, X, C of that type.  RQLP_MIXED_BF16 / RQLP_MIXED_F16: A, X
+ * and C are float; A and X are rounded to 16 bits (nearest even) into
+ * library scratch and multiplied on the precision-form kernel with fp32
+ * accumulation.  Synchronous (the library's scratch may be reused). */
 rqlp_status randqlp_gemm(int trans_a, const void* A, int64_t m, int64_t n, int64_t lda,
                          const void* X, int64_t d, int64_t ldx, void* C, int64_t ldc,
                          int precision, void* stream);

@@ -227,20 +227,26 @@ def gaussian(m, d, seed, stream_id=0, dtype=None, device="cuda"):
     return out
 
 
-def gemm(A, X, trans_a):
-    """C = A^T X (trans_a) or A X, on the sketch-product kernels."""
+def gemm(A, X, trans_a, precision=None):
+    """C = A^T X (trans_a) or A X, on the sketch-product kernels.
+
+    precision: None (from the dtype), or "bf16" / "f16" for the precision-form
+    kernel (A, X float32, rounded to 16 bits inside; C float32)."""
     A = colmajor(A)
     X = colmajor(X)
     m, n = A.shape
     rows = n if trans_a else m
     if X.shape[0] != (m if trans_a else n) or X.dtype != A.dtype:
         raise ValueError("shape or dtype mismatch")
+    prec = _precision(A.dtype)
+    if precision is not None:
+        prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     d = X.shape[1]
     C = empty_colmajor(rows, d, A.dtype, A.device)
     _check(lib().randqlp_gemm(1 if trans_a else 0, ctypes.c_void_p(A.data_ptr()), m, n, _ld(A),
                               ctypes.c_void_p(X.data_ptr()), d, _ld(X),
                               ctypes.c_void_p(C.data_ptr()), max(1, rows),
-                              _precision(A.dtype), _stream_ptr(A.device)))
+                              prec, _stream_ptr(A.device)))
     return C
 
 

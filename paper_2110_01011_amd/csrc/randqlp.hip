@@ -61,8 +61,9 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
   size_t m1, m2, n1, n2, part, part_bytes, G, R[4], Racc[2], Rfin, dinv, colf, scal, flags,
-      chs, a16, at16, total;
+      chs, a16, at16, p16, total;
   int64_t ld16, ldt16;  // leading dimensions of the 16-bit copies of A and A^T
+  int64_t ldp16;        // leading dimension of the 16-bit copy of a panel
   size_t flags_bytes;  // status words cleared at the start of a call
 };
 
@@ -90,8 +91,10 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
     part = std::max(part, gemm_partial_bytes(1, dd - CHOL_MAX_D, dd - CHOL_MAX_D, CHOL_MAX_D,
                                              DT_F64, DT_F64, true));
   if (mixed) {
-    part = std::max(part, gemm16_partial_bytes(n, d, m));
-    part = std::max(part, gemm16_partial_bytes(m, d, n));
+    for (bool f16 : {false, true}) {
+      part = std::max(part, gemm16_partial_bytes(n, d, m, f16));
+      part = std::max(part, gemm16_partial_bytes(m, d, n, f16));
+    }
   }
   L.part = take(part);
   L.part_bytes = part;
@@ -103,13 +106,15 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
   L.dinv = take((size_t)((d + 15) / 16) * 256 * 8);
   L.colf = take((size_t)d * 4);
   if (mixed) {
-    L.ld16 = (m + 7) / 8 * 8;
-    L.ldt16 = (n + 7) / 8 * 8;
+    L.ld16 = gemm16_ld(m);
+    L.ldt16 = gemm16_ld(n);
     L.a16 = take((size_t)L.ld16 * n * 2);
     L.at16 = take((size_t)L.ldt16 * m * 2);
+    L.ldp16 = gemm16_ld(std::max(m, n));
+    L.p16 = take((size_t)L.ldp16 * d * 2);
   } else {
-    L.ld16 = L.ldt16 = 0;
-    L.a16 = L.at16 = 0;
+    L.ld16 = L.ldt16 = L.ldp16 = 0;
+    L.a16 = L.at16 = L.p16 = 0;
   }
   L.scal = take(64);
   L.flags = take(64);
@@ -207,15 +212,15 @@ hipError_t gemm(Ctx& c, int trans_a, const void* A, int64_t lda, const void* B, 
 
 // Precision-form product C (rows x d, fp32) = op(A) X on the 16-bit copies:
 // trans_a = 1 uses A16 (C = A^T X, rows = n, K = m), trans_a = 0 uses the
-// copy of A^T (C = A X, rows = m, K = n).
+// copy of A^T (C = A X, rows = m, K = n).  X is rounded to 16 bits first.
 hipError_t gemm16(Ctx& c, int trans_a, int64_t m, int64_t n, const float* X, int64_t ldx,
                   float* C, int64_t ldc, int64_t d) {
   Gemm16Args g;
   g.f16 = (c.mixed == 2);
   g.A = trans_a ? (const void*)(c.ws + c.lay.a16) : (const void*)(c.ws + c.lay.at16);
   g.lda = trans_a ? c.lay.ld16 : c.lay.ldt16;
-  g.B = X;
-  g.ldb = ldx;
+  g.B = c.ws + c.lay.p16;
+  g.ldb = c.lay.ldp16;
   g.C = C;
   g.ldc = ldc;
   g.M = trans_a ? n : m;
@@ -223,17 +228,19 @@ hipError_t gemm16(Ctx& c, int trans_a, int64_t m, int64_t n, const float* X, int
   g.K = trans_a ? m : n;
   g.partial = c.ws + c.lay.part;
   g.partial_bytes = c.lay.part_bytes;
+  hipError_t e = launch_convert_panel16(X, g.K, d, ldx, c.ws + c.lay.p16, c.lay.ldp16, g.f16, c.st);
+  if (e != hipSuccess) return e;
   if (g_prof.on) {
     const size_t i = g_prof.used++;
     while (g_prof.ev.size() < 2 * g_prof.used) {
-      hipEvent_t e;
-      if (hipEventCreate(&e) != hipSuccess) return hipErrorOutOfMemory;
-      g_prof.ev.push_back(e);
+      hipEvent_t ev;
+      if (hipEventCreate(&ev) != hipSuccess) return hipErrorOutOfMemory;
+      g_prof.ev.push_back(ev);
     }
     g_prof.work_flops.resize(g_prof.used);
     g_prof.work_bytes.resize(g_prof.used);
     g_prof.work_flops[i] = 2.0 * (double)g.M * (double)g.N * (double)g.K;
-    g_prof.work_bytes[i] = 2.0 * (double)g.M * g.K + 4.0 * ((double)g.K * g.N + (double)g.M * g.N);
+    g_prof.work_bytes[i] = 2.0 * ((double)g.M * g.K + (double)g.K * g.N) + 4.0 * (double)g.M * g.N;
     g.ev_begin = g_prof.ev[2 * i];
     g.ev_end = g_prof.ev[2 * i + 1];
   }
@@ -636,34 +643,68 @@ rqlp_status randqlp_gemm(int trans_a, const void* A, int64_t m, int64_t n, int64
     return fail(RQLP_E_INVALID_ARG, "bad size, pointer or leading dimension");
   const int64_t rows = trans_a ? n : m, K = trans_a ? m : n;
   if (ldx < K || ldc < rows) return fail(RQLP_E_INVALID_ARG, "bad leading dimension");
-  if (precision != RQLP_F64 && precision != RQLP_F32)
+  if (precision < RQLP_F64 || precision > RQLP_MIXED_F16)
     return fail(RQLP_E_INVALID_ARG, "unknown precision %d", precision);
-  const Dtype dt = precision == RQLP_F64 ? DT_F64 : DT_F32;
+  const hipStream_t st = (hipStream_t)stream;
   rqlp_opts o;
   rqlp_opts_default(&o);
-  const size_t part = gemm_partial_bytes(trans_a, rows, d, K, dt, dt, false);
   std::unique_lock<std::mutex> lk;
   char* ws = nullptr;
-  rqlp_status s = acquire_ws(o, part > 0 ? part : 256, &ws, lk);
-  if (s != RQLP_OK) return s;
-  GemmArgs g;
-  g.trans_a = trans_a ? 1 : 0;
-  g.A = A;
-  g.lda = lda;
-  g.B = X;
-  g.ldb = ldx;
-  g.C = C;
-  g.ldc = ldc;
-  g.M = rows;
-  g.N = d;
-  g.K = K;
-  g.in_t = dt;
-  g.out_t = dt;
-  g.gram = false;
-  g.partial = ws;
-  g.partial_bytes = part;
-  hipError_t e = launch_gemm(g, (hipStream_t)stream);
-  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);  // cache may be reused
+  hipError_t e = hipSuccess;
+  if (precision >= RQLP_MIXED_BF16) {
+    // 16-bit copies of op(A) (contraction-contiguous) and of X, then the
+    // precision-form product kernel.
+    const bool f16 = precision == RQLP_MIXED_F16;
+    const int64_t ld16 = gemm16_ld(m), ldt16 = gemm16_ld(n), ldx16 = gemm16_ld(K);
+    const size_t part = gemm16_partial_bytes(rows, d, K, f16);
+    const size_t off_a = 0, off_at = align_up((size_t)ld16 * n * 2);
+    const size_t off_x = off_at + align_up((size_t)ldt16 * m * 2);
+    const size_t off_p = off_x + align_up((size_t)ldx16 * d * 2);
+    rqlp_status s = acquire_ws(o, off_p + std::max<size_t>(part, 256), &ws, lk);
+    if (s != RQLP_OK) return s;
+    e = launch_convert16((const float*)A, m, n, lda, ws + off_a, ld16, ws + off_at, ldt16, f16, st);
+    if (e == hipSuccess)
+      e = launch_convert_panel16((const float*)X, K, d, ldx, ws + off_x, ldx16, f16, st);
+    if (e == hipSuccess) {
+      Gemm16Args g;
+      g.f16 = f16;
+      g.A = trans_a ? (const void*)(ws + off_a) : (const void*)(ws + off_at);
+      g.lda = trans_a ? ld16 : ldt16;
+      g.B = ws + off_x;
+      g.ldb = ldx16;
+      g.C = (float*)C;
+      g.ldc = ldc;
+      g.M = rows;
+      g.N = d;
+      g.K = K;
+      g.partial = ws + off_p;
+      g.partial_bytes = part;
+      e = launch_gemm16(g, st);
+    }
+  } else {
+    const Dtype dt = precision == RQLP_F64 ? DT_F64 : DT_F32;
+    const size_t part = gemm_partial_bytes(trans_a, rows, d, K, dt, dt, false);
+    rqlp_status s = acquire_ws(o, part > 0 ? part : 256, &ws, lk);
+    if (s != RQLP_OK) return s;
+    GemmArgs g;
+    g.trans_a = trans_a ? 1 : 0;
+    g.A = A;
+    g.lda = lda;
+    g.B = X;
+    g.ldb = ldx;
+    g.C = C;
+    g.ldc = ldc;
+    g.M = rows;
+    g.N = d;
+    g.K = K;
+    g.in_t = dt;
+    g.out_t = dt;
+    g.gram = false;
+    g.partial = ws;
+    g.partial_bytes = part;
+    e = launch_gemm(g, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);  // cache may be reused
   if (e != hipSuccess) return fail(RQLP_E_HIP, "gemm: %s", hipGetErrorString(e));
   return RQLP_OK;
 }

@@ -71,6 +71,37 @@ def test_gemm_f32_within_rounding_bound(rq, m, n, d, trans):
     assert np.all(np.abs(C - ref) <= bound)
 
 
+def _round16(x, precision):
+    """Round float32 values to bf16 / fp16 (nearest even) on the CPU, as float64."""
+    import torch
+    dt = torch.bfloat16 if precision == "bf16" else torch.float16
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(dt).double().numpy()
+
+
+@pytest.mark.parametrize("m,n,d", [(1000, 700, 25), (333, 517, 210), (5, 7, 3), (2100, 1500, 520),
+                                   (130, 4000, 64), (4000, 130, 272), (777, 901, 273)])
+@pytest.mark.parametrize("trans", [1, 0])
+@pytest.mark.parametrize("precision", ["bf16", "f16"])
+def test_gemm16_within_rounding_bound(rq, m, n, d, trans, precision):
+    """Precision-form product: A and X rounded to 16 bits, fp32 accumulation.
+    The products of 16-bit values are exact in fp32, so the only error is
+    the fp32 summation: |C - op(A16) X16| <= 2 (K + 2) u32 |op(A16)| |X16|."""
+    import torch
+    log(f"gemm16 {precision} trans={trans} m={m} n={n} d={d}")
+    r = np.random.default_rng(m * 5 + n + d)
+    A = np.asfortranarray(r.standard_normal((m, n)).astype(np.float32))
+    X = r.standard_normal((m if trans else n, d)).astype(np.float32)
+    C = to_np(rq.gemm(to_dev(A, torch.float32), to_dev(X, torch.float32), trans,
+                      precision=precision))
+    A16, X16 = _round16(A, precision), _round16(X, precision)
+    Aop = A16.T if trans else A16
+    ref = Aop @ X16
+    K = Aop.shape[1]
+    bound = 2 * (K + 2) * U32 * (np.abs(Aop) @ np.abs(X16))
+    assert C.shape == ref.shape
+    assert np.all(np.abs(C - ref) <= bound)
+
+
 def _panel(rows, d, kappa, seed):
     r = np.random.default_rng(seed)
     U, _ = np.linalg.qr(r.standard_normal((rows, d)))
