@@ -91,6 +91,32 @@ typedef struct {
   rqlp_info* info;         /* optional host struct filled on return        */
 } rqlp_opts;
 
+/* ---- Learned power-iteration predictor ----
+ * A small MLP (fp32) reads the spectrum of a cheap sketch and predicts how
+ * many power rounds the method needs.  Input: 65 features, the singular
+ * values of the 64-column sketch A^T Omega[:, :64] (the leading columns of
+ * the method's own Gaussian sketch, same seed) as
+ * clamp(log10(sigma_i / sigma_1), -6, 0) / 6 for i = 1..64, then k / 256.
+ * Network: 65 -> 128 (ReLU) -> 128 (ReLU) -> 6 logits, class c = q for
+ * c = 0..4 and c = 5 for "more than 4".  Parameters: one float vector
+ * [W1 b1 W2 b2 W3 b3], each W (fan_in x fan_out) stored column by column.
+ * Activations and feature rows are row-major (one sample contiguous). */
+#define RQLP_MLP_INPUTS 65
+#define RQLP_MLP_HIDDEN 128
+#define RQLP_MLP_CLASSES 6
+#define RQLP_MLP_PARAMS 25734
+
+typedef struct {
+  int32_t q_predicted; /* predictor's class (0..4, 5 = more than 4)          */
+  int32_t q_used;      /* power rounds in the returned factors                */
+  int32_t judged;      /* 1 if the error judge ran (q_predicted < q_fallback) */
+  int32_t resumed;     /* 1 if the judge rejected q_predicted and the power
+                          rounds were resumed up to q_fallback                */
+  double judge_ratio;  /* the judge's statistic Delta / e^2 (0 if not run)    */
+  double est_rel_err;  /* sqrt(1 - ||L||_F^2 / ||A||_F^2) for the q_predicted
+                          factors, when judged                                */
+} rqlp_auto_info;
+
 /* Fill *opts with defaults: F64, AUTO, tight leading dimensions, null
  * stream, library-managed workspace, no info. */
 void rqlp_opts_default(rqlp_opts* opts);
@@ -139,6 +165,57 @@ rqlp_status randqlp_gemm(int trans_a, const void* A, int64_t m, int64_t n, int64
 rqlp_status randqlp_orth(const void* X, int64_t rows, int64_t d, int64_t ldx, void* Qx,
                          int64_t ldq, double* R, int64_t ldr, int precision,
                          int panel_qr, void* stream);
+
+/* randqlp_factor with the number of power rounds chosen by the predictor
+ * (params: device pointer to RQLP_MLP_PARAMS floats).  Steps: the 64-column
+ * feature sketch in A's own precision (fp32 for the precision form), its
+ * features, the MLP, q_hat = predicted class.  If q_hat >= q_fallback the
+ * result is randqlp_factor with q = q_fallback.  Otherwise the method runs
+ * with q = q_hat and an error judge looks one power round ahead: P =
+ * orth(A^T Q) is the next power iterate, so Z = A P is the next round's
+ * product; with e^2 = ||A||_F^2 - ||L||_F^2 (the squared residual of the
+ * factors) and Delta = ||(I - Q Q^T) Z||_F^2 (how much one more round would
+ * lower it), q_hat is accepted when Delta <= 0.0404 e^2 (2% in the error).
+ * Otherwise the power rounds resume from Z up to q_fallback, and the result
+ * equals randqlp_factor with q = q_fallback up to rounding.  opts as for
+ * randqlp_factor (info->q_used reports the rounds used); ainfo may be NULL.
+ * Synchronous. */
+rqlp_status randqlp_factor_auto(const void* A, int64_t m, int64_t n, int k, int p,
+                                int q_fallback, uint64_t seed, const float* params, void* Q,
+                                void* L, void* P, const rqlp_opts* opts,
+                                rqlp_auto_info* ainfo);
+
+/* The predictor's 65 features of A (m x n, lda; precision RQLP_F64 or
+ * RQLP_F32 = the type of A) into feat (device, 65 floats).  Synchronous. */
+rqlp_status randqlp_features(const void* A, int64_t m, int64_t n, int64_t lda, int k,
+                             uint64_t seed, int precision, float* feat, void* stream);
+
+/* MLP forward pass: X (B x 65, device, row-major) -> logits (B x 6).
+ * Synchronous. */
+rqlp_status randqlp_mlp_forward(const float* params, const float* X, int B, float* logits,
+                                void* stream);
+
+/* Mean softmax cross-entropy over the batch (X: B x 65, y: B labels in
+ * 0..5, device) into *loss (device float) and its gradient with respect to
+ * the parameters into grad (device, RQLP_MLP_PARAMS).  Synchronous. */
+rqlp_status randqlp_mlp_loss_grad(const float* params, const float* X, const int* y, int B,
+                                  float* grad, float* loss, void* stream);
+
+/* One Adam step (Kingma & Ba; beta1 0.9, beta2 0.999, eps 1e-8) at step
+ * t >= 1 on params with moment buffers m, v (device, RQLP_MLP_PARAMS).
+ * Asynchronous. */
+rqlp_status randqlp_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t t,
+                             float lr, void* stream);
+
+/* Train on N samples (X: N x 65, y: N labels, device) for `epochs` passes
+ * of minibatches of `batch`, with Adam at learning rate lr.  Each epoch
+ * visits the samples in the order i -> (a i + c) mod N with a coprime to N
+ * and (a, c) drawn from (seed, epoch).  *step (host) is the Adam step count
+ * so far and is advanced.  epoch_loss (device, `epochs` floats) receives
+ * each epoch's mean minibatch loss.  Deterministic.  Synchronous. */
+rqlp_status randqlp_mlp_train(float* params, float* m, float* v, const float* X, const int* y,
+                              int64_t N, int epochs, int batch, float lr, uint64_t seed,
+                              int64_t* step, float* epoch_loss, void* stream);
 
 /* ---- Diagnostics ---- */
 

@@ -12,7 +12,8 @@ Matrices are column-major: a tensor of shape (rows, cols) with stride
 import ctypes
 import os
 
-__all__ = ["factor", "gaussian", "gemm", "orth", "sketch_width", "workspace_size",
+__all__ = ["factor", "factor_auto", "features", "mlp_forward", "mlp_loss_grad", "mlp_adam",
+           "mlp_train", "gaussian", "gemm", "orth", "sketch_width", "workspace_size",
            "colmajor", "empty_colmajor", "lib", "RandQLPError", "F64", "F32", "MIXED_BF16",
            "MIXED_F16",
            "PANEL_AUTO", "PANEL_CHOLQR2", "PANEL_ROBUST"]
@@ -29,7 +30,9 @@ STATUS = {0: "RQLP_OK", 1: "RQLP_E_INVALID_ARG", 2: "RQLP_E_NONFINITE", 3: "RQLP
 
 # Every symbol include/randqlp.h declares.
 EXPORTS = ["rqlp_opts_default", "randqlp_sketch_width", "randqlp_workspace_size",
-           "randqlp_factor", "randqlp_gaussian", "randqlp_gemm", "randqlp_orth",
+           "randqlp_factor", "randqlp_factor_auto", "randqlp_features", "randqlp_mlp_forward",
+           "randqlp_mlp_loss_grad", "randqlp_mlp_adam", "randqlp_mlp_train",
+           "randqlp_gaussian", "randqlp_gemm", "randqlp_orth",
            "randqlp_profile_enable", "randqlp_profile_read",
            "randqlp_status_string", "randqlp_last_error"]
 
@@ -47,6 +50,18 @@ class Info(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+MLP_INPUTS, MLP_HIDDEN, MLP_CLASSES, MLP_PARAMS = 65, 128, 6, 25734
+
+
+class AutoInfo(ctypes.Structure):
+    _fields_ = [("q_predicted", ctypes.c_int32), ("q_used", ctypes.c_int32),
+                ("judged", ctypes.c_int32), ("resumed", ctypes.c_int32),
+                ("judge_ratio", ctypes.c_double), ("est_rel_err", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Opts(ctypes.Structure):
@@ -78,6 +93,20 @@ def lib():
     L.randqlp_workspace_size.restype = sz
     L.randqlp_factor.argtypes = [vp, i64, i64, i32, i32, i32, u64, vp, vp, vp, ctypes.POINTER(Opts)]
     L.randqlp_factor.restype = i32
+    L.randqlp_factor_auto.argtypes = [vp, i64, i64, i32, i32, i32, u64, vp, vp, vp, vp,
+                                      ctypes.POINTER(Opts), ctypes.POINTER(AutoInfo)]
+    L.randqlp_factor_auto.restype = i32
+    L.randqlp_features.argtypes = [vp, i64, i64, i64, i32, u64, i32, vp, vp]
+    L.randqlp_features.restype = i32
+    L.randqlp_mlp_forward.argtypes = [vp, vp, i32, vp, vp]
+    L.randqlp_mlp_forward.restype = i32
+    L.randqlp_mlp_loss_grad.argtypes = [vp, vp, vp, i32, vp, vp, vp]
+    L.randqlp_mlp_loss_grad.restype = i32
+    L.randqlp_mlp_adam.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, vp]
+    L.randqlp_mlp_adam.restype = i32
+    L.randqlp_mlp_train.argtypes = [vp, vp, vp, vp, vp, i64, i32, i32, ctypes.c_float, u64,
+                                    ctypes.POINTER(i64), vp, vp]
+    L.randqlp_mlp_train.restype = i32
     L.randqlp_gaussian.argtypes = [vp, i64, i64, i64, u64, u64, i32, vp]
     L.randqlp_gaussian.restype = i32
     L.randqlp_gemm.argtypes = [i32, vp, i64, i64, i64, vp, i64, i64, vp, i64, i32, vp]
@@ -170,14 +199,7 @@ def _ld(t):
     return max(1, t.stride(1)) if t.shape[1] > 1 else max(1, t.shape[0])
 
 
-def factor(A, k, p, q, seed, panel="auto", precision=None, return_info=False):
-    """Rand-QLP of a device matrix A (m x n, float64 or float32).
-
-    precision: None (from A's dtype), "f64", "f32", or the precision forms
-    "bf16" / "f16" (A float32; the products with A run on a 16-bit copy).
-    Returns (Q, L, P): Q (m x d) and P (n x d) in A's dtype, L (d x d)
-    float64, all column-major, with d = min(k + p, m, n).
-    """
+def _prepare(A, k, p, q, panel, precision):
     torch = _torch()
     if not A.is_cuda:
         raise ValueError("A must be a device tensor")
@@ -191,7 +213,7 @@ def factor(A, k, p, q, seed, panel="auto", precision=None, return_info=False):
                             "f32/bf16/f16 need float32)")
     d = sketch_width(m, n, k, p)
     if d < 1:
-        _check(lib().randqlp_factor(None, m, n, k, p, q, seed, None, None, None, None))
+        _check(lib().randqlp_factor(None, m, n, k, p, q, 0, None, None, None, None))
     dev = A.device
     Q = empty_colmajor(m, d, A.dtype, dev)
     P = empty_colmajor(n, d, A.dtype, dev)
@@ -200,14 +222,28 @@ def factor(A, k, p, q, seed, panel="auto", precision=None, return_info=False):
     o.precision = prec
     o.panel_qr = _PANELS[panel] if isinstance(panel, str) else int(panel)
     o.lda, o.ldq, o.ldl, o.ldp = _ld(A), _ld(Q), _ld(L), _ld(P)
+    o.stream = _stream_ptr(dev)
+    return A, Q, L, P, o
+
+
+def factor(A, k, p, q, seed, panel="auto", precision=None, return_info=False):
+    """Rand-QLP of a device matrix A (m x n, float64 or float32).
+
+    precision: None (from A's dtype), "f64", "f32", or the precision forms
+    "bf16" / "f16" (A float32; the products with A run on a 16-bit copy).
+    Returns (Q, L, P): Q (m x d) and P (n x d) in A's dtype, L (d x d)
+    float64, all column-major, with d = min(k + p, m, n).
+    """
+    torch = _torch()
+    A, Q, L, P, o = _prepare(A, k, p, q, panel, precision)
+    m, n = A.shape
     ws_bytes = lib().randqlp_workspace_size(m, n, k, p, q, ctypes.byref(o))
-    ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=dev)
+    ws = torch.empty(max(ws_bytes, 256), dtype=torch.uint8, device=A.device)
     o.workspace = ctypes.c_void_p(ws.data_ptr())
     o.workspace_bytes = ws.numel()
-    o.stream = _stream_ptr(dev)
     info = Info()
     o.info = ctypes.pointer(info)
-    with torch.cuda.device(dev):
+    with torch.cuda.device(A.device):
         _check(lib().randqlp_factor(ctypes.c_void_p(A.data_ptr()), m, n, k, p, q, seed,
                                     ctypes.c_void_p(Q.data_ptr()), ctypes.c_void_p(L.data_ptr()),
                                     ctypes.c_void_p(P.data_ptr()), ctypes.byref(o)))
@@ -215,6 +251,101 @@ def factor(A, k, p, q, seed, panel="auto", precision=None, return_info=False):
     if return_info:
         return Q, L, P, info.as_dict()
     return Q, L, P
+
+
+def factor_auto(A, k, p, seed, params, q_fallback=2, panel="auto", precision=None,
+                return_info=False):
+    """Rand-QLP with the number of power rounds predicted from a first sketch
+    (params: float32 device tensor of MLP_PARAMS), judged one round ahead and
+    resumed up to q_fallback when the prediction was too low.  Uses the
+    library's workspace cache.  Returns (Q, L, P) or, with return_info,
+    (Q, L, P, info, auto_info)."""
+    torch = _torch()
+    if params.dtype != torch.float32 or params.numel() != MLP_PARAMS or not params.is_cuda:
+        raise ValueError("params must be a float32 device tensor of MLP_PARAMS values")
+    A, Q, L, P, o = _prepare(A, k, p, q_fallback, panel, precision)
+    m, n = A.shape
+    info, ainfo = Info(), AutoInfo()
+    o.info = ctypes.pointer(info)
+    params = params.contiguous()
+    with torch.cuda.device(A.device):
+        _check(lib().randqlp_factor_auto(ctypes.c_void_p(A.data_ptr()), m, n, k, p, q_fallback,
+                                         seed, ctypes.c_void_p(params.data_ptr()),
+                                         ctypes.c_void_p(Q.data_ptr()),
+                                         ctypes.c_void_p(L.data_ptr()),
+                                         ctypes.c_void_p(P.data_ptr()), ctypes.byref(o),
+                                         ctypes.byref(ainfo)))
+    if return_info:
+        return Q, L, P, info.as_dict(), ainfo.as_dict()
+    return Q, L, P
+
+
+def features(A, k, seed):
+    """The predictor's 65 features of a device matrix (float64 or float32)."""
+    torch = _torch()
+    A = colmajor(A)
+    m, n = A.shape
+    out = torch.empty(MLP_INPUTS, dtype=torch.float32, device=A.device)
+    _check(lib().randqlp_features(ctypes.c_void_p(A.data_ptr()), m, n, _ld(A), k, seed,
+                                  _precision(A.dtype), ctypes.c_void_p(out.data_ptr()),
+                                  _stream_ptr(A.device)))
+    return out
+
+
+def _rows(X, cols, dtype):
+    torch = _torch()
+    if X.dim() != 2 or X.shape[1] != cols or X.dtype != dtype or not X.is_cuda:
+        raise ValueError(f"expected a device {dtype} tensor with {cols} columns")
+    return X.contiguous()
+
+
+def mlp_forward(params, X):
+    """Logits (B x 6) of the predictor MLP for features X (B x 65, float32)."""
+    torch = _torch()
+    X = _rows(X, MLP_INPUTS, torch.float32)
+    out = torch.empty((X.shape[0], MLP_CLASSES), dtype=torch.float32, device=X.device)
+    _check(lib().randqlp_mlp_forward(ctypes.c_void_p(params.data_ptr()),
+                                     ctypes.c_void_p(X.data_ptr()), X.shape[0],
+                                     ctypes.c_void_p(out.data_ptr()), _stream_ptr(X.device)))
+    return out
+
+
+def mlp_loss_grad(params, X, y):
+    """(mean cross-entropy, gradient) of the predictor MLP on a batch."""
+    torch = _torch()
+    X = _rows(X, MLP_INPUTS, torch.float32)
+    y = y.to(torch.int32).contiguous()
+    grad = torch.empty(MLP_PARAMS, dtype=torch.float32, device=X.device)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    _check(lib().randqlp_mlp_loss_grad(ctypes.c_void_p(params.data_ptr()),
+                                       ctypes.c_void_p(X.data_ptr()),
+                                       ctypes.c_void_p(y.data_ptr()), X.shape[0],
+                                       ctypes.c_void_p(grad.data_ptr()),
+                                       ctypes.c_void_p(loss.data_ptr()), _stream_ptr(X.device)))
+    return loss, grad
+
+
+def mlp_adam(params, grad, m, v, t, lr):
+    """One Adam step in place (t >= 1)."""
+    _check(lib().randqlp_mlp_adam(ctypes.c_void_p(params.data_ptr()),
+                                  ctypes.c_void_p(grad.data_ptr()), ctypes.c_void_p(m.data_ptr()),
+                                  ctypes.c_void_p(v.data_ptr()), int(t), float(lr),
+                                  _stream_ptr(params.device)))
+
+
+def mlp_train(params, m, v, X, y, epochs, batch, lr, seed, step=0):
+    """Train in place on (X, y); returns (per-epoch mean loss tensor, step)."""
+    torch = _torch()
+    X = _rows(X, MLP_INPUTS, torch.float32)
+    y = y.to(torch.int32).contiguous()
+    losses = torch.empty(max(epochs, 1), dtype=torch.float32, device=X.device)
+    st = ctypes.c_int64(step)
+    _check(lib().randqlp_mlp_train(ctypes.c_void_p(params.data_ptr()),
+                                   ctypes.c_void_p(m.data_ptr()), ctypes.c_void_p(v.data_ptr()),
+                                   ctypes.c_void_p(X.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                   X.shape[0], epochs, batch, float(lr), seed, ctypes.byref(st),
+                                   ctypes.c_void_p(losses.data_ptr()), _stream_ptr(X.device)))
+    return losses[:epochs], st.value
 
 
 def gaussian(m, d, seed, stream_id=0, dtype=None, device="cuda"):

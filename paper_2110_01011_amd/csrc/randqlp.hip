@@ -59,17 +59,30 @@ constexpr double kTolDepRobust = 1e-12;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
+constexpr int kPredCols = 64;  // sketch columns the predictor reads
+// Offsets of the MLP parameters [W1 b1 W2 b2 W3 b3] (floats).
+constexpr int kNI = RQLP_MLP_INPUTS, kNH = RQLP_MLP_HIDDEN, kNC = RQLP_MLP_CLASSES;
+constexpr int64_t kOW1 = 0, kOB1 = kOW1 + kNI * kNH, kOW2 = kOB1 + kNH, kOB2 = kOW2 + kNH * kNH,
+                  kOW3 = kOB2 + kNH, kOB3 = kOW3 + kNH * kNC, kNParams = kOB3 + kNC;
+static_assert(kNParams == RQLP_MLP_PARAMS, "MLP parameter count");
+// The error judge accepts q_predicted when one more power round would lower
+// the squared residual by at most this fraction: (1 + 0.02)^2 - 1.
+constexpr double kJudgeSlack = 0.0404;
+
 struct Layout {
   size_t m1, m2, n1, n2, part, part_bytes, G, R[4], Racc[2], Rfin, dinv, colf, scal, flags,
       chs, a16, at16, p16, total;
   int64_t ld16, ldt16;  // leading dimensions of the 16-bit copies of A and A^T
   int64_t ldp16;        // leading dimension of the 16-bit copy of a panel
+  // predictor and error judge (randqlp_factor_auto only)
+  size_t om64, y64, g64, feat, mlp, cls, jd, sums, sres;
   size_t flags_bytes;  // status words cleared at the start of a call
 };
 
 size_t elem_size(Dtype dt) { return dt == DT_F64 ? 8 : 4; }
 
-Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false) {
+Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false,
+                   bool autoq = false) {
   Layout L;
   const size_t es = elem_size(dt);
   size_t off = 0;
@@ -96,6 +109,12 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
       part = std::max(part, gemm16_partial_bytes(m, d, n, f16));
     }
   }
+  if (autoq) {
+    part = std::max(part, gemm_partial_bytes(1, n, kPredCols, m, dt, dt, false));
+    part = std::max(part, gemm_partial_bytes(1, kPredCols, kPredCols, n, dt, DT_F64, true));
+    part = std::max(part, gemm_partial_bytes(1, d, d, m, dt, dt, false));
+    part = std::max(part, gemm_partial_bytes(0, m, d, d, dt, dt, false));
+  }
   L.part = take(part);
   L.part_bytes = part;
   L.G = take((size_t)d * d * 8);
@@ -115,6 +134,19 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
   } else {
     L.ld16 = L.ldt16 = L.ldp16 = 0;
     L.a16 = L.at16 = L.p16 = 0;
+  }
+  if (autoq) {
+    L.om64 = take((size_t)m * kPredCols * es);
+    L.y64 = take((size_t)n * kPredCols * es);
+    L.g64 = take((size_t)kPredCols * kPredCols * 8);
+    L.feat = take(RQLP_MLP_INPUTS * 4);
+    L.mlp = take((2 * RQLP_MLP_HIDDEN + RQLP_MLP_CLASSES) * 4);
+    L.cls = take(16);
+    L.jd = take((size_t)d * d * es);
+    L.sums = take(sumsq_scratch_bytes());
+    L.sres = take(4 * 8);
+  } else {
+    L.om64 = L.y64 = L.g64 = L.feat = L.mlp = L.cls = L.jd = L.sums = L.sres = 0;
   }
   L.scal = take(64);
   L.flags = take(64);
@@ -381,61 +413,75 @@ struct FactorArgs {
   int64_t ldp;
 };
 
-// Precision form of the pipeline: products with A on the 16-bit copies,
-// final projection in fp32.
-hipError_t run_pipeline_mixed(Ctx& c, const FactorArgs& f, PanelMode mode) {
+// A product of the power iteration with A: C (rows x d) = op(A) X.  The
+// precision form runs it on the 16-bit copies; `full` forces the input
+// precision (the final projection and the error judge's product).
+hipError_t prod(Ctx& c, const FactorArgs& f, int trans_a, const void* X, int64_t ldx, void* C,
+                int64_t ldc, bool full = false) {
+  const int64_t rows = trans_a ? f.n : f.m, K = trans_a ? f.m : f.n;
+  if (c.mixed && !full)
+    return gemm16(c, trans_a, f.m, f.n, (const float*)X, ldx, (float*)C, ldc, c.d);
+  return gemm(c, trans_a, f.A, f.lda, X, ldx, C, ldc, rows, c.d, K, c.dt, c.dt, false, true);
+}
+
+// Stages of the generalised Algorithm 1.  Panels: Zm / Tm (m x d) and
+// Yn / Tn (n x d) in the workspace; Qbar lives in Yn between stages.
+// start: Omega, Y = A^T Omega, Qbar = orth(Y).
+hipError_t stage_start(Ctx& c, const FactorArgs& f, PanelMode mode) {
   const int64_t m = f.m, n = f.n, d = c.d;
-  float* Zm = c.at<float>(c.lay.m1);
-  void* Tm = c.ws + c.lay.m2;
-  float* Yn = c.at<float>(c.lay.n1);
+  void* Zm = c.ws + c.lay.m1;
+  void* Yn = c.ws + c.lay.n1;
   void* Tn = c.ws + c.lay.n2;
-  double* Rfin = c.at<double>(c.lay.Rfin);
-  c.orth_calls = 0;
-  HIP_TRY(hipMemsetAsync(c.flags(), 0, c.lay.flags_bytes, c.st));
-  HIP_TRY(launch_convert16((const float*)f.A, m, n, f.lda, c.ws + c.lay.a16, c.lay.ld16,
-                           c.ws + c.lay.at16, c.lay.ldt16, c.mixed == 2, c.st));
-  HIP_TRY(launch_gaussian(Zm, m, d, m, c.seed, 0, DT_F32, c.st));             // randn
-  HIP_TRY(gemm16(c, 1, m, n, Zm, m, Yn, n, d));                                // A^T Omega
-  HIP_TRY(orth(c, Yn, n, n, Yn, n, Tn, nullptr, mode, false));
-  for (int it = 0; it < f.q; ++it) {
-    HIP_TRY(gemm16(c, 0, m, n, Yn, n, Zm, m, d));                              // A Qbar
+  if (c.mixed)
+    HIP_TRY(launch_convert16((const float*)f.A, m, n, f.lda, c.ws + c.lay.a16, c.lay.ld16,
+                             c.ws + c.lay.at16, c.lay.ldt16, c.mixed == 2, c.st));
+  HIP_TRY(launch_gaussian(Zm, m, d, m, c.seed, 0, c.dt, c.st));                // randn
+  HIP_TRY(prod(c, f, 1, Zm, m, Yn, n));                                        // A^T Omega
+  return orth(c, Yn, n, n, Yn, n, Tn, nullptr, mode, false);                   // Qbar
+}
+
+// `count` power rounds: Q = orth(A Qbar), Qbar = orth(A^T Q).
+hipError_t stage_rounds(Ctx& c, const FactorArgs& f, PanelMode mode, int count) {
+  const int64_t m = f.m, n = f.n;
+  void* Zm = c.ws + c.lay.m1;
+  void* Tm = c.ws + c.lay.m2;
+  void* Yn = c.ws + c.lay.n1;
+  void* Tn = c.ws + c.lay.n2;
+  for (int it = 0; it < count; ++it) {
+    HIP_TRY(prod(c, f, 0, Yn, n, Zm, m));                                      // A Qbar
     HIP_TRY(orth(c, Zm, m, m, Zm, m, Tm, nullptr, mode, false));
-    HIP_TRY(gemm16(c, 1, m, n, Zm, m, Yn, n, d));                              // A^T Q
+    HIP_TRY(prod(c, f, 1, Zm, m, Yn, n));                                      // A^T Q
     HIP_TRY(orth(c, Yn, n, n, Yn, n, Tn, nullptr, mode, false));
   }
-  HIP_TRY(gemm16(c, 0, m, n, Yn, n, Zm, m, d));                                // A Qbar
-  HIP_TRY(orth(c, Zm, m, m, f.Q, f.ldq, Tm, nullptr, mode, true));             // Q
-  HIP_TRY(gemm(c, 1, f.A, f.lda, f.Q, f.ldq, Yn, n, n, d, m, DT_F32, DT_F32, false, true));
-  HIP_TRY(orth(c, Yn, n, n, f.P, f.ldp, Tn, Rfin, mode, true));                // P, R
-  HIP_TRY(launch_lower_from_upper(Rfin, d, f.L, f.ldl, c.st));                // L = R^T
   return hipSuccess;
 }
 
-hipError_t run_pipeline(Ctx& c, const FactorArgs& f, PanelMode mode) {
-  if (c.mixed) return run_pipeline_mixed(c, f, mode);
+// From Z = A Qbar (in Zm): Q = orth(Z), W = A^T Q, (P, R) = orth(W), L = R^T.
+hipError_t stage_finish_from_z(Ctx& c, const FactorArgs& f, PanelMode mode) {
   const int64_t m = f.m, n = f.n, d = c.d;
   void* Zm = c.ws + c.lay.m1;
   void* Tm = c.ws + c.lay.m2;
   void* Yn = c.ws + c.lay.n1;
   void* Tn = c.ws + c.lay.n2;
   double* Rfin = c.at<double>(c.lay.Rfin);
+  HIP_TRY(orth(c, Zm, m, m, f.Q, f.ldq, Tm, nullptr, mode, true));             // Q
+  HIP_TRY(prod(c, f, 1, f.Q, f.ldq, Yn, n, true));                             // A^T Q
+  HIP_TRY(orth(c, Yn, n, n, f.P, f.ldp, Tn, Rfin, mode, true));                // P, R
+  return launch_lower_from_upper(Rfin, d, f.L, f.ldl, c.st);                  // L = R^T
+}
+
+// Z = A Qbar, then stage_finish_from_z.
+hipError_t stage_finish(Ctx& c, const FactorArgs& f, PanelMode mode) {
+  HIP_TRY(prod(c, f, 0, c.ws + c.lay.n1, f.n, c.ws + c.lay.m1, f.m));          // A Qbar
+  return stage_finish_from_z(c, f, mode);
+}
+
+hipError_t run_pipeline(Ctx& c, const FactorArgs& f, PanelMode mode) {
   c.orth_calls = 0;
   HIP_TRY(hipMemsetAsync(c.flags(), 0, c.lay.flags_bytes, c.st));
-  HIP_TRY(launch_gaussian(Zm, m, d, m, c.seed, 0, c.dt, c.st));                     // randn
-  HIP_TRY(gemm(c, 1, f.A, f.lda, Zm, m, Yn, n, n, d, m, c.dt, c.dt, false, true));  // A^T Omega
-  HIP_TRY(orth(c, Yn, n, n, Yn, n, Tn, nullptr, mode, false));                       // Qbar
-  for (int it = 0; it < f.q; ++it) {
-    HIP_TRY(gemm(c, 0, f.A, f.lda, Yn, n, Zm, m, m, d, n, c.dt, c.dt, false, true));  // A Qbar
-    HIP_TRY(orth(c, Zm, m, m, Zm, m, Tm, nullptr, mode, false));
-    HIP_TRY(gemm(c, 1, f.A, f.lda, Zm, m, Yn, n, n, d, m, c.dt, c.dt, false, true));  // A^T Q
-    HIP_TRY(orth(c, Yn, n, n, Yn, n, Tn, nullptr, mode, false));
-  }
-  HIP_TRY(gemm(c, 0, f.A, f.lda, Yn, n, Zm, m, m, d, n, c.dt, c.dt, false, true));  // A Qbar
-  HIP_TRY(orth(c, Zm, m, m, f.Q, f.ldq, Tm, nullptr, mode, true));                   // Q
-  HIP_TRY(gemm(c, 1, f.A, f.lda, f.Q, f.ldq, Yn, n, n, d, m, c.dt, c.dt, false, true));  // A^T Q
-  HIP_TRY(orth(c, Yn, n, n, f.P, f.ldp, Tn, Rfin, mode, true));                      // P, R
-  HIP_TRY(launch_lower_from_upper(Rfin, d, f.L, f.ldl, c.st));                      // L = R^T
-  return hipSuccess;
+  HIP_TRY(stage_start(c, f, mode));
+  HIP_TRY(stage_rounds(c, f, mode, f.q));
+  return stage_finish(c, f, mode);
 }
 
 }  // namespace
@@ -540,13 +586,12 @@ rqlp_status read_flags(Ctx& c, int host[4]) {
   return RQLP_OK;
 }
 
-}  // namespace
 
-extern "C" {
-
-rqlp_status randqlp_factor(const void* A, int64_t m, int64_t n, int k, int p, int q,
-                           uint64_t seed, void* Q, void* L, void* P, const rqlp_opts* opts) {
-  rqlp_opts o;
+// ---- shared set-up of randqlp_factor / randqlp_factor_auto
+rqlp_status setup_factor(const void* A, int64_t m, int64_t n, int k, int p, int q,
+                         uint64_t seed, void* Q, void* L, void* P, const rqlp_opts* opts,
+                         bool autoq, Ctx& c, FactorArgs& f, rqlp_opts& o,
+                         std::unique_lock<std::mutex>& lk) {
   if (opts)
     o = *opts;
   else
@@ -569,25 +614,36 @@ rqlp_status randqlp_factor(const void* A, int64_t m, int64_t n, int k, int p, in
     return fail(RQLP_E_UNSUPPORTED, "sketch width d = %lld exceeds %d", (long long)d, RQLP_MAX_D);
   const Dtype dt = (o.precision == RQLP_F64) ? DT_F64 : DT_F32;
   const int mixed = (o.precision == RQLP_MIXED_BF16) ? 1 : (o.precision == RQLP_MIXED_F16) ? 2 : 0;
-
-  Ctx c;
   c.st = (hipStream_t)o.stream;
   c.dt = dt;
   c.mixed = mixed;
-  c.lay = make_layout(m, n, d, dt, mixed != 0);
+  c.lay = make_layout(m, n, d, dt, mixed != 0, autoq);
   c.d = d;
   c.seed = seed;
   c.orth_calls = 0;
-  std::unique_lock<std::mutex> lk;
   rqlp_status s = acquire_ws(o, c.lay.total, &c.ws, lk);
   if (s != RQLP_OK) return s;
+  f = FactorArgs{A, m, n, lda, q, Q, ldq, (double*)L, ldl, P, ldp};
+  return RQLP_OK;
+}
 
-  FactorArgs f{A, m, n, lda, q, Q, ldq, (double*)L, ldl, P, ldp};
-  PanelMode mode = (o.panel_qr == RQLP_PANEL_ROBUST)    ? PM_ROBUST
-                   : (o.panel_qr == RQLP_PANEL_CHOLQR2) ? PM_CHOLQR2
-                                                        : PM_FAST;
+PanelMode start_mode(const rqlp_opts& o) {
+  return (o.panel_qr == RQLP_PANEL_ROBUST)    ? PM_ROBUST
+         : (o.panel_qr == RQLP_PANEL_CHOLQR2) ? PM_CHOLQR2
+                                              : PM_FAST;
+}
+
+struct Outcome {
+  int breakdowns = 0, reran = 0, completed = 0;
+};
+
+// The method with f.q rounds; in AUTO mode a panel that reports an unsafe
+// pivot (or an inaccurate second pass) makes the whole call rerun with the
+// stronger panel QR.
+rqlp_status run_with_escalation(Ctx& c, const FactorArgs& f, const rqlp_opts& o,
+                                PanelMode mode, Outcome& r) {
   int fl[4] = {0, 0, 0, 0};
-  int reran = 0, breakdowns = 0;
+  rqlp_status s;
   for (;;) {
     hipError_t e = run_pipeline(c, f, mode);
     if (e != hipSuccess) return fail(RQLP_E_HIP, "launch failed: %s", hipGetErrorString(e));
@@ -595,7 +651,7 @@ rqlp_status randqlp_factor(const void* A, int64_t m, int64_t n, int k, int p, in
     if (fl[0] & FLAG_NONFINITE) {
       int fin[4] = {0, 0, 0, 0};
       e = hipMemsetAsync(c.flags(), 0, 64, c.st);
-      if (e == hipSuccess) e = launch_check_finite(A, m, n, lda, dt, c.flags(), c.st);
+      if (e == hipSuccess) e = launch_check_finite(f.A, f.m, f.n, f.lda, c.dt, c.flags(), c.st);
       if (e != hipSuccess) return fail(RQLP_E_HIP, "finite check: %s", hipGetErrorString(e));
       if ((s = read_flags(c, fin)) != RQLP_OK) return s;
       if (fin[0] & FLAG_NONFINITE) return fail(RQLP_E_NONFINITE, "A holds NaN or Inf");
@@ -605,22 +661,369 @@ rqlp_status randqlp_factor(const void* A, int64_t m, int64_t n, int k, int p, in
     const bool pivot_bad = (fl[0] & (FLAG_NONPOS_PIVOT | FLAG_NONFINITE)) != 0;
     const bool second_bad = (fl[0] & FLAG_SECOND_PASS) != 0;
     if (mode == PM_ROBUST || (!pivot_bad && !second_bad)) break;
-    ++breakdowns;
+    ++r.breakdowns;
     if (o.panel_qr != RQLP_PANEL_AUTO) break;  // explicit strategy: no retry
     // A second pass that was not accurate enough: two full passes suffice
     // unless a pivot itself was unsafe, which needs the robust panels.
     mode = (!pivot_bad && mode == PM_FAST) ? PM_CHOLQR2 : PM_ROBUST;
-    reran = 1;
+    r.reran = 1;
   }
-  if (o.info) {
-    o.info->d = (int32_t)d;
-    o.info->q_used = q;
-    o.info->breakdowns = breakdowns;
-    o.info->robust_rerun = reran;
-    o.info->completed = fl[2];
-    o.info->reserved = 0;
+  r.completed = fl[2];
+  return RQLP_OK;
+}
+
+void fill_info(const rqlp_opts& o, int64_t d, int q_used, const Outcome& r) {
+  if (!o.info) return;
+  o.info->d = (int32_t)d;
+  o.info->q_used = q_used;
+  o.info->breakdowns = r.breakdowns;
+  o.info->robust_rerun = r.reran;
+  o.info->completed = r.completed;
+  o.info->reserved = 0;
+}
+
+// ---- predictor
+struct MlpScratch {
+  float *Xb, *H1, *H2, *Z, *dZ, *dH1, *dH2, *lossv, *grad, *step_loss;
+  int* yb;
+};
+
+size_t mlp_scratch_bytes(int64_t B, int64_t steps) {
+  return align_up((size_t)B * kNI * 4) + align_up((size_t)B * 4) +
+         4 * align_up((size_t)B * kNH * 4) + 2 * align_up((size_t)B * kNC * 4) +
+         align_up((size_t)B * 4) + align_up((size_t)kNParams * 4) +
+         align_up((size_t)std::max<int64_t>(steps, 1) * 4);
+}
+
+void mlp_scratch_map(char* ws, int64_t B, int64_t steps, MlpScratch& sc) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    char* p = ws + off;
+    off += align_up(bytes);
+    return p;
+  };
+  sc.Xb = (float*)take((size_t)B * kNI * 4);
+  sc.yb = (int*)take((size_t)B * 4);
+  sc.H1 = (float*)take((size_t)B * kNH * 4);
+  sc.H2 = (float*)take((size_t)B * kNH * 4);
+  sc.dH1 = (float*)take((size_t)B * kNH * 4);
+  sc.dH2 = (float*)take((size_t)B * kNH * 4);
+  sc.Z = (float*)take((size_t)B * kNC * 4);
+  sc.dZ = (float*)take((size_t)B * kNC * 4);
+  sc.lossv = (float*)take((size_t)B * 4);
+  sc.grad = (float*)take((size_t)kNParams * 4);
+  sc.step_loss = (float*)take((size_t)std::max<int64_t>(steps, 1) * 4);
+}
+
+hipError_t mlp_forward_dev(const float* th, const float* X, int B, float* H1, float* H2,
+                           float* Z, hipStream_t st) {
+  HIP_TRY(launch_linear_forward(X, kNI, th + kOW1, th + kOB1, H1, B, kNI, kNH, true, st));
+  HIP_TRY(launch_linear_forward(H1, kNH, th + kOW2, th + kOB2, H2, B, kNH, kNH, true, st));
+  return launch_linear_forward(H2, kNH, th + kOW3, th + kOB3, Z, B, kNH, kNC, false, st);
+}
+
+// Mean cross-entropy and its gradient by backpropagation through the three
+// layers (the ReLU masks come from the stored activations).
+hipError_t mlp_loss_grad_dev(const float* th, const float* X, const int* y, int B,
+                             const MlpScratch& sc, float* grad, float* loss, hipStream_t st) {
+  HIP_TRY(mlp_forward_dev(th, X, B, sc.H1, sc.H2, sc.Z, st));
+  HIP_TRY(launch_softmax_xent(sc.Z, y, B, kNC, sc.dZ, sc.lossv, st));
+  HIP_TRY(launch_sum(sc.lossv, B, 1.0f / (float)B, loss, st));
+  HIP_TRY(launch_linear_backward_weight(sc.H2, kNH, sc.dZ, grad + kOW3, grad + kOB3, B, kNH,
+                                        kNC, st));
+  HIP_TRY(launch_linear_backward_input(sc.dZ, th + kOW3, sc.H2, sc.dH2, B, kNH, kNC, st));
+  HIP_TRY(launch_linear_backward_weight(sc.H1, kNH, sc.dH2, grad + kOW2, grad + kOB2, B, kNH,
+                                        kNH, st));
+  HIP_TRY(launch_linear_backward_input(sc.dH2, th + kOW2, sc.H1, sc.dH1, B, kNH, kNH, st));
+  return launch_linear_backward_weight(X, kNI, sc.dH1, grad + kOW1, grad + kOB1, B, kNI, kNH,
+                                       st);
+}
+
+// The 64-column sketch of A (in A's precision), its fp64 Gram and the
+// features.  Omega's columns are the leading columns of the method's sketch.
+hipError_t feature_sketch(Ctx& c, const void* A, int64_t m, int64_t n, int64_t lda, int k,
+                          uint64_t seed, void* om, void* y64, double* g64, float* feat) {
+  HIP_TRY(launch_gaussian(om, m, kPredCols, m, seed, 0, c.dt, c.st));
+  HIP_TRY(gemm(c, 1, A, lda, om, m, y64, n, n, kPredCols, m, c.dt, c.dt, false));
+  HIP_TRY(gemm(c, 1, y64, n, y64, n, g64, kPredCols, kPredCols, kPredCols, n, c.dt, DT_F64,
+               true));
+  return launch_features(g64, kPredCols, k, feat, c.st);
+}
+
+// Features -> MLP -> predicted class (read back to the host).
+hipError_t predict_q(Ctx& c, const FactorArgs& f, int k, const float* params, int* cls) {
+  float* mlp = c.at<float>(c.lay.mlp);
+  int* dcls = c.at<int>(c.lay.cls);
+  HIP_TRY(feature_sketch(c, f.A, f.m, f.n, f.lda, k, c.seed, c.ws + c.lay.om64,
+                         c.ws + c.lay.y64, c.at<double>(c.lay.g64), c.at<float>(c.lay.feat)));
+  HIP_TRY(mlp_forward_dev(params, c.at<float>(c.lay.feat), 1, mlp, mlp + kNH, mlp + 2 * kNH,
+                          c.st));
+  HIP_TRY(launch_argmax(mlp + 2 * kNH, kNC, dcls, c.st));
+  HIP_TRY(hipMemcpyAsync(cls, dcls, sizeof(int), hipMemcpyDeviceToHost, c.st));
+  return hipStreamSynchronize(c.st);
+}
+
+// Error judge after a run with q_hat rounds: sums = {||A||^2, ||L||^2,
+// ||(I - Q Q^T) A P||^2}; Zm keeps Z = A P (the next round's product).
+hipError_t judge(Ctx& c, const FactorArgs& f, double sums[3]) {
+  const int64_t m = f.m, d = c.d;
+  void* Zm = c.ws + c.lay.m1;
+  void* Tm = c.ws + c.lay.m2;
+  void* C1 = c.ws + c.lay.jd;
+  double* scr = c.at<double>(c.lay.sums);
+  double* res = c.at<double>(c.lay.sres);
+  HIP_TRY(launch_sumsq(f.A, f.lda, nullptr, 0, f.m, f.n, c.dt, scr, res, c.st));
+  HIP_TRY(launch_sumsq(f.L, f.ldl, nullptr, 0, d, d, DT_F64, scr, res + 1, c.st));
+  HIP_TRY(prod(c, f, 0, f.P, f.ldp, Zm, m, true));                             // Z = A P
+  HIP_TRY(gemm(c, 1, f.Q, f.ldq, Zm, m, C1, d, d, d, m, c.dt, c.dt, false));   // Q^T Z
+  HIP_TRY(gemm(c, 0, f.Q, f.ldq, C1, d, Tm, m, m, d, d, c.dt, c.dt, false));   // Q Q^T Z
+  HIP_TRY(launch_sumsq(Zm, m, Tm, m, m, d, c.dt, scr, res + 2, c.st));
+  HIP_TRY(hipMemcpyAsync(sums, res, 3 * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  return hipStreamSynchronize(c.st);
+}
+
+// Continue from Z = A Qbar_{j} in Zm with `more` further full rounds, then
+// finish (more = 0: Q = orth(Z) is the final range basis).
+hipError_t resume(Ctx& c, const FactorArgs& f, PanelMode mode, int more) {
+  const int64_t m = f.m, n = f.n;
+  void* Zm = c.ws + c.lay.m1;
+  void* Tm = c.ws + c.lay.m2;
+  void* Yn = c.ws + c.lay.n1;
+  void* Tn = c.ws + c.lay.n2;
+  HIP_TRY(hipMemsetAsync(c.flags(), 0, c.lay.flags_bytes, c.st));
+  if (more == 0) return stage_finish_from_z(c, f, mode);
+  HIP_TRY(orth(c, Zm, m, m, Zm, m, Tm, nullptr, mode, false));                 // Q
+  HIP_TRY(prod(c, f, 1, Zm, m, Yn, n));                                        // A^T Q
+  HIP_TRY(orth(c, Yn, n, n, Yn, n, Tn, nullptr, mode, false));                 // Qbar
+  HIP_TRY(stage_rounds(c, f, mode, more - 1));
+  return stage_finish(c, f, mode);
+}
+
+uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+
+int64_t gcd64(int64_t a, int64_t b) {
+  while (b) {
+    const int64_t t = a % b;
+    a = b;
+    b = t;
   }
+  return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+rqlp_status randqlp_factor(const void* A, int64_t m, int64_t n, int k, int p, int q,
+                           uint64_t seed, void* Q, void* L, void* P, const rqlp_opts* opts) {
+  Ctx c;
+  FactorArgs f;
+  rqlp_opts o;
+  std::unique_lock<std::mutex> lk;
+  rqlp_status s = setup_factor(A, m, n, k, p, q, seed, Q, L, P, opts, false, c, f, o, lk);
+  if (s != RQLP_OK) return s;
+  Outcome r;
+  if ((s = run_with_escalation(c, f, o, start_mode(o), r)) != RQLP_OK) return s;
+  fill_info(o, c.d, q, r);
   g_last_error.clear();
+  return RQLP_OK;
+}
+
+rqlp_status randqlp_factor_auto(const void* A, int64_t m, int64_t n, int k, int p,
+                                int q_fallback, uint64_t seed, const float* params, void* Q,
+                                void* L, void* P, const rqlp_opts* opts,
+                                rqlp_auto_info* ainfo) {
+  if (!params) return fail(RQLP_E_INVALID_ARG, "null predictor parameters");
+  Ctx c;
+  FactorArgs f;
+  rqlp_opts o;
+  std::unique_lock<std::mutex> lk;
+  rqlp_status s =
+      setup_factor(A, m, n, k, p, q_fallback, seed, Q, L, P, opts, true, c, f, o, lk);
+  if (s != RQLP_OK) return s;
+  rqlp_auto_info ai;
+  std::memset(&ai, 0, sizeof ai);
+  int cls = 0;
+  hipError_t e = predict_q(c, f, k, params, &cls);
+  if (e != hipSuccess) return fail(RQLP_E_HIP, "predictor: %s", hipGetErrorString(e));
+  ai.q_predicted = cls;
+  Outcome r;
+  int q_used = q_fallback;
+  bool done = false;
+  const PanelMode mode0 = start_mode(o);
+  if (cls < q_fallback) {
+    // the method with q_hat, then the judge
+    f.q = cls;
+    c.orth_calls = 0;
+    e = hipMemsetAsync(c.flags(), 0, c.lay.flags_bytes, c.st);
+    if (e == hipSuccess) e = stage_start(c, f, mode0);
+    if (e == hipSuccess) e = stage_rounds(c, f, mode0, cls);
+    if (e == hipSuccess) e = stage_finish(c, f, mode0);
+    double sums[3] = {0, 0, 0};
+    if (e == hipSuccess) e = judge(c, f, sums);
+    if (e != hipSuccess) return fail(RQLP_E_HIP, "launch failed: %s", hipGetErrorString(e));
+    int fl[4] = {0, 0, 0, 0};
+    if ((s = read_flags(c, fl)) != RQLP_OK) return s;
+    const bool clean = (fl[0] & (FLAG_NONPOS_PIVOT | FLAG_NONFINITE | FLAG_SECOND_PASS)) == 0;
+    if (clean) {
+      const double e2 = sums[0] - sums[1], delta = sums[2];
+      ai.judged = 1;
+      ai.judge_ratio = e2 > 0.0 ? delta / e2 : (delta > 0.0 ? 1e300 : 0.0);
+      ai.est_rel_err = sums[0] > 0.0 ? std::sqrt(std::max(0.0, e2 / sums[0])) : 0.0;
+      if (ai.judge_ratio <= kJudgeSlack) {
+        q_used = cls;
+        r.completed = fl[2];
+        done = true;
+      } else {
+        // resume from Z = A P = A Qbar_{q_hat + 1} up to q_fallback
+        ai.resumed = 1;
+        f.q = q_fallback;
+        e = resume(c, f, mode0, q_fallback - (cls + 1));
+        if (e != hipSuccess) return fail(RQLP_E_HIP, "launch failed: %s", hipGetErrorString(e));
+        if ((s = read_flags(c, fl)) != RQLP_OK) return s;
+        if ((fl[0] & (FLAG_NONPOS_PIVOT | FLAG_NONFINITE | FLAG_SECOND_PASS)) == 0) {
+          r.completed = fl[2];
+          done = true;
+        }
+      }
+    }
+  }
+  if (!done) {
+    // q_hat >= q_fallback, or a panel needed the stronger treatment:
+    // the plain method with q_fallback (escalating as randqlp_factor does)
+    f.q = q_fallback;
+    q_used = q_fallback;
+    if ((s = run_with_escalation(c, f, o, mode0, r)) != RQLP_OK) return s;
+  }
+  ai.q_used = q_used;
+  fill_info(o, c.d, q_used, r);
+  if (ainfo) *ainfo = ai;
+  g_last_error.clear();
+  return RQLP_OK;
+}
+
+rqlp_status randqlp_features(const void* A, int64_t m, int64_t n, int64_t lda, int k,
+                             uint64_t seed, int precision, float* feat, void* stream) {
+  if (m < 1 || n < 1 || !A || !feat || lda < m || k < 1)
+    return fail(RQLP_E_INVALID_ARG, "bad size, pointer, leading dimension or k");
+  if (precision != RQLP_F64 && precision != RQLP_F32)
+    return fail(RQLP_E_INVALID_ARG, "unknown precision %d", precision);
+  const Dtype dt = precision == RQLP_F64 ? DT_F64 : DT_F32;
+  const size_t es = elem_size(dt);
+  const size_t part = std::max(gemm_partial_bytes(1, n, kPredCols, m, dt, dt, false),
+                               gemm_partial_bytes(1, kPredCols, kPredCols, n, dt, DT_F64, true));
+  const size_t o_om = 0, o_y = align_up((size_t)m * kPredCols * es);
+  const size_t o_g = o_y + align_up((size_t)n * kPredCols * es);
+  const size_t o_p = o_g + align_up((size_t)kPredCols * kPredCols * 8);
+  rqlp_opts o;
+  rqlp_opts_default(&o);
+  std::unique_lock<std::mutex> lk;
+  char* ws = nullptr;
+  rqlp_status s = acquire_ws(o, o_p + std::max<size_t>(part, 256), &ws, lk);
+  if (s != RQLP_OK) return s;
+  Ctx c;
+  c.st = (hipStream_t)stream;
+  c.dt = dt;
+  c.ws = ws;
+  c.lay.part = o_p;
+  c.lay.part_bytes = part;
+  hipError_t e = feature_sketch(c, A, m, n, lda, k, seed, ws + o_om, ws + o_y,
+                                (double*)(ws + o_g), feat);
+  if (e == hipSuccess) e = hipStreamSynchronize(c.st);
+  if (e != hipSuccess) return fail(RQLP_E_HIP, "features: %s", hipGetErrorString(e));
+  return RQLP_OK;
+}
+
+rqlp_status randqlp_mlp_forward(const float* params, const float* X, int B, float* logits,
+                                void* stream) {
+  if (!params || !X || !logits || B < 1)
+    return fail(RQLP_E_INVALID_ARG, "bad pointer or batch size");
+  rqlp_opts o;
+  rqlp_opts_default(&o);
+  std::unique_lock<std::mutex> lk;
+  char* ws = nullptr;
+  rqlp_status s = acquire_ws(o, 2 * align_up((size_t)B * kNH * 4), &ws, lk);
+  if (s != RQLP_OK) return s;
+  float* H1 = (float*)ws;
+  float* H2 = (float*)(ws + align_up((size_t)B * kNH * 4));
+  const hipStream_t st = (hipStream_t)stream;
+  hipError_t e = mlp_forward_dev(params, X, B, H1, H2, logits, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(RQLP_E_HIP, "mlp forward: %s", hipGetErrorString(e));
+  return RQLP_OK;
+}
+
+rqlp_status randqlp_mlp_loss_grad(const float* params, const float* X, const int* y, int B,
+                                  float* grad, float* loss, void* stream) {
+  if (!params || !X || !y || !grad || !loss || B < 1)
+    return fail(RQLP_E_INVALID_ARG, "bad pointer or batch size");
+  rqlp_opts o;
+  rqlp_opts_default(&o);
+  std::unique_lock<std::mutex> lk;
+  char* ws = nullptr;
+  MlpScratch sc;
+  rqlp_status s = acquire_ws(o, mlp_scratch_bytes(B, 0), &ws, lk);
+  if (s != RQLP_OK) return s;
+  mlp_scratch_map(ws, B, 0, sc);
+  const hipStream_t st = (hipStream_t)stream;
+  hipError_t e = mlp_loss_grad_dev(params, X, y, B, sc, grad, loss, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(RQLP_E_HIP, "mlp gradient: %s", hipGetErrorString(e));
+  return RQLP_OK;
+}
+
+rqlp_status randqlp_mlp_adam(float* params, const float* grad, float* m, float* v, int64_t t,
+                             float lr, void* stream) {
+  if (!params || !grad || !m || !v || t < 1 || !(lr > 0.0f))
+    return fail(RQLP_E_INVALID_ARG, "bad pointer, step or learning rate");
+  hipError_t e = launch_adam(params, grad, m, v, kNParams, lr, 0.9f, 0.999f, 1e-8f, t,
+                             (hipStream_t)stream);
+  if (e != hipSuccess) return fail(RQLP_E_HIP, "adam: %s", hipGetErrorString(e));
+  return RQLP_OK;
+}
+
+rqlp_status randqlp_mlp_train(float* params, float* m, float* v, const float* X, const int* y,
+                              int64_t N, int epochs, int batch, float lr, uint64_t seed,
+                              int64_t* step, float* epoch_loss, void* stream) {
+  if (!params || !m || !v || !X || !y || !step || !epoch_loss || N < 1 || N >= (1ll << 31) ||
+      epochs < 0 || batch < 1 || !(lr > 0.0f) || *step < 0)
+    return fail(RQLP_E_INVALID_ARG, "bad pointer, size, batch, step or learning rate");
+  const int64_t steps = (N + batch - 1) / batch;
+  rqlp_opts o;
+  rqlp_opts_default(&o);
+  std::unique_lock<std::mutex> lk;
+  char* ws = nullptr;
+  rqlp_status s = acquire_ws(o, mlp_scratch_bytes(batch, steps), &ws, lk);
+  if (s != RQLP_OK) return s;
+  MlpScratch sc;
+  mlp_scratch_map(ws, batch, steps, sc);
+  const hipStream_t st = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  for (int ep = 0; ep < epochs && e == hipSuccess; ++ep) {
+    // visiting order i -> (a i + c) mod N, a coprime to N
+    uint64_t h = splitmix64(seed ^ (0x9E3779B97F4A7C15ull * (uint64_t)(ep + 1)));
+    int64_t a = (int64_t)(h % (uint64_t)N);
+    if (a == 0) a = 1;
+    while (gcd64(a, N) != 1) a = (a + 1) % N == 0 ? 1 : a + 1;
+    const int64_t cc = (int64_t)(splitmix64(h) % (uint64_t)N);
+    for (int64_t it = 0; it < steps && e == hipSuccess; ++it) {
+      const int64_t start = it * batch;
+      const int B = (int)std::min<int64_t>(batch, N - start);
+      e = launch_gather(X, y, N, a, cc, start, B, kNI, sc.Xb, sc.yb, st);
+      if (e == hipSuccess) e = mlp_loss_grad_dev(params, sc.Xb, sc.yb, B, sc, sc.grad,
+                                                 sc.step_loss + it, st);
+      if (e == hipSuccess)
+        e = launch_adam(params, sc.grad, m, v, kNParams, lr, 0.9f, 0.999f, 1e-8f, ++*step, st);
+    }
+    if (e == hipSuccess) e = launch_sum(sc.step_loss, steps, 1.0f / (float)steps, epoch_loss + ep, st);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return fail(RQLP_E_HIP, "mlp training: %s", hipGetErrorString(e));
   return RQLP_OK;
 }
 

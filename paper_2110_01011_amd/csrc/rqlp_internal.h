@@ -149,4 +149,29 @@ hipError_t launch_count_flags(const int* col_flags, int64_t d, int* count, hipSt
 hipError_t launch_check_finite(const void* A, int64_t m, int64_t n, int64_t lda, Dtype dt,
                                int* flags, hipStream_t st);
 
+// ---- learned.hip ----
+// Predictor features (65 floats) from the fp64 Gram G (64 x 64, ldg) of the
+// 64-column sketch; one workgroup.
+hipError_t launch_features(const double* G, int64_t ldg, int k, float* feat, hipStream_t st);
+// MLP layers (fp32, activations row-major, W column-major fan_in x fan_out).
+hipError_t launch_linear_forward(const float* X, int ldx, const float* W, const float* bias,
+                                 float* Y, int B, int nin, int nout, bool relu, hipStream_t st);
+hipError_t launch_softmax_xent(const float* Z, const int* y, int B, int C, float* dZ,
+                               float* loss, hipStream_t st);
+hipError_t launch_linear_backward_input(const float* dY, const float* W, const float* H,
+                                        float* dX, int B, int nin, int nout, hipStream_t st);
+hipError_t launch_linear_backward_weight(const float* X, int ldx, const float* dY, float* dW,
+                                         float* db, int B, int nin, int nout, hipStream_t st);
+hipError_t launch_adam(float* theta, const float* g, float* m, float* v, int64_t count, float lr,
+                       float beta1, float beta2, float eps, int64_t t, hipStream_t st);
+hipError_t launch_gather(const float* X, const int* y, int64_t N, int64_t a, int64_t c,
+                         int64_t start, int B, int nin, float* Xb, int* yb, hipStream_t st);
+hipError_t launch_sum(const float* x, int64_t n, float scale, float* out, hipStream_t st);
+hipError_t launch_argmax(const float* Z, int C, int* out, hipStream_t st);
+// ||X||_F^2 or ||X - Y||_F^2 (Y may be null) in fp64, deterministic order;
+// scratch holds sumsq_scratch_bytes().
+size_t sumsq_scratch_bytes();
+hipError_t launch_sumsq(const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t rows,
+                        int64_t cols, Dtype dt, double* scratch, double* out, hipStream_t st);
+
 }  // namespace rqlp

@@ -1,0 +1,183 @@
+"""GPU checks of the learned power-iteration predictor and the error judge:
+features, MLP forward / gradient / Adam against the fp64 numpy oracle, and
+randqlp_factor_auto with forced predictions against the oracle method."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import mlp, randqlp
+from oracle.learned import sketch_features
+from tests.gpu_util import compare, invariants, log, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def rq():
+    import paper_2110_01011_amd as rq
+    rq.lib()
+    return rq
+
+
+def _t(x, dtype=None):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).to(dtype or torch.float32).cuda()
+
+
+@pytest.mark.parametrize("case", ["poly", "exp_fast", "rank5", "small_n", "zero"])
+def test_features_match_oracle(rq, case):
+    """Singular values of A^T Omega[:, :64] via the fp64 Gram and Jacobi vs LAPACK's SVD."""
+    log(f"features {case}")
+    if case == "poly":
+        A, U, s, V = W.poly_decay(700, 500, 0.8, seed=1)
+    elif case == "exp_fast":
+        A, U, s, V = W.exp_decay(600, 400, 400, 5.0, seed=2)
+    elif case == "rank5":
+        A, U, s, V = W.svd_matrix(500, 300, np.array([3.0, 2.0, 1.0, 0.5, 0.1]), seed=3)
+    elif case == "small_n":
+        A, U, s, V = W.poly_decay(400, 40, 1.0, seed=4)
+    else:
+        A = np.zeros((200, 100))
+    k = 17
+    ref = sketch_features(A, k, seed=9)
+    g = to_np(rq.features(to_dev(A), k, 9))
+    log(f"  max diff {np.abs(g - ref).max():.2e}")
+    # sigma ratios >= 1e-6 come out of an fp64 Gram to ~1e-7 in log10 / 6;
+    # exactly-zero singular values are clamped to -1 on both sides
+    assert np.abs(g - ref).max() < 2e-4
+    g32 = to_np(rq.features(to_dev(A, __import__("torch").float32), k, 9))
+    assert np.abs(g32 - ref).max() < 5e-3
+
+
+def _params(seed):
+    th = mlp.init_params(seed)
+    th += 0.05 * np.random.default_rng(seed).standard_normal(th.size)
+    return th
+
+
+def test_mlp_forward_and_gradient_match_oracle(rq):
+    r = np.random.default_rng(0)
+    X = np.clip(r.standard_normal((300, 65)) * 0.4 - 0.3, -1, 1)
+    y = r.integers(0, 6, 300)
+    th = _params(1)
+    Z = to_np(rq.mlp_forward(_t(th), _t(X)))
+    Zo, _ = mlp.forward(th, X)
+    assert np.abs(Z - Zo).max() <= 1e-5 * max(1.0, np.abs(Zo).max())
+    loss, g = rq.mlp_loss_grad(_t(th), _t(X), _t(y, __import__("torch").int32))
+    lo, go = mlp.loss_and_grad(th, X, y)
+    g = to_np(g)
+    log(f"  loss {float(loss.item())} vs {lo}; grad max diff {np.abs(g - go).max():.2e}")
+    assert abs(float(loss.item()) - lo) <= 1e-5 * max(1.0, lo)
+    assert np.abs(g - go).max() <= 1e-5 * max(1e-3, np.abs(go).max())
+
+
+def test_adam_step_matches_oracle(rq):
+    import torch
+    r = np.random.default_rng(2)
+    th = _params(3)
+    g = r.standard_normal(th.size) * 1e-2
+    m0 = r.standard_normal(th.size) * 1e-3
+    v0 = np.abs(r.standard_normal(th.size)) * 1e-5
+    tt, mt, vt = _t(th), _t(m0), _t(v0)
+    rq.mlp_adam(tt, _t(g), mt, vt, 7, 1e-3)
+    torch.cuda.synchronize()
+    to, mo, vo = mlp.adam_step(th, g, m0, v0, 7, 1e-3)
+    assert np.abs(to_np(tt) - to).max() < 1e-6
+    assert np.abs(to_np(mt) - mo).max() < 1e-7
+    assert np.abs(to_np(vt) - vo).max() < 1e-9
+
+
+def test_training_is_deterministic_and_learns(rq):
+    import torch
+    r = np.random.default_rng(5)
+    X = np.clip(r.standard_normal((2000, 65)) * 0.5, -1, 1)
+    y = (X[:, 0] > 0).astype(int) + 2 * (X[:, 1] > 0)
+    res = []
+    for _ in range(2):
+        th = _t(mlp.init_params(0))
+        m = torch.zeros_like(th)
+        v = torch.zeros_like(th)
+        losses, step = rq.mlp_train(th, m, v, _t(X), _t(y, torch.int32), 30, 128, 3e-3, 11)
+        res.append((to_np(th), to_np(losses), step))
+    assert np.array_equal(res[0][0], res[1][0]) and res[0][2] == 30 * 16
+    losses = res[0][1]
+    log(f"  losses {losses[0]:.3f} -> {losses[-1]:.3f}")
+    assert losses[-1] < 0.3 * losses[0]
+    acc = np.mean(mlp.predict(res[0][0].astype(np.float64), X) == y)
+    assert acc > 0.95
+
+
+def _forced(rq, cls):
+    """Parameters whose prediction is `cls` for every input (W3 = 0)."""
+    th = np.zeros(rq.MLP_PARAMS)
+    th[-6:] = -10.0
+    th[-6 + cls] = 10.0
+    return _t(th)
+
+
+def _check_against_oracle(A, Qg, Lg, Pg, k, p, q, seed, tol=TOL):
+    Qo, Lo, Po = randqlp(A, k, p, q, seed)
+    c = compare(A, Qg, Lg, Pg, Qo, Lo, Po, min(k, Lo.shape[0]))
+    inv = invariants(A, Qg, Lg, Pg)
+    log(f"  vs oracle q={q}: {c} {inv}")
+    assert c["de"] <= tol and c["dsigma"] <= tol
+    assert c["sinQk"] <= tol and c["sinPk"] <= tol and c["sinQ"] <= tol and c["sinP"] <= tol
+    assert inv["orthQ"] < 1e-12 and inv["orthP"] < 1e-12
+    assert inv["upper_max"] == 0.0 and inv["min_diag"] >= 0.0
+
+
+@pytest.mark.parametrize("q_fb", [2, 3])
+def test_judge_resumes_when_forced_zero_on_slow_decay(rq, q_fb):
+    """q forced to 0 on a slowly decaying spectrum: the judge sees one more
+    round still lowering the residual, resumes, and the result is the
+    q = q_fallback method."""
+    A, U, s, V = W.poly_decay(900, 700, 0.6, seed=6)
+    k, p, seed = 30, 5, 4
+    Qg, Lg, Pg, info, ai = rq.factor_auto(to_dev(A), k, p, seed, _forced(rq, 0), q_fallback=q_fb,
+                                          return_info=True)
+    log(f"  auto info {ai} {info}")
+    assert ai["q_predicted"] == 0 and ai["judged"] == 1 and ai["resumed"] == 1
+    assert ai["q_used"] == q_fb and info["q_used"] == q_fb
+    assert ai["judge_ratio"] > 0.0404
+    _check_against_oracle(A, to_np(Qg), to_np(Lg), to_np(Pg), k, p, q_fb, seed)
+
+
+def test_judge_accepts_when_converged(rq):
+    """Rank k plus a flat noise floor: q = 0 already captures the signal and
+    more rounds cannot pick better noise directions, so the judge accepts
+    and the result is the q = 0 method.  (The floor is 1e-3 of sigma_1: the
+    trailing sketch directions then carry rounding at ~1e-13, inside the
+    1e-10 subspace tolerance.)"""
+    sig = np.concatenate([np.linspace(2.0, 1.0, 20), 1e-3 * np.ones(380)])
+    A, U, s, V = W.svd_matrix(800, 400, sig, seed=7)
+    k, p, seed = 20, 8, 2
+    Qg, Lg, Pg, info, ai = rq.factor_auto(to_dev(A), k, p, seed, _forced(rq, 0), return_info=True)
+    log(f"  auto info {ai}")
+    assert ai["judged"] == 1 and ai["resumed"] == 0 and ai["q_used"] == 0
+    assert ai["judge_ratio"] <= 0.0404
+    _check_against_oracle(A, to_np(Qg), to_np(Lg), to_np(Pg), k, p, 0, seed)
+
+
+def test_prediction_at_or_above_fallback_runs_fixed_q(rq):
+    A, U, s, V = W.fast_decay(500, 400, seed=8)
+    for cls in (2, 5):
+        Qg, Lg, Pg, info, ai = rq.factor_auto(to_dev(A), 15, 5, 3, _forced(rq, cls),
+                                              return_info=True)
+        assert ai["q_predicted"] == cls and ai["judged"] == 0 and ai["q_used"] == 2
+        _check_against_oracle(A, to_np(Qg), to_np(Lg), to_np(Pg), 15, 5, 2, 3)
+
+
+def test_judge_in_precision_form(rq):
+    """bf16 form, forced q = 0: on the slow decay the judge resumes, and the
+    error stays within 1.05x the fp64 oracle's at q_fallback = 2."""
+    import torch
+    from oracle import rel_error
+    A, U, s, V = W.poly_decay(1500, 1200, 0.6, seed=9)
+    Qg, Lg, Pg, info, ai = rq.factor_auto(to_dev(A, torch.float32), 40, 10, 1, _forced(rq, 0),
+                                          precision="bf16", return_info=True)
+    log(f"  bf16 auto info {ai}")
+    assert ai["resumed"] == 1 and ai["q_used"] == 2
+    e_g = rel_error(A, to_np(Qg), to_np(Lg), to_np(Pg))
+    e_o = rel_error(A, *randqlp(A, 40, 10, 2, 1))
+    assert e_g <= 1.05 * e_o
