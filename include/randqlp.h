@@ -217,6 +217,64 @@ rqlp_status randqlp_mlp_train(float* params, float* m, float* v, const float* X,
                               int64_t N, int epochs, int batch, float lr, uint64_t seed,
                               int64_t* step, float* epoch_loss, void* stream);
 
+/* ---- Batched form ----
+ * Many independent matrices of different shapes factored together: every
+ * step of the method runs as one grouped launch over all matrices (one
+ * workgroup list per step, built once per plan), and the sequence is
+ * captured into a HIP graph that randqlp_batch_run replays.  Matrix i is
+ * A[i] (m[i] x n[i], lda[i]) -> Q[i] (m x d_i, ldq[i]), L[i] (d_i x d_i,
+ * double, ldl[i]), P[i] (n x d_i, ldp[i]) with d_i = min(k[i] + p, m, n),
+ * sketch seed seeds[i]; pointer arrays are host arrays of device pointers
+ * (any ld array may be NULL for tight).  precision: RQLP_F64 or RQLP_F32
+ * (A, Q, P of that type).  The plan binds these pointers: a run reads the
+ * current contents of A and overwrites Q, L, P.  Panels use fast Cholesky
+ * QR; a matrix whose panel reports an unsafe pivot, or whose d_i exceeds
+ * the one-workgroup Cholesky limit (224), is refactored on its own with
+ * randqlp_factor after the grouped run.  tune != 0 times the candidate tile
+ * widths of the products with A on this batch and records the fastest in
+ * the process-wide table (see randqlp_tune_save); tune = 0 takes the table's
+ * entry, else a width covering the median d.  The plan owns its device
+ * memory (allocated here, freed by randqlp_batch_destroy). */
+typedef struct rqlp_batch rqlp_batch;
+
+typedef struct {
+  int32_t count;      /* matrices in the plan                           */
+  int32_t grouped;    /* of those, factored by the grouped launches      */
+  int32_t fallbacks;  /* refactored one by one in the last run           */
+  int32_t wn_tn;      /* tile width (16-column blocks per wave) of A^T X */
+  int32_t wn_nn;      /* tile width of A X                               */
+  int32_t dmax;       /* largest d among the grouped matrices            */
+  double tune_ms;     /* time spent tuning at creation                   */
+} rqlp_batch_info;
+
+rqlp_status randqlp_batch_create(int count, const void* const* A, const int64_t* m,
+                                 const int64_t* n, const int64_t* lda, const int* k, int p, int q,
+                                 const uint64_t* seeds, void* const* Q, const int64_t* ldq,
+                                 void* const* L, const int64_t* ldl, void* const* P,
+                                 const int64_t* ldp, int precision, int tune,
+                                 rqlp_batch** plan);
+
+/* Run the plan on `stream` (use_graph != 0: replay the captured graph; 0:
+ * launch the same sequence directly), then refactor any flagged matrix on
+ * its own.  Synchronous. */
+rqlp_status randqlp_batch_run(rqlp_batch* plan, int use_graph, void* stream);
+
+rqlp_status randqlp_batch_query(const rqlp_batch* plan, rqlp_batch_info* info);
+
+void randqlp_batch_destroy(rqlp_batch* plan);
+
+/* create (tight leading dimensions, no tuning) + run + destroy. */
+rqlp_status randqlp_factor_batched(int count, const void* const* A, const int64_t* m,
+                                   const int64_t* n, const int* k, int p, int q,
+                                   const uint64_t* seeds, void* const* Q, void* const* L,
+                                   void* const* P, int precision, void* stream);
+
+/* The tile-width table: text lines "dtype trans dbucket wn" (dtype 0 = f64,
+ * 1 = f32; trans 1 = A^T X, 0 = A X; dbucket = 32, 64, 128 or 256, the
+ * bucket of the largest d; wn = 1, 2, 4 or 8).  load merges into the table. */
+rqlp_status randqlp_tune_save(const char* path);
+rqlp_status randqlp_tune_load(const char* path);
+
 /* ---- Diagnostics ---- */
 
 /* When on != 0, randqlp_factor records HIP events on its stream around each

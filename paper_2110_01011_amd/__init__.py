@@ -12,7 +12,7 @@ Matrices are column-major: a tensor of shape (rows, cols) with stride
 import ctypes
 import os
 
-__all__ = ["factor", "factor_auto", "features", "mlp_forward", "mlp_loss_grad", "mlp_adam",
+__all__ = ["factor", "factor_auto", "Batch", "factor_batched", "tune_save", "tune_load", "features", "mlp_forward", "mlp_loss_grad", "mlp_adam",
            "mlp_train", "gaussian", "gemm", "orth", "sketch_width", "workspace_size",
            "colmajor", "empty_colmajor", "lib", "RandQLPError", "F64", "F32", "MIXED_BF16",
            "MIXED_F16",
@@ -32,6 +32,9 @@ STATUS = {0: "RQLP_OK", 1: "RQLP_E_INVALID_ARG", 2: "RQLP_E_NONFINITE", 3: "RQLP
 EXPORTS = ["rqlp_opts_default", "randqlp_sketch_width", "randqlp_workspace_size",
            "randqlp_factor", "randqlp_factor_auto", "randqlp_features", "randqlp_mlp_forward",
            "randqlp_mlp_loss_grad", "randqlp_mlp_adam", "randqlp_mlp_train",
+           "randqlp_batch_create", "randqlp_batch_run", "randqlp_batch_query",
+           "randqlp_batch_destroy", "randqlp_factor_batched", "randqlp_tune_save",
+           "randqlp_tune_load",
            "randqlp_gaussian", "randqlp_gemm", "randqlp_orth",
            "randqlp_profile_enable", "randqlp_profile_read",
            "randqlp_status_string", "randqlp_last_error"]
@@ -59,6 +62,15 @@ class AutoInfo(ctypes.Structure):
     _fields_ = [("q_predicted", ctypes.c_int32), ("q_used", ctypes.c_int32),
                 ("judged", ctypes.c_int32), ("resumed", ctypes.c_int32),
                 ("judge_ratio", ctypes.c_double), ("est_rel_err", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("grouped", ctypes.c_int32),
+                ("fallbacks", ctypes.c_int32), ("wn_tn", ctypes.c_int32),
+                ("wn_nn", ctypes.c_int32), ("dmax", ctypes.c_int32), ("tune_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -107,6 +119,25 @@ def lib():
     L.randqlp_mlp_train.argtypes = [vp, vp, vp, vp, vp, i64, i32, i32, ctypes.c_float, u64,
                                     ctypes.POINTER(i64), vp, vp]
     L.randqlp_mlp_train.restype = i32
+    P64 = ctypes.POINTER(i64)
+    PVP = ctypes.POINTER(vp)
+    L.randqlp_batch_create.argtypes = [i32, PVP, P64, P64, P64, ctypes.POINTER(i32), i32, i32,
+                                       ctypes.POINTER(u64), PVP, P64, PVP, P64, PVP, P64, i32, i32,
+                                       ctypes.POINTER(vp)]
+    L.randqlp_batch_create.restype = i32
+    L.randqlp_batch_run.argtypes = [vp, i32, vp]
+    L.randqlp_batch_run.restype = i32
+    L.randqlp_batch_query.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+    L.randqlp_batch_query.restype = i32
+    L.randqlp_batch_destroy.argtypes = [vp]
+    L.randqlp_batch_destroy.restype = None
+    L.randqlp_factor_batched.argtypes = [i32, PVP, P64, P64, ctypes.POINTER(i32), i32, i32,
+                                         ctypes.POINTER(u64), PVP, PVP, PVP, i32, vp]
+    L.randqlp_factor_batched.restype = i32
+    L.randqlp_tune_save.argtypes = [ctypes.c_char_p]
+    L.randqlp_tune_save.restype = i32
+    L.randqlp_tune_load.argtypes = [ctypes.c_char_p]
+    L.randqlp_tune_load.restype = i32
     L.randqlp_gaussian.argtypes = [vp, i64, i64, i64, u64, u64, i32, vp]
     L.randqlp_gaussian.restype = i32
     L.randqlp_gemm.argtypes = [i32, vp, i64, i64, i64, vp, i64, i64, vp, i64, i32, vp]
@@ -346,6 +377,90 @@ def mlp_train(params, m, v, X, y, epochs, batch, lr, seed, step=0):
                                    X.shape[0], epochs, batch, float(lr), seed, ctypes.byref(st),
                                    ctypes.c_void_p(losses.data_ptr()), _stream_ptr(X.device)))
     return losses[:epochs], st.value
+
+
+class Batch:
+    """A batched plan over device matrices As (float64 or float32, one dtype):
+    outputs self.Q, self.L, self.P (lists of column-major tensors) are
+    allocated here and bound to the plan together with As; run() replays the
+    captured graph.  Keep the object alive while the plan is used."""
+
+    def __init__(self, As, ks, p, q, seeds, tune=False):
+        torch = _torch()
+        if not As:
+            raise ValueError("empty batch")
+        self.A = [colmajor(a) for a in As]
+        dtype = self.A[0].dtype
+        if any(a.dtype != dtype for a in self.A):
+            raise TypeError("all matrices must share one dtype")
+        cnt = len(self.A)
+        dev = self.A[0].device
+        self.Q, self.L, self.P = [], [], []
+        for a, k in zip(self.A, ks):
+            m, n = a.shape
+            d = sketch_width(m, n, k, p)
+            if d < 1:
+                raise ValueError("bad k or p")
+            self.Q.append(empty_colmajor(m, d, dtype, dev))
+            self.L.append(empty_colmajor(d, d, torch.float64, dev))
+            self.P.append(empty_colmajor(n, d, dtype, dev))
+        vp, i64 = ctypes.c_void_p, ctypes.c_int64
+        arr = lambda T, xs: (T * cnt)(*xs)
+        self._keep = [
+            arr(vp, [t.data_ptr() for t in self.A]),
+            arr(i64, [t.shape[0] for t in self.A]), arr(i64, [t.shape[1] for t in self.A]),
+            arr(i64, [_ld(t) for t in self.A]), arr(ctypes.c_int32, list(ks)),
+            arr(ctypes.c_uint64, list(seeds)),
+            arr(vp, [t.data_ptr() for t in self.Q]), arr(i64, [_ld(t) for t in self.Q]),
+            arr(vp, [t.data_ptr() for t in self.L]), arr(i64, [_ld(t) for t in self.L]),
+            arr(vp, [t.data_ptr() for t in self.P]), arr(i64, [_ld(t) for t in self.P])]
+        k_ = self._keep
+        h = ctypes.c_void_p()
+        with torch.cuda.device(dev):
+            _check(lib().randqlp_batch_create(cnt, k_[0], k_[1], k_[2], k_[3], k_[4], p, q, k_[5],
+                                              k_[6], k_[7], k_[8], k_[9], k_[10], k_[11],
+                                              _precision(dtype), 1 if tune else 0,
+                                              ctypes.byref(h)))
+        self._h = h
+        self.device = dev
+
+    def run(self, use_graph=True):
+        _check(lib().randqlp_batch_run(self._h, 1 if use_graph else 0, _stream_ptr(self.device)))
+        return self.Q, self.L, self.P
+
+    def info(self):
+        i = BatchInfo()
+        _check(lib().randqlp_batch_query(self._h, ctypes.byref(i)))
+        return i.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().randqlp_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def factor_batched(As, ks, p, q, seeds, tune=False):
+    """Factor a list of device matrices together; returns (Qs, Ls, Ps, info)."""
+    b = Batch(As, ks, p, q, seeds, tune=tune)
+    try:
+        Q, L, P = b.run()
+        return Q, L, P, b.info()
+    finally:
+        b.close()
+
+
+def tune_save(path):
+    _check(lib().randqlp_tune_save(str(path).encode()))
+
+
+def tune_load(path):
+    _check(lib().randqlp_tune_load(str(path).encode()))
 
 
 def gaussian(m, d, seed, stream_id=0, dtype=None, device="cuda"):

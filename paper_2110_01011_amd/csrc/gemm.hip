@@ -12,6 +12,7 @@
 // contraction.  Partial sums are reduced in a fixed order (bitwise
 // reproducible).  Gram products compute only upper tiles and mirror them.
 #include <algorithm>
+#include <vector>
 
 #include "rqlp_internal.h"
 
@@ -37,10 +38,12 @@ struct Mfma<float> {
 
 template <typename TI, typename TC, typename TO, bool TA, int WAVES_M, int WAVES_N, int WM,
           int WN, int BK>
-__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(
-    const TI* __restrict__ A, int64_t lda, const TI* __restrict__ B, int64_t ldb,
-    TO* __restrict__ C, int64_t ldc, int64_t strideS, int64_t M, int64_t N, int64_t K,
-    int64_t kchunk, int gram) {
+__device__ __forceinline__ void gemm_body(const TI* __restrict__ A, int64_t lda,
+                                          const TI* __restrict__ B, int64_t ldb,
+                                          TO* __restrict__ C, int64_t ldc, int64_t strideS,
+                                          int64_t M, int64_t N, int64_t K, int64_t kchunk,
+                                          int gram, const int tile_m, const int tile_n,
+                                          const int split) {
   constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int BM = 16 * WM * WAVES_M;
   constexpr int BN = 16 * WN * WAVES_N;
@@ -53,7 +56,6 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(
   __shared__ TI As[2][BK][LA];
   __shared__ TI Bs[2][BK][LB];
 
-  const int tile_m = blockIdx.x, tile_n = blockIdx.y, split = blockIdx.z;
   if (gram && tile_m > tile_n) return;  // whole workgroup leaves together
   const int64_t i0 = (int64_t)tile_m * BM, j0 = (int64_t)tile_n * BN;
   const int64_t kbeg = (int64_t)split * kchunk;
@@ -161,6 +163,30 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(
         if (row < M && col < N) Cs[row + col * ldc] = (TO)acc[a][b][r];
       }
     }
+}
+
+template <typename TI, typename TC, typename TO, bool TA, int WAVES_M, int WAVES_N, int WM,
+          int WN, int BK>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(
+    const TI* __restrict__ A, int64_t lda, const TI* __restrict__ B, int64_t ldb,
+    TO* __restrict__ C, int64_t ldc, int64_t strideS, int64_t M, int64_t N, int64_t K,
+    int64_t kchunk, int gram) {
+  gemm_body<TI, TC, TO, TA, WAVES_M, WAVES_N, WM, WN, BK>(A, lda, B, ldb, C, ldc, strideS, M, N,
+                                                          K, kchunk, gram, blockIdx.x,
+                                                          blockIdx.y, blockIdx.z);
+}
+
+// Grouped form: workgroup b computes tile (bmap[b].y, bmap[b].z) of product
+// descs[bmap[b].x] over its whole contraction (no split).
+template <typename TI, typename TC, typename TO, bool TA, int WAVES_M, int WAVES_N, int WM,
+          int WN, int BK>
+__global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_grouped_kernel(
+    const GroupGemm* __restrict__ descs, const int4* __restrict__ bmap) {
+  const int4 b = bmap[blockIdx.x];
+  const GroupGemm g = descs[b.x];
+  gemm_body<TI, TC, TO, TA, WAVES_M, WAVES_N, WM, WN, BK>(
+      (const TI*)g.A, g.lda, (const TI*)g.B, g.ldb, (TO*)g.C, g.ldc, 0, g.M, g.N, g.K, g.K, 0,
+      b.y, b.z, 0);
 }
 
 // C = sum_s P[s] in split order.  gram_bm > 0: element (i, j) in a lower
@@ -744,6 +770,60 @@ hipError_t launch_convert16(const float* A, int64_t m, int64_t n, int64_t lda, v
   else
     hipLaunchKernelGGL(convert16_kernel<__bf16>, grid, dim3(256), 0, st, A, m, n, lda,
                        (__bf16*)A16, ld16, (__bf16*)At16, ldt16);
+  return hipGetLastError();
+}
+
+namespace {
+
+template <typename TI, typename TC, typename TO, bool TA, int WM, int WN>
+void run_grouped(const GroupGemm* descs, const int4* bmap, int64_t nblocks, hipStream_t st) {
+  hipLaunchKernelGGL((gemm_grouped_kernel<TI, TC, TO, TA, kWavesM, kWavesN, WM, WN, kBK>),
+                     dim3((unsigned)nblocks), dim3(64 * kWavesM * kWavesN), 0, st, descs, bmap);
+}
+
+template <typename T, bool TA>
+void grouped_wn(int wn, const GroupGemm* descs, const int4* bmap, int64_t nblocks,
+                hipStream_t st) {
+  if (wn <= 1) run_grouped<T, T, T, TA, kWM, 1>(descs, bmap, nblocks, st);
+  else if (wn <= 2) run_grouped<T, T, T, TA, kWM, 2>(descs, bmap, nblocks, st);
+  else if (wn <= 4) run_grouped<T, T, T, TA, kWM, 4>(descs, bmap, nblocks, st);
+  else run_grouped<T, T, T, TA, kWM, 8>(descs, bmap, nblocks, st);
+}
+
+}  // namespace
+
+int grouped_wn_round(int wn) { return wn <= 1 ? 1 : wn <= 2 ? 2 : wn <= 4 ? 4 : 8; }
+
+void gemm_grouped_blocks(const GroupGemm& g, int idx, bool gram, int wn,
+                         std::vector<int4>& out) {
+  const int64_t BM = gram ? kGramBM : kBM;
+  const int64_t BN = gram ? 32 : 32 * grouped_wn_round(wn);
+  const int64_t tm = (g.M + BM - 1) / BM, tn = (g.N + BN - 1) / BN;
+  for (int64_t j = 0; j < tn; ++j)
+    for (int64_t i = 0; i < tm; ++i)
+      if (!gram || i >= j) out.push_back(int4{idx, (int)i, (int)j, 0});
+}
+
+hipError_t launch_gemm_grouped(Dtype in_t, Dtype out_t, int trans_a, bool gram, int wn,
+                               const GroupGemm* descs, const int4* bmap, int64_t nblocks,
+                               hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if (gram) {
+    if (in_t == DT_F64)
+      run_grouped<double, double, double, true, kGramWM, 1>(descs, bmap, nblocks, st);
+    else if (out_t == DT_F64)
+      run_grouped<float, double, double, true, kGramWM, 1>(descs, bmap, nblocks, st);
+    else
+      return hipErrorInvalidValue;
+  } else if (in_t != out_t) {
+    return hipErrorInvalidValue;
+  } else if (in_t == DT_F64) {
+    if (trans_a) grouped_wn<double, true>(wn, descs, bmap, nblocks, st);
+    else grouped_wn<double, false>(wn, descs, bmap, nblocks, st);
+  } else {
+    if (trans_a) grouped_wn<float, true>(wn, descs, bmap, nblocks, st);
+    else grouped_wn<float, false>(wn, descs, bmap, nblocks, st);
+  }
   return hipGetLastError();
 }
 

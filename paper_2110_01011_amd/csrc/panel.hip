@@ -256,7 +256,7 @@ __device__ __forceinline__ void chol_tile_wave(
 // (an LDS flag; the owner never waits on wave 0, so the wait always ends);
 // wave 4 shares wave 0's SIMD and stays idle so no MFMA issue competes with
 // the pivot chain; the six other waves hold the tiles.
-__global__ __launch_bounds__(512) void cholesky_kernel(
+__device__ __forceinline__ void cholesky_body(
     const double* __restrict__ G, int d, int64_t ldg, double shift,
     const double* __restrict__ shift_dev, double tol_dep, double tol_warn,
     double* __restrict__ R, int64_t ldr, double* __restrict__ dinv,
@@ -307,6 +307,23 @@ __global__ __launch_bounds__(512) void cholesky_kernel(
   if (tid == 0 && sflag) atomicOr(flags, sflag);
 }
 
+__global__ __launch_bounds__(512) void cholesky_kernel(
+    const double* __restrict__ G, int d, int64_t ldg, double shift,
+    const double* __restrict__ shift_dev, double tol_dep, double tol_warn,
+    double* __restrict__ R, int64_t ldr, double* __restrict__ dinv,
+    int* __restrict__ col_flags, int* __restrict__ flags,
+    const double* __restrict__ odiag_src, int64_t odiag_stride) {
+  cholesky_body(G, d, ldg, shift, shift_dev, tol_dep, tol_warn, R, ldr, dinv, col_flags, flags,
+                odiag_src, odiag_stride);
+}
+
+// Grouped form: workgroup i factors problem i.
+__global__ __launch_bounds__(512) void cholesky_grouped_kernel(const GroupChol* __restrict__ descs) {
+  const GroupChol c = descs[blockIdx.x];
+  cholesky_body(c.G, c.d, c.ldg, 0.0, nullptr, c.tol_dep, c.tol_warn, c.R, c.ldr, c.dinv,
+                nullptr, c.flags, nullptr, 0);
+}
+
 // Qx = X R^+ by block forward substitution.  One wave (one workgroup) owns 16
 // rows: for each 16-column block J it forms V_J = X_J - sum_{K<J} Q_K R_KJ
 // with MFMA (A fragments from its finished columns kept in LDS, B fragments
@@ -317,15 +334,14 @@ __global__ __launch_bounds__(512) void cholesky_kernel(
 // and Qx may be the same array (each wave reads a block of its rows before
 // overwriting it).
 template <typename TX, typename TO>
-__global__ __launch_bounds__(64) void trsm_kernel(const TX* X, int64_t rows, int d, int64_t ldx,
-                                                  const double* __restrict__ R, int64_t ldr,
-                                                  const double* __restrict__ dinv, TO* Qx,
-                                                  int64_t ldq) {
+__device__ __forceinline__ void trsm_body(const TX* X, int64_t rows, int d, int64_t ldx,
+                                          const double* __restrict__ R, int64_t ldr,
+                                          const double* __restrict__ dinv, TO* Qx, int64_t ldq,
+                                          const int64_t r0) {
   extern __shared__ double Qw[];
   constexpr int B = 16;
   const int nt = (d + 15) / 16, dp = nt * 16, lq = dp + 1;
   const int lane = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * 16;
   const int li = lane & 15, lk = lane >> 4;
   for (int J = 0; J < nt; ++J) {
     const int kk = 16 * J;
@@ -389,6 +405,24 @@ __global__ __launch_bounds__(64) void trsm_kernel(const TX* X, int64_t rows, int
   }
 }
 
+template <typename TX, typename TO>
+__global__ __launch_bounds__(64) void trsm_kernel(const TX* X, int64_t rows, int d, int64_t ldx,
+                                                  const double* __restrict__ R, int64_t ldr,
+                                                  const double* __restrict__ dinv, TO* Qx,
+                                                  int64_t ldq) {
+  trsm_body<TX, TO>(X, rows, d, ldx, R, ldr, dinv, Qx, ldq, (int64_t)blockIdx.x * 16);
+}
+
+// Grouped form: workgroup b solves rows 16 bmap[b].y.. of problem bmap[b].x.
+template <typename T>
+__global__ __launch_bounds__(64) void trsm_grouped_kernel(const GroupTrsm* __restrict__ descs,
+                                                          const int2* __restrict__ bmap) {
+  const int2 b = bmap[blockIdx.x];
+  const GroupTrsm t = descs[b.x];
+  trsm_body<T, T>((const T*)t.X, t.rows, t.d, t.ldx, t.R, t.ldr, t.dinv, (T*)t.Qx, t.ldq,
+                  (int64_t)b.y * 16);
+}
+
 // Second Cholesky QR pass to first order.  For a nearly orthonormal Q1 the
 // Gram matrix is G2 = I + E with small E, and chol(I + E) = I + F + O(|E|^2)
 // with F = (strict upper part of E) + diag(E) / 2.  Writes B = I - F (so
@@ -402,7 +436,8 @@ __global__ __launch_bounds__(256) void first_order_pass_kernel(const double* __r
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= (int64_t)d * d) return;
   const int i = (int)(idx % d), j = (int)(idx / d);
-  const double e = G2[idx] - (i == j ? 1.0 : 0.0);
+  // E is symmetric: read it from the lower triangle
+  const double e = (i < j ? G2[j + (int64_t)i * d] : G2[idx]) - (i == j ? 1.0 : 0.0);
   double f = 0.0;
   if (i < j) f = e;
   else if (i == j) f = 0.5 * e;
@@ -518,6 +553,39 @@ __global__ __launch_bounds__(256) void check_finite_kernel(const T* __restrict__
 }
 
 inline unsigned grid_for(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// Grouped first-order pass: one workgroup per problem (see the single form).
+template <typename TB>
+__global__ __launch_bounds__(256) void first_order_grouped_kernel(
+    const GroupFirstOrder* __restrict__ descs) {
+  const GroupFirstOrder g = descs[blockIdx.x];
+  const int d = g.d;
+  int bad = 0;
+  for (int64_t idx = threadIdx.x; idx < (int64_t)d * d; idx += 256) {
+    const int i = (int)(idx % d), j = (int)(idx / d);
+    const double e = (i < j ? g.G2[j + (int64_t)i * d] : g.G2[idx]) - (i == j ? 1.0 : 0.0);
+    double f = 0.0;
+    if (i < j) f = e;
+    else if (i == j) f = 0.5 * e;
+    ((TB*)g.B)[idx] = (TB)((i == j ? 1.0 : 0.0) - f);
+    g.R2[idx] = (i == j ? 1.0 : 0.0) + f;
+    if (!(fabs(e) <= g.tol)) bad = 1;
+  }
+  if (bad) atomicOr(g.flags, FLAG_SECOND_PASS);
+}
+
+__global__ __launch_bounds__(256) void lower_grouped_kernel(const GroupLower* __restrict__ descs) {
+  const GroupLower g = descs[blockIdx.x];
+  for (int64_t idx = threadIdx.x; idx < (int64_t)g.d * g.d; idx += 256) {
+    const int i = (int)(idx % g.d), j = (int)(idx / g.d);
+    g.L[i + j * g.ldl] = (i >= j) ? g.R[j + (int64_t)i * g.d] : 0.0;
+  }
+}
+
+__global__ __launch_bounds__(256) void zero_ints_kernel(int* __restrict__ p, int64_t n) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < n) p[idx] = 0;
+}
 
 }  // namespace
 
@@ -643,6 +711,52 @@ hipError_t launch_check_finite(const void* A, int64_t m, int64_t n, int64_t lda,
   else
     hipLaunchKernelGGL(check_finite_kernel<float>, dim3(g), dim3(256), 0, st, (const float*)A,
                        m, n, lda, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_cholesky_grouped(const GroupChol* descs, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(cholesky_grouped_kernel, dim3(count), dim3(512), 0, st, descs);
+  return hipGetLastError();
+}
+
+void trsm_grouped_blocks(const GroupTrsm& t, int idx, std::vector<int2>& out) {
+  for (int64_t r = 0; r < (t.rows + 15) / 16; ++r) out.push_back(int2{idx, (int)r});
+}
+
+hipError_t launch_trsm_grouped(Dtype dt, const GroupTrsm* descs, const int2* bmap,
+                               int64_t nblocks, int dmax, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  const int dp = (dmax + 15) / 16 * 16;
+  const size_t lds = (size_t)16 * (dp + 1) * sizeof(double);
+  if (dt == DT_F64)
+    hipLaunchKernelGGL(trsm_grouped_kernel<double>, dim3((unsigned)nblocks), dim3(64), lds, st,
+                       descs, bmap);
+  else
+    hipLaunchKernelGGL(trsm_grouped_kernel<float>, dim3((unsigned)nblocks), dim3(64), lds, st,
+                       descs, bmap);
+  return hipGetLastError();
+}
+
+hipError_t launch_first_order_grouped(Dtype dt, const GroupFirstOrder* descs, int count,
+                                      hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  if (dt == DT_F64)
+    hipLaunchKernelGGL(first_order_grouped_kernel<double>, dim3(count), dim3(256), 0, st, descs);
+  else
+    hipLaunchKernelGGL(first_order_grouped_kernel<float>, dim3(count), dim3(256), 0, st, descs);
+  return hipGetLastError();
+}
+
+hipError_t launch_lower_grouped(const GroupLower* descs, int count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(lower_grouped_kernel, dim3(count), dim3(256), 0, st, descs);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_ints_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
   return hipGetLastError();
 }
 

@@ -117,6 +117,31 @@ __global__ __launch_bounds__(256) void gaussian_columns_kernel(T* __restrict__ X
   }
 }
 
+// Grouped form: workgroup b fills the 1024 values starting at
+// 1024 bmap[b].y of sketch bmap[b].x (same values as the single form).
+template <typename T>
+__global__ __launch_bounds__(256) void gaussian_grouped_kernel(const GroupGauss* __restrict__ descs,
+                                                               const int2* __restrict__ bmap) {
+  const int2 b = bmap[blockIdx.x];
+  const GroupGauss g = descs[b.x];
+  const int64_t total = g.m * g.d;
+  const int64_t blk = (int64_t)b.y * 256 + threadIdx.x;
+  const int64_t l0 = blk * 4;
+  if (l0 >= total) return;
+  double z[4];
+  block_normals((uint64_t)blk, g.seed, 0, z);
+  int64_t j = l0 / g.m, i = l0 - j * g.m;
+  T* out = (T*)g.out;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    if (l0 + t < total) out[i + j * g.ld] = (T)z[t];
+    if (++i == g.m) {
+      i = 0;
+      ++j;
+    }
+  }
+}
+
 }  // namespace
 
 hipError_t launch_gaussian(void* out, int64_t m, int64_t d, int64_t ld, uint64_t seed,
@@ -147,6 +172,23 @@ hipError_t launch_gaussian_columns(void* X, int64_t rows, int64_t ldx, const int
   else
     hipLaunchKernelGGL(gaussian_columns_kernel<float>, dim3(grid), dim3(256), 0, st,
                        (float*)X, rows, ldx, col_flags, d, seed, sid);
+  return hipGetLastError();
+}
+
+void gauss_grouped_blocks(const GroupGauss& g, int idx, std::vector<int2>& out) {
+  const int64_t nb = (g.m * g.d + 1023) / 1024;
+  for (int64_t b = 0; b < nb; ++b) out.push_back(int2{idx, (int)b});
+}
+
+hipError_t launch_gaussian_grouped(Dtype dt, const GroupGauss* descs, const int2* bmap,
+                                   int64_t nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if (dt == DT_F64)
+    hipLaunchKernelGGL(gaussian_grouped_kernel<double>, dim3((unsigned)nblocks), dim3(256), 0, st,
+                       descs, bmap);
+  else
+    hipLaunchKernelGGL(gaussian_grouped_kernel<float>, dim3((unsigned)nblocks), dim3(256), 0, st,
+                       descs, bmap);
   return hipGetLastError();
 }
 

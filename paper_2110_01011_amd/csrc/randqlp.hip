@@ -40,6 +40,21 @@ rqlp_status fail(rqlp_status s, const char* fmt, ...) {
   return s;
 }
 
+}  // namespace
+
+// The same, for the library's other translation units.
+rqlp_status rqlp_fail(rqlp_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+namespace {
+
 #define HIP_TRY(expr)                   \
   do {                                  \
     hipError_t e_ = (expr);             \

@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <vector>
+
 namespace rqlp {
 
 typedef double double4_t __attribute__((ext_vector_type(4)));
@@ -148,6 +150,79 @@ hipError_t launch_count_flags(const int* col_flags, int64_t d, int* count, hipSt
 // Scan A (m x n, lda) for NaN / Inf; raise FLAG_NONFINITE in *flags.
 hipError_t launch_check_finite(const void* A, int64_t m, int64_t n, int64_t lda, Dtype dt,
                                int* flags, hipStream_t st);
+
+// ---- grouped launches (many independent problems in one launch) ----
+// One product C = op(A) B of a grouped launch (whole contraction, no split).
+struct GroupGemm {
+  const void* A; int64_t lda;
+  const void* B; int64_t ldb;
+  void* C; int64_t ldc;
+  int64_t M, N, K;
+};
+// Appends the workgroups (descriptor idx, tile_m, tile_n) of product g for
+// a grouped launch with tile width wn (16-column blocks per wave; rounded up
+// to 1, 2, 4 or 8).  gram: the 32 x 32 Gram tiling, lower tiles only (the
+// part the panel kernels read).
+void gemm_grouped_blocks(const GroupGemm& g, int idx, bool gram, int wn, std::vector<int4>& out);
+int grouped_wn_round(int wn);
+hipError_t launch_gemm_grouped(Dtype in_t, Dtype out_t, int trans_a, bool gram, int wn,
+                               const GroupGemm* descs, const int4* bmap, int64_t nblocks,
+                               hipStream_t st);
+
+// One Cholesky factorisation (d <= CHOL_MAX_D) of a grouped launch.
+struct GroupChol {
+  const double* G; int64_t ldg;
+  double* R; int64_t ldr;
+  double* dinv;
+  int* flags;
+  int d;
+  double tol_dep, tol_warn;
+};
+hipError_t launch_cholesky_grouped(const GroupChol* descs, int count, hipStream_t st);
+
+// One triangular solve Qx = X R^+ of a grouped launch; blocks (idx, 16-row block).
+struct GroupTrsm {
+  const void* X; int64_t rows, ldx;
+  const double* R; int64_t ldr;
+  const double* dinv;
+  void* Qx; int64_t ldq;
+  int d;
+};
+void trsm_grouped_blocks(const GroupTrsm& t, int idx, std::vector<int2>& out);
+hipError_t launch_trsm_grouped(Dtype dt, const GroupTrsm* descs, const int2* bmap,
+                               int64_t nblocks, int dmax, hipStream_t st);
+
+// First-order second pass of a grouped launch (one workgroup per problem):
+// from G2 = Q1^T Q1 (d x d, read from its lower triangle) writes B (d x d,
+// in the panel type) and R2 (double), raising FLAG_SECOND_PASS in flags.
+struct GroupFirstOrder {
+  const double* G2;
+  void* B;
+  double* R2;
+  int* flags;
+  int d;
+  double tol;
+};
+hipError_t launch_first_order_grouped(Dtype dt, const GroupFirstOrder* descs, int count,
+                                      hipStream_t st);
+// L (d x d, ldl) = R^T of each upper-triangular R (d x d, tight); one workgroup each.
+struct GroupLower {
+  const double* R;
+  double* L; int64_t ldl;
+  int d;
+};
+hipError_t launch_lower_grouped(const GroupLower* descs, int count, hipStream_t st);
+// Zero n ints (a kernel, so that graph capture records no memset node).
+hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t st);
+
+// Gaussian sketches of a grouped launch: blocks (idx, local block).
+struct GroupGauss {
+  void* out; int64_t m, d, ld;
+  uint64_t seed;
+};
+void gauss_grouped_blocks(const GroupGauss& g, int idx, std::vector<int2>& out);
+hipError_t launch_gaussian_grouped(Dtype dt, const GroupGauss* descs, const int2* bmap,
+                                   int64_t nblocks, hipStream_t st);
 
 // ---- learned.hip ----
 // Predictor features (65 floats) from the fp64 Gram G (64 x 64, ldg) of the
