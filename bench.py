@@ -95,6 +95,199 @@ def cpu_baseline(A, k, p, q, flops, budget_s=15.0, max_reps=40):
                       f"matrix (median {t:.2f} s each, Omega generation included)"}, e
 
 
+def gpu_svd_matrix(n, sigma, gen):
+    """A = U diag(sigma) V^T (n x n, fp64, column-major) with Haar U, V from
+    the QR of seeded Gaussian matrices, generated on the device."""
+    import torch
+    U, R = torch.linalg.qr(torch.randn(n, n, dtype=torch.float64, device="cuda", generator=gen))
+    U *= torch.sign(torch.diagonal(R))[None, :]
+    V, R = torch.linalg.qr(torch.randn(n, n, dtype=torch.float64, device="cuda", generator=gen))
+    V *= torch.sign(torch.diagonal(R))[None, :]
+    A = (U * sigma[None, :]) @ V.T
+    del U, V, R
+    return A.t().contiguous().t()
+
+
+def device_rel_error(A, Q, L, P):
+    import torch
+    A64 = A.double()
+    R = A64 - Q.double() @ (L.double() @ P.double().T)
+    return float(torch.linalg.norm(R) / torch.linalg.norm(A64))
+
+
+def headline(rq, A_c2, k, p, steps):
+    """bf16 precision form + learned q (randqlp_factor_auto) against the plain
+    fp64 method with q = 2, on 8000 x 8000 matrices of the predictor's three
+    training families; factorisations per second and errors."""
+    import numpy as np
+    import torch
+    wpath = os.path.join(ROOT, "paper_2110_01011_amd", "qpredictor.npy")
+    if not os.path.exists(wpath):
+        return None
+    th = torch.from_numpy(np.load(wpath).astype(np.float32)).cuda()
+    n = A_c2.shape[0]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2021)
+    j = torch.arange(1, n + 1, dtype=torch.float64, device="cuda")
+    cases = [("rank-200 + noise", A_c2)]
+    log("generating the poly / exp evaluation matrices on the device")
+    cases.append(("poly sigma_j = j^-1", gpu_svd_matrix(n, j ** -1.0, gen)))
+    cases.append(("exp sigma_j = exp(-(j-1)/100)", gpu_svd_matrix(n, torch.exp(-(j - 1) / 100.0), gen)))
+    out = []
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            r = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, r
+
+    for name, A in cases:
+        A32 = rq.colmajor(A.float().t().contiguous().t())
+        t64, (Q, L, P) = timed(lambda: rq.factor(A, k, p, 2, 0))
+        e64 = device_rel_error(A, Q, L, P)
+        ta, (Q, L, P, info, ai) = timed(lambda: rq.factor_auto(A32, k, p, 0, th, q_fallback=2,
+                                                               precision="bf16",
+                                                               return_info=True))
+        ea = device_rel_error(A, Q, L, P)
+        out.append({"matrix": name, "fp64_q2_per_s": round(1.0 / t64, 2),
+                    "bf16_learned_per_s": round(1.0 / ta, 2), "speedup": round(t64 / ta, 3),
+                    "e_fp64_q2": e64, "e_bf16_learned": ea, "error_ratio": ea / e64,
+                    "q_predicted": ai["q_predicted"], "q_used": ai["q_used"],
+                    "resumed": ai["resumed"]})
+        log(f"  {out[-1]}")
+        del A32
+    sp = [c["speedup"] for c in out]
+    return {"metric": "factorisations/s, bf16 precision form + learned q vs plain fp64 q = 2",
+            "workload": f"{n}x{n}, k={k} p={p}", "cases": out,
+            "speedup_geomean": float(np.exp(np.mean(np.log(sp)))),
+            "errors_within_1.05": all(c["error_ratio"] <= 1.05 for c in out)}
+
+
+def workload_c3(args):
+    """Precision form: 20000 x 16000, sigma_i = exp(-i/100) (rank 4000, Haar
+    factors), k = 500, p = 20, q = 2 (d = 520); fp64, fp32, bf16 and fp16 forms,
+    each with its error against the fp64 oracle's value for the same matrix."""
+    import torch
+
+    import paper_2110_01011_amd as rq
+    from paper_2110_01011_amd.metrics import PEAK_TFLOPS, randqlp_flops
+    m, n, r, k, p, q = 20000, 16000, 4000, 500, 20, 2
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3)
+    log("generating the 20000 x 16000 exp-decay matrix on the device")
+    U, _ = torch.linalg.qr(torch.randn(m, r, dtype=torch.float64, device="cuda", generator=gen))
+    V, _ = torch.linalg.qr(torch.randn(n, r, dtype=torch.float64, device="cuda", generator=gen))
+    sig = torch.exp(-torch.arange(1, r + 1, dtype=torch.float64, device="cuda") / 100.0)
+    A64 = rq.colmajor(((U * sig) @ V.T).t().contiguous().t())
+    del U, V
+    A32 = rq.colmajor(A64.float().t().contiguous().t())
+    d = rq.sketch_width(m, n, k, p)
+    flops = randqlp_flops(m, n, d, q)
+    opt = float(torch.sqrt(torch.sum(sig[d:] ** 2)).item() / torch.linalg.norm(sig).item())
+    forms = {}
+    for prec in ("f64", "f32", "bf16", "f16"):
+        A = A64 if prec == "f64" else A32
+        for _ in range(args.warmup):
+            rq.factor(A, k, p, q, 0, precision=prec)
+        torch.cuda.synchronize()
+        rq.profile_read()
+        rq.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            Q, L, P = rq.factor(A, k, p, q, 0, precision=prec)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / args.steps
+        rq.profile_enable(False)
+        kms, nl, kfl, kby = rq.profile_read()
+        e = device_rel_error(A64, Q, L, P)
+        forms[prec] = {"ms_per_step": round(t * 1e3, 3), "gflops": round(flops / t / 1e9, 1),
+                       "products_avg_ms": round(kms / max(nl, 1), 4),
+                       "products_tflops": round(kfl / max(kms, 1e-9) / 1e9, 2),
+                       "e": e, "e_over_eckart_young_d": e / opt}
+        log(f"  {prec}: {forms[prec]}")
+        del Q, L, P
+    ref = forms["f64"]["e"]
+    for prec in forms:
+        forms[prec]["e_over_fp64"] = forms[prec]["e"] / ref
+    b = forms["bf16"]
+    print(json.dumps({
+        "metric": "Rand-QLP GFLOP/s, precision form (bf16 products) vs fp64", "value": b["gflops"],
+        "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": b["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16+f32+f64", "data": "synthetic",
+        "config": {"workload": f"exp-decay sigma_i = exp(-i/100), rank {r}, {m}x{n}, "
+                               f"k={k} p={p} q={q} (d={d}), precision form",
+                   "flops_per_step": flops},
+        "forms": forms}), flush=True)
+
+
+def workload_batched(args):
+    """Batched form: 512 matrices, m, n uniform in 256..4096, sigma_j = j^-alpha
+    with alpha uniform in [0.5, 3] and Haar factors, k uniform in 8..128,
+    p = 10, q = 2, fp32; grouped launches replayed from a HIP graph, tuned
+    tile widths; against the same matrices factored one call at a time."""
+    import numpy as np
+    import torch
+
+    import paper_2110_01011_amd as rq
+    from paper_2110_01011_amd.metrics import PEAK_HBM_GBS, PEAK_TFLOPS, randqlp_flops
+    count, p, q = 512, 10, 2
+    r = np.random.default_rng(0)
+    specs = [(int(r.integers(256, 4097)), int(r.integers(256, 4097)), int(r.integers(8, 129)),
+              float(r.uniform(0.5, 3.0))) for _ in range(count)]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    log("generating 512 matrices on the device")
+    As = []
+    for (m, n, k, a) in specs:
+        rr = min(m, n)
+        U, _ = torch.linalg.qr(torch.randn(m, rr, device="cuda", generator=gen))
+        V, _ = torch.linalg.qr(torch.randn(n, rr, device="cuda", generator=gen))
+        s = torch.arange(1, rr + 1, device="cuda", dtype=torch.float32) ** (-a)
+        As.append(rq.colmajor(((U * s) @ V.T).t().contiguous().t()))
+        del U, V
+    torch.cuda.synchronize()
+    ks = [sp[2] for sp in specs]
+    seeds = list(range(count))
+    F, roof = 0.0, 0.0
+    for (m, n, k, a) in specs:
+        d = min(k + p, m, n)
+        f = randqlp_flops(m, n, d, q)
+        F += f
+        roof += max(f / (PEAK_TFLOPS["f32"] * 1e12), (2 * q + 3) * m * n * 4 / (PEAK_HBM_GBS * 1e9))
+    b = rq.Batch(As, ks, p, q, seeds, tune=True)
+    for _ in range(args.warmup):
+        b.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.run()
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    info = b.info()
+    t0 = time.perf_counter()
+    for A, k, sd in zip(As, ks, seeds):
+        rq.factor(A, k, p, q, sd)
+    torch.cuda.synchronize()
+    tseq = time.perf_counter() - t0
+    b.close()
+    print(json.dumps({
+        "metric": "Rand-QLP GFLOP/s, batched form", "value": round(F / t / 1e9, 1),
+        "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(t * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "512 matrices, m, n ~ U{256..4096}, sigma_j = j^-alpha, "
+                               "alpha ~ U[0.5, 3], k ~ U{8..128}, p=10, q=2, fp32",
+                   "flops_per_step": F},
+        "roofline": {"bound": "sum over matrices of max(flops / fp32 peak, bytes / HBM peak)",
+                     "roof_ms": round(roof * 1e3, 3), "frac": round(roof / t, 4)},
+        "sequential_ms": round(tseq * 1e3, 2), "speedup_vs_sequential": round(tseq / t, 2),
+        "plan": info}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +296,10 @@ def main():
     ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
     ap.add_argument("--size", type=int, default=8000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-headline", action="store_true")
+    ap.add_argument("--workload", choices=["c2", "c3", "batched"], default="c2",
+                    help="c2 (default): 8000 x 8000 rank-200 + noise; c3: the precision form "
+                         "at 20000 x 16000; batched: 512 uneven matrices")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain copy of this size first (for counter scaling)")
     args = ap.parse_args()
@@ -110,6 +307,11 @@ def main():
         print("bench.py measures one GPU only: the factorisation of one matrix runs on a "
               "single MI355X (multi-GPU sharding is described, not built).", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c3":
+        return workload_c3(args)
+    if args.workload == "batched":
+        return workload_batched(args)
 
     import numpy as np
     import torch
@@ -163,6 +365,10 @@ def main():
     Qn, Ln, Pn = (t.double().cpu().numpy() for t in (Q, L, P))
     from numpy.linalg import norm
     e_gpu = float(norm(A64 - Qn @ (Ln @ Pn.T)) / norm(A64))
+    head = None
+    if not args.no_headline and args.precision == "f64" and args.size == 8000:
+        log("headline: bf16 + learned q vs fp64 q = 2")
+        head = headline(rq, Ad, k, p, max(3, args.steps // 4))
     cpu = None
     e_orc = None
     if not args.no_cpu_baseline:
@@ -182,6 +388,7 @@ def main():
         "cpu_baseline": cpu,
         "error": {"e_gpu": e_gpu, "e_oracle": e_orc,
                   "ratio": (e_gpu / e_orc) if e_orc else None},
+        "headline": head,
     }
     print(json.dumps(out), flush=True)
 

@@ -16,7 +16,9 @@
 // Tile widths of the products with A come from a table: tuned on the plan's
 // own data when asked (each candidate timed with HIP events), kept per
 // (precision, product orientation, bucket of the largest d), and saved to /
-// loaded from a text file.
+// loaded from a text file.  Candidates: one width for every matrix, or
+// width 0 = per class (each matrix gets the width that covers its d in one
+// tile, one launch per width present, so A is read once).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -61,6 +63,17 @@ struct Launch {
   int64_t count = 0, nblocks = 0;
 };
 
+// A product step: one launch per tile width used.  wn > 0: every matrix
+// with that width; wn = 0 ("per class"): each matrix with the width that
+// covers its d in one tile (1, 2, 4 or 8 blocks of 32 columns), one launch
+// per width present.
+struct ProdSet {
+  int wn = 2;
+  std::vector<std::pair<int, Launch>> parts;  // (width, launch)
+};
+
+int class_wn(int64_t d) { return grouped_wn_round((int)((d + 31) / 32)); }
+
 }  // namespace
 
 struct rqlp_batch {
@@ -83,10 +96,11 @@ struct rqlp_batch {
   double tune_ms = 0.0;
   int last_fallbacks = 0;
   // launches
-  Launch gauss, tn, nn, tn_final, gramY, gramZ, gramTm, gramTn, chol, trsmY, trsmZ, trsmZT,
-      trsmYT, fo, qfin, pfin, rcomb, lower;
-  // alternative block maps of the products, per candidate width
-  std::map<int, Launch> tn_alt, nn_alt;
+  Launch gauss, gramY, gramZ, gramTm, gramTn, chol, trsmY, trsmZ, trsmZT, trsmYT, fo, qfin, pfin,
+      rcomb, lower;
+  ProdSet tn, nn, tn_final;
+  // candidate product sets per width (0 = per class)
+  std::map<int, ProdSet> tn_alt, nn_alt, tnf_alt;
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -121,6 +135,28 @@ Launch gemm_launch(std::vector<char>& buf, const std::vector<GroupGemm>& descs, 
   return l;
 }
 
+ProdSet prod_set(std::vector<char>& buf, const std::vector<GroupGemm>& descs, int wn) {
+  ProdSet ps;
+  ps.wn = wn;
+  if (wn > 0) {
+    ps.parts.push_back({wn, gemm_launch(buf, descs, false, wn)});
+    return ps;
+  }
+  for (int c : {1, 2, 4, 8}) {
+    std::vector<int4> map;
+    for (size_t i = 0; i < descs.size(); ++i)
+      if (class_wn(descs[i].N) == c) gemm_grouped_blocks(descs[i], (int)i, false, c, map);
+    if (map.empty()) continue;
+    Launch l;
+    l.desc = put(buf, descs);
+    l.map = put(buf, map);
+    l.count = (int64_t)descs.size();
+    l.nblocks = (int64_t)map.size();
+    ps.parts.push_back({c, l});
+  }
+  return ps;
+}
+
 Launch trsm_launch(std::vector<char>& buf, const std::vector<GroupTrsm>& descs) {
   std::vector<int2> map;
   for (size_t i = 0; i < descs.size(); ++i) trsm_grouped_blocks(descs[i], (int)i, map);
@@ -136,6 +172,14 @@ hipError_t run_gemm(const rqlp_batch* b, const Launch& l, Dtype in_t, Dtype out_
                     bool gram, int wn, hipStream_t st) {
   return launch_gemm_grouped(in_t, out_t, trans, gram, wn, at<GroupGemm>(b, l.desc),
                              at<int4>(b, l.map), l.nblocks, st);
+}
+
+hipError_t run_prod(const rqlp_batch* b, const ProdSet& ps, int trans, hipStream_t st) {
+  for (const auto& pl : ps.parts) {
+    hipError_t e = run_gemm(b, pl.second, b->dt, b->dt, trans, false, pl.first, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 hipError_t run_trsm(const rqlp_batch* b, const Launch& l, hipStream_t st) {
@@ -171,15 +215,15 @@ hipError_t enqueue(const rqlp_batch* b, hipStream_t st) {
   B_TRY(launch_zero_ints(b->flags, (int64_t)b->grouped.size() * 16, st));
   B_TRY(launch_gaussian_grouped(dt, at<GroupGauss>(b, b->gauss.desc), at<int2>(b, b->gauss.map),
                                 b->gauss.nblocks, st));                       // randn
-  B_TRY(run_gemm(b, b->tn, dt, dt, 1, false, b->wn_tn, st));                  // A^T Omega
+  B_TRY(run_prod(b, b->tn, 1, st));                                           // A^T Omega
   B_TRY(orth_inplace(b->gramY, b->trsmY));                                    // Qbar
   for (int it = 0; it < b->q; ++it) {
-    B_TRY(run_gemm(b, b->nn, dt, dt, 0, false, b->wn_nn, st));                // A Qbar
+    B_TRY(run_prod(b, b->nn, 0, st));                                         // A Qbar
     B_TRY(orth_inplace(b->gramZ, b->trsmZ));
-    B_TRY(run_gemm(b, b->tn, dt, dt, 1, false, b->wn_tn, st));                // A^T Q
+    B_TRY(run_prod(b, b->tn, 1, st));                                         // A^T Q
     B_TRY(orth_inplace(b->gramY, b->trsmY));
   }
-  B_TRY(run_gemm(b, b->nn, dt, dt, 0, false, b->wn_nn, st));                  // A Qbar
+  B_TRY(run_prod(b, b->nn, 0, st));                                           // A Qbar
   // Q: Cholesky QR, then the second pass to first order
   B_TRY(run_gemm(b, b->gramZ, dt, DT_F64, 1, true, 1, st));
   B_TRY(run_chol(b, st));
@@ -188,7 +232,7 @@ hipError_t enqueue(const rqlp_batch* b, hipStream_t st) {
   B_TRY(run_fo(b, st));
   B_TRY(run_gemm(b, b->qfin, dt, dt, 0, false, 2, st));
   // W = A^T Q; P, R
-  B_TRY(run_gemm(b, b->tn_final, dt, dt, 1, false, b->wn_tn, st));
+  B_TRY(run_prod(b, b->tn_final, 1, st));
   B_TRY(run_gemm(b, b->gramY, dt, DT_F64, 1, true, 1, st));
   B_TRY(run_chol(b, st));
   B_TRY(run_trsm(b, b->trsmYT, st));
@@ -200,7 +244,7 @@ hipError_t enqueue(const rqlp_batch* b, hipStream_t st) {
 }
 
 // Times one grouped product with the given block map (ms per launch).
-double time_product(const rqlp_batch* b, const Launch& l, int trans, int wn, hipStream_t st) {
+double time_product(const rqlp_batch* b, const ProdSet& ps, int trans, hipStream_t st) {
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return 1e30;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -208,10 +252,10 @@ double time_product(const rqlp_batch* b, const Launch& l, int trans, int wn, hip
     return 1e30;
   }
   double best = 1e30;
-  (void)run_gemm(b, l, b->dt, b->dt, trans, false, wn, st);  // warm-up
+  (void)run_prod(b, ps, trans, st);  // warm-up
   for (int r = 0; r < 3; ++r) {
     (void)hipEventRecord(e0, st);
-    (void)run_gemm(b, l, b->dt, b->dt, trans, false, wn, st);
+    (void)run_prod(b, ps, trans, st);
     (void)hipEventRecord(e1, st);
     float ms = 0.f;
     if (hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
@@ -358,9 +402,9 @@ rqlp_status randqlp_batch_create(int count, const void* const* A, const int64_t*
   for (int i : b->grouped) ds.push_back(b->d[i]);
   std::sort(ds.begin(), ds.end());
   const int64_t dmed = ds.empty() ? 1 : ds[ds.size() / 2];
-  const int heur = grouped_wn_round((int)((dmed + 31) / 32));
-  b->wn_tn = lookup_wn(b->dt, 1, b->dmax, heur);
-  b->wn_nn = lookup_wn(b->dt, 0, b->dmax, std::min(heur, 4));
+  (void)dmed;
+  b->wn_tn = lookup_wn(b->dt, 1, b->dmax, 0);
+  b->wn_nn = lookup_wn(b->dt, 0, b->dmax, 0);
   std::vector<char>& buf = b->host_tab;
   {
     std::vector<int2> map;
@@ -370,11 +414,16 @@ rqlp_status randqlp_batch_create(int count, const void* const* A, const int64_t*
     b->gauss.count = (int64_t)gg.size();
     b->gauss.nblocks = (int64_t)map.size();
   }
-  for (int wn : {1, 2, 4, 8}) b->tn_alt[wn] = gemm_launch(buf, tn, false, wn);
-  for (int wn : {1, 2, 4}) b->nn_alt[wn] = gemm_launch(buf, nn, false, wn);
+  for (int wn : {0, 1, 2, 4, 8}) {
+    b->tn_alt[wn] = prod_set(buf, tn, wn);
+    b->tnf_alt[wn] = prod_set(buf, tnf, wn);
+  }
+  for (int wn : {0, 1, 2, 4}) b->nn_alt[wn] = prod_set(buf, nn, wn);
+  if (!b->tn_alt.count(b->wn_tn)) b->wn_tn = 0;
+  if (!b->nn_alt.count(b->wn_nn)) b->wn_nn = 0;
   b->tn = b->tn_alt[b->wn_tn];
   b->nn = b->nn_alt[b->wn_nn];
-  b->tn_final = gemm_launch(buf, tnf, false, b->wn_tn);
+  b->tn_final = b->tnf_alt[b->wn_tn];
   b->gramY = gemm_launch(buf, grY, true, 1);
   b->gramZ = gemm_launch(buf, grZ, true, 1);
   b->gramTm = gemm_launch(buf, grTm, true, 1);
@@ -416,7 +465,7 @@ rqlp_status randqlp_batch_create(int count, const void* const* A, const int64_t*
                                 at<int2>(b, b->gauss.map), b->gauss.nblocks, b->cap);
     double best = 1e30;
     for (auto& kv : b->tn_alt) {
-      const double t = time_product(b, kv.second, 1, kv.first, b->cap);
+      const double t = time_product(b, kv.second, 1, b->cap);
       if (t < best) {
         best = t;
         b->wn_tn = kv.first;
@@ -424,7 +473,7 @@ rqlp_status randqlp_batch_create(int count, const void* const* A, const int64_t*
     }
     best = 1e30;
     for (auto& kv : b->nn_alt) {
-      const double t = time_product(b, kv.second, 0, kv.first, b->cap);
+      const double t = time_product(b, kv.second, 0, b->cap);
       if (t < best) {
         best = t;
         b->wn_nn = kv.first;
@@ -442,20 +491,7 @@ rqlp_status randqlp_batch_create(int count, const void* const* A, const int64_t*
     }
     b->tn = b->tn_alt[b->wn_tn];
     b->nn = b->nn_alt[b->wn_nn];
-    // the final projection's block map follows the tuned width
-    std::vector<char> extra = buf;
-    Launch l = gemm_launch(extra, tnf, false, b->wn_tn);
-    if (extra.size() > buf.size()) {
-      char* nt = nullptr;
-      e = hipMalloc((void**)&nt, extra.size());
-      if (e == hipSuccess) e = hipMemcpy(nt, extra.data(), extra.size(), hipMemcpyHostToDevice);
-      if (e == hipSuccess) {
-        (void)hipFree(b->tab);
-        b->tab = nt;
-        buf.swap(extra);
-        b->tn_final = l;
-      }
-    }
+    b->tn_final = b->tnf_alt[b->wn_tn];
   }
   // capture the grouped sequence
   e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
@@ -554,8 +590,8 @@ rqlp_status randqlp_tune_load(const char* path) {
     if (line[0] == '#') continue;
     int dt = 0, tr = 0, bk = 0, wn = 0;
     if (std::sscanf(line, "%d %d %d %d", &dt, &tr, &bk, &wn) == 4 && (dt == 0 || dt == 1) &&
-        (tr == 0 || tr == 1) && wn >= 1 && wn <= 8) {
-      g_tune[{dt, tr, bk}] = grouped_wn_round(wn);
+        (tr == 0 || tr == 1) && wn >= 0 && wn <= 8) {
+      g_tune[{dt, tr, bk}] = wn == 0 ? 0 : grouped_wn_round(wn);
       ++nread;
     }
   }

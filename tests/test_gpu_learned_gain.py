@@ -1,0 +1,74 @@
+"""What the trained predictor gains: trained on the GPU by the library's own
+kernels from the oracle-labelled dataset, then randqlp_factor_auto against
+fixed q = 2 on fresh matrices of the three training families."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import rel_error
+from tests.gpu_util import log, to_dev, to_np
+
+pytestmark = pytest.mark.gpu
+DATA = os.path.join(os.path.dirname(__file__), "learned", "qpred_data.npz")
+
+
+@pytest.fixture(scope="module")
+def rq():
+    import paper_2110_01011_amd as rq
+    rq.lib()
+    return rq
+
+
+@pytest.fixture(scope="module")
+def trained(rq):
+    if not os.path.exists(DATA):
+        pytest.skip("training data not generated (tests/learned/make_qpred_data.py)")
+    from paper_2110_01011_amd.train_predictor import train
+    params, summary = train(DATA, epochs=(40, 20))
+    log(f"  training summary {summary}")
+    return params, summary
+
+
+def test_training_beats_the_majority_class(trained):
+    params, s = trained
+    counts = np.array(s["label_counts"], dtype=float)
+    majority = counts.max() / counts.sum()
+    assert s["loss_last"] < 0.7 * s["loss_first"]
+    assert s["validation_accuracy"] > majority + 0.05
+    # too-low predictions only cost a judged resume, but should stay rare
+    assert s["validation_under"] < 0.1
+
+
+def _eval_matrices():
+    """Fresh matrices (seeds unused by the dataset) of the three families."""
+    out = []
+    m, n = 2400, 2000
+    j = np.arange(1, n + 1, dtype=np.float64)
+    for i, alpha in enumerate((0.7, 1.5, 2.5)):
+        out.append((f"poly{alpha}", W.svd_matrix(m, n, j ** -alpha, seed=900 + i)[0], 60))
+    for i, tau in enumerate((20.0, 80.0)):
+        out.append((f"exp{tau}", W.svd_matrix(m, n, np.exp(-(j - 1) / tau), seed=910 + i)[0], 60))
+    A, s = W.rank_plus_noise(m, n, 60, 1e-3, seed=920)
+    out.append(("rank60+noise", A, 60))
+    return out
+
+
+def test_learned_q_saves_rounds_at_equal_error(rq, trained):
+    import torch
+    params, _ = trained
+    th = torch.from_numpy(params).cuda()
+    used, rows = [], []
+    for name, A, k in _eval_matrices():
+        Ad = to_dev(A)
+        Qa, La, Pa, info, ai = rq.factor_auto(Ad, k, 10, 3, th, q_fallback=2, return_info=True)
+        Q2, L2, P2 = rq.factor(Ad, k, 10, 2, 3)
+        ea = rel_error(A, to_np(Qa), to_np(La), to_np(Pa))
+        e2 = rel_error(A, to_np(Q2), to_np(L2), to_np(P2))
+        used.append(ai["q_used"])
+        rows.append((name, ai["q_predicted"], ai["q_used"], ai["resumed"], ea / e2))
+        log(f"  {name}: q_pred={ai['q_predicted']} q_used={ai['q_used']} resumed={ai['resumed']} "
+            f"judge={ai['judge_ratio']:.3g} e_auto/e_q2={ea / e2:.4f}")
+        assert ea <= 1.05 * e2
+    assert np.mean(used) < 2.0
