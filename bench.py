@@ -156,7 +156,7 @@ def headline(rq, A_c2, k, p, steps):
                     "bf16_learned_per_s": round(1.0 / ta, 2), "speedup": round(t64 / ta, 3),
                     "e_fp64_q2": e64, "e_bf16_learned": ea, "error_ratio": ea / e64,
                     "q_predicted": ai["q_predicted"], "q_used": ai["q_used"],
-                    "resumed": ai["resumed"]})
+                    "resumed": ai["resumed"], "judge_ratio": ai["judge_ratio"]})
         log(f"  {out[-1]}")
         del A32
     sp = [c["speedup"] for c in out]

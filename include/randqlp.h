@@ -176,6 +176,9 @@ rqlp_status randqlp_orth(const void* X, int64_t rows, int64_t d, int64_t ldx, vo
  * product; with e^2 = ||A||_F^2 - ||L||_F^2 (the squared residual of the
  * factors) and Delta = ||(I - Q Q^T) Z||_F^2 (how much one more round would
  * lower it), q_hat is accepted when Delta <= 0.0404 e^2 (2% in the error).
+ * In the precision form Z is the 16-bit product (the one further rounds would
+ * use) and the expected share of A's rounding error in it, (d / n)
+ * ||A16 - A||_F^2, is taken off Delta first: no number of rounds removes it.
  * Otherwise the power rounds resume from Z up to q_fallback, and the result
  * equals randqlp_factor with q = q_fallback up to rounding.  opts as for
  * randqlp_factor (info->q_used reports the rounds used); ainfo may be NULL.

@@ -412,18 +412,28 @@ __global__ __launch_bounds__(256) void convert_panel16_kernel(const float* __res
 // to multiples of 64; the padding rows of both copies are written as zeros
 // (the contraction padding of gemm16_kernel).  64 x 64 tiles through LDS keep
 // the transposed writes coalesced; the grid covers exactly the padded sizes.
+// If rerr is given, each workgroup also writes the sum of squared rounding
+// errors (a - a16)^2 of its tile (fp64) to rerr[its linear index].
 template <typename T16>
 __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict__ A, int64_t m,
                                                         int64_t n, int64_t lda,
                                                         T16* __restrict__ A16, int64_t ld16,
-                                                        T16* __restrict__ At16, int64_t ldt16) {
+                                                        T16* __restrict__ At16, int64_t ldt16,
+                                                        double* __restrict__ rerr) {
   __shared__ T16 tile[64][66];
+  __shared__ double red[256];
   const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  double err = 0.0;
   for (int jj = ty; jj < 64; jj += 4) {
     const int64_t i = i0 + tx, j = j0 + jj;
     T16 v = (T16)0.0f;
-    if (i < m && j < n) v = to16(A[i + j * lda], (T16*)nullptr);
+    if (i < m && j < n) {
+      const float a = A[i + j * lda];
+      v = to16(a, (T16*)nullptr);
+      const double e = (double)a - (double)(float)v;
+      err += e * e;
+    }
     if (j < n) A16[i + j * ld16] = v;  // i < ld16 always
     tile[jj][tx] = v;
   }
@@ -431,6 +441,15 @@ __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict_
   for (int ii = ty; ii < 64; ii += 4) {
     const int64_t j = j0 + tx, i = i0 + ii;
     if (i < m) At16[j + i * ldt16] = tile[tx][ii];  // j < ldt16 always
+  }
+  if (rerr) {
+    red[threadIdx.x] = err;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) rerr[blockIdx.x + (int64_t)blockIdx.y * gridDim.x] = red[0];
   }
 }
 
@@ -759,17 +778,20 @@ hipError_t launch_convert_panel16(const float* X, int64_t rows, int64_t d, int64
   return hipGetLastError();
 }
 
+int64_t convert16_blocks(int64_t m, int64_t n) { return ((m + 63) / 64) * ((n + 63) / 64); }
+
 hipError_t launch_convert16(const float* A, int64_t m, int64_t n, int64_t lda, void* A16,
-                            int64_t ld16, void* At16, int64_t ldt16, bool f16, hipStream_t st) {
+                            int64_t ld16, void* At16, int64_t ldt16, bool f16, hipStream_t st,
+                            double* rerr) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (ld16 < pad16(m) || ldt16 < pad16(n)) return hipErrorInvalidValue;
   dim3 grid((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64));
   if (f16)
     hipLaunchKernelGGL(convert16_kernel<_Float16>, grid, dim3(256), 0, st, A, m, n, lda,
-                       (_Float16*)A16, ld16, (_Float16*)At16, ldt16);
+                       (_Float16*)A16, ld16, (_Float16*)At16, ldt16, rerr);
   else
     hipLaunchKernelGGL(convert16_kernel<__bf16>, grid, dim3(256), 0, st, A, m, n, lda,
-                       (__bf16*)A16, ld16, (__bf16*)At16, ldt16);
+                       (__bf16*)A16, ld16, (__bf16*)At16, ldt16, rerr);
   return hipGetLastError();
 }
 

@@ -298,10 +298,10 @@ __global__ __launch_bounds__(256) void sumsq_partial_kernel(const T* __restrict_
 }
 
 __global__ __launch_bounds__(256) void sumsq_finish_kernel(const double* __restrict__ part,
-                                                           int nparts, double* __restrict__ out) {
+                                                           int64_t nparts, double* __restrict__ out) {
   __shared__ double red[256];
   double s = 0.0;
-  for (int i = threadIdx.x; i < nparts; i += 256) s += part[i];
+  for (int64_t i = threadIdx.x; i < nparts; i += 256) s += part[i];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -378,6 +378,11 @@ hipError_t launch_argmax(const float* Z, int C, int* out, hipStream_t st) {
 }
 
 size_t sumsq_scratch_bytes() { return (size_t)kSumsqBlocks * sizeof(double); }
+
+hipError_t launch_sum_f64(const double* x, int64_t n, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(sumsq_finish_kernel, dim3(1), dim3(256), 0, st, x, (int)n, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_sumsq(const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t rows,
                         int64_t cols, Dtype dt, double* scratch, double* out, hipStream_t st) {

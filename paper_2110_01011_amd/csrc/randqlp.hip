@@ -90,7 +90,7 @@ struct Layout {
   int64_t ld16, ldt16;  // leading dimensions of the 16-bit copies of A and A^T
   int64_t ldp16;        // leading dimension of the 16-bit copy of a panel
   // predictor and error judge (randqlp_factor_auto only)
-  size_t om64, y64, g64, feat, mlp, cls, jd, sums, sres;
+  size_t om64, y64, g64, feat, mlp, cls, jd, sums, sres, rerr;
   size_t flags_bytes;  // status words cleared at the start of a call
 };
 
@@ -160,8 +160,9 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
     L.jd = take((size_t)d * d * es);
     L.sums = take(sumsq_scratch_bytes());
     L.sres = take(4 * 8);
+    L.rerr = mixed ? take((size_t)convert16_blocks(m, n) * 8) : 0;
   } else {
-    L.om64 = L.y64 = L.g64 = L.feat = L.mlp = L.cls = L.jd = L.sums = L.sres = 0;
+    L.om64 = L.y64 = L.g64 = L.feat = L.mlp = L.cls = L.jd = L.sums = L.sres = L.rerr = 0;
   }
   L.scal = take(64);
   L.flags = take(64);
@@ -449,7 +450,8 @@ hipError_t stage_start(Ctx& c, const FactorArgs& f, PanelMode mode) {
   void* Tn = c.ws + c.lay.n2;
   if (c.mixed)
     HIP_TRY(launch_convert16((const float*)f.A, m, n, f.lda, c.ws + c.lay.a16, c.lay.ld16,
-                             c.ws + c.lay.at16, c.lay.ldt16, c.mixed == 2, c.st));
+                             c.ws + c.lay.at16, c.lay.ldt16, c.mixed == 2, c.st,
+                             c.lay.rerr ? c.at<double>(c.lay.rerr) : nullptr));
   HIP_TRY(launch_gaussian(Zm, m, d, m, c.seed, 0, c.dt, c.st));                // randn
   HIP_TRY(prod(c, f, 1, Zm, m, Yn, n));                                        // A^T Omega
   return orth(c, Yn, n, n, Yn, n, Tn, nullptr, mode, false);                   // Qbar
@@ -779,8 +781,12 @@ hipError_t predict_q(Ctx& c, const FactorArgs& f, int k, const float* params, in
 }
 
 // Error judge after a run with q_hat rounds: sums = {||A||^2, ||L||^2,
-// ||(I - Q Q^T) A P||^2}; Zm keeps Z = A P (the next round's product).
-hipError_t judge(Ctx& c, const FactorArgs& f, double sums[3]) {
+// ||(I - Q Q^T) Z||^2, floor}; Zm keeps Z = A P (the next round's product, in
+// the precision the rounds use).  In the precision form Z is the 16-bit
+// product, which carries the rounding error dA = A16 - A of A; more rounds
+// cannot remove it, so `floor` = (d / n) ||dA||_F^2 -- the expected energy of
+// dA P for an orthonormal P -- is what Delta holds beyond the round's gain.
+hipError_t judge(Ctx& c, const FactorArgs& f, double sums[4]) {
   const int64_t m = f.m, d = c.d;
   void* Zm = c.ws + c.lay.m1;
   void* Tm = c.ws + c.lay.m2;
@@ -789,12 +795,18 @@ hipError_t judge(Ctx& c, const FactorArgs& f, double sums[3]) {
   double* res = c.at<double>(c.lay.sres);
   HIP_TRY(launch_sumsq(f.A, f.lda, nullptr, 0, f.m, f.n, c.dt, scr, res, c.st));
   HIP_TRY(launch_sumsq(f.L, f.ldl, nullptr, 0, d, d, DT_F64, scr, res + 1, c.st));
-  HIP_TRY(prod(c, f, 0, f.P, f.ldp, Zm, m, true));                             // Z = A P
+  HIP_TRY(prod(c, f, 0, f.P, f.ldp, Zm, m));                                   // Z = A P
   HIP_TRY(gemm(c, 1, f.Q, f.ldq, Zm, m, C1, d, d, d, m, c.dt, c.dt, false));   // Q^T Z
   HIP_TRY(gemm(c, 0, f.Q, f.ldq, C1, d, Tm, m, m, d, d, c.dt, c.dt, false));   // Q Q^T Z
   HIP_TRY(launch_sumsq(Zm, m, Tm, m, m, d, c.dt, scr, res + 2, c.st));
-  HIP_TRY(hipMemcpyAsync(sums, res, 3 * sizeof(double), hipMemcpyDeviceToHost, c.st));
-  return hipStreamSynchronize(c.st);
+  if (c.mixed && c.lay.rerr)
+    HIP_TRY(launch_sum_f64(c.at<double>(c.lay.rerr), convert16_blocks(f.m, f.n), res + 3, c.st));
+  else
+    HIP_TRY(launch_zero_block(res + 3, 1, 1, 1, c.st));
+  HIP_TRY(hipMemcpyAsync(sums, res, 4 * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  HIP_TRY(hipStreamSynchronize(c.st));
+  sums[3] *= (double)d / (double)f.n;
+  return hipSuccess;
 }
 
 // Continue from Z = A Qbar_{j} in Zm with `more` further full rounds, then
@@ -879,14 +891,14 @@ rqlp_status randqlp_factor_auto(const void* A, int64_t m, int64_t n, int k, int 
     if (e == hipSuccess) e = stage_start(c, f, mode0);
     if (e == hipSuccess) e = stage_rounds(c, f, mode0, cls);
     if (e == hipSuccess) e = stage_finish(c, f, mode0);
-    double sums[3] = {0, 0, 0};
+    double sums[4] = {0, 0, 0, 0};
     if (e == hipSuccess) e = judge(c, f, sums);
     if (e != hipSuccess) return fail(RQLP_E_HIP, "launch failed: %s", hipGetErrorString(e));
     int fl[4] = {0, 0, 0, 0};
     if ((s = read_flags(c, fl)) != RQLP_OK) return s;
     const bool clean = (fl[0] & (FLAG_NONPOS_PIVOT | FLAG_NONFINITE | FLAG_SECOND_PASS)) == 0;
     if (clean) {
-      const double e2 = sums[0] - sums[1], delta = sums[2];
+      const double e2 = sums[0] - sums[1], delta = std::max(0.0, sums[2] - sums[3]);
       ai.judged = 1;
       ai.judge_ratio = e2 > 0.0 ? delta / e2 : (delta > 0.0 ? 1e300 : 0.0);
       ai.est_rel_err = sums[0] > 0.0 ? std::sqrt(std::max(0.0, e2 / sums[0])) : 0.0;

@@ -96,8 +96,12 @@ hipError_t launch_convert_panel16(const float* X, int64_t rows, int64_t d, int64
                                   int64_t ldy, bool f16, hipStream_t st);
 // A (m x n fp32) -> A16 (m x n, ld16) and At16 = A^T (n x m, ldt16), 16-bit,
 // with ld16 >= gemm16_ld(m), ldt16 >= gemm16_ld(n) and zero padding rows.
+// rerr (optional): per-workgroup sums of the squared rounding errors, one
+// double for each of convert16_blocks(m, n) workgroups.
 hipError_t launch_convert16(const float* A, int64_t m, int64_t n, int64_t lda, void* A16,
-                            int64_t ld16, void* At16, int64_t ldt16, bool f16, hipStream_t st);
+                            int64_t ld16, void* At16, int64_t ldt16, bool f16, hipStream_t st,
+                            double* rerr = nullptr);
+int64_t convert16_blocks(int64_t m, int64_t n);
 
 // ---- panel.hip ----
 // One-workgroup Cholesky of G + shift*I (d x d, double, ldg; d <= CHOL_MAX_D)
@@ -246,6 +250,8 @@ hipError_t launch_argmax(const float* Z, int C, int* out, hipStream_t st);
 // ||X||_F^2 or ||X - Y||_F^2 (Y may be null) in fp64, deterministic order;
 // scratch holds sumsq_scratch_bytes().
 size_t sumsq_scratch_bytes();
+// out = sum of the n doubles in x, fixed order.
+hipError_t launch_sum_f64(const double* x, int64_t n, double* out, hipStream_t st);
 hipError_t launch_sumsq(const void* X, int64_t ldx, const void* Y, int64_t ldy, int64_t rows,
                         int64_t cols, Dtype dt, double* scratch, double* out, hipStream_t st);
 
