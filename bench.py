@@ -30,7 +30,7 @@ def log(msg):
 
 # Sources of the product kernel: a traffic measurement is only reported
 # while they are unchanged since the counters were taken.
-KERNEL_SOURCES = ["paper_2110_01011_amd/csrc/gemm.hip", "paper_2110_01011_amd/csrc/rqlp_internal.h"]
+KERNEL_SOURCES = ["paper_2110_01011_amd/csrc/gemm.hip"]
 
 
 def kernel_source_sha():

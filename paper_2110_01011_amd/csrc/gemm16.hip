@@ -1,0 +1,382 @@
+// Precision form of the products with A: C (fp32) = op(A) X with A and X
+// rounded to 16 bits (bf16 or fp16) and fp32 accumulation on the 16x16x32
+// MFMA, plus the conversions that produce the 16-bit operands.
+#include <algorithm>
+
+#include "rqlp_internal.h"
+
+namespace rqlp {
+namespace {
+
+// Precision form: C (fp32) = sum_k A16[k + i lda] B16[k + j ldb] with both
+// operands 16-bit (bf16 or fp16) and contiguous along the contraction, fp32
+// accumulation on the 16x16x32 MFMA.  A16 is the one-time rounded copy of A
+// (or of A^T), B16 the rounded panel (convert_panel16_kernel).  Both are
+// zero-padded along the contraction to a multiple of 64 (k16BK), so every
+// tile is whole and the main loop carries no bounds checks; rows >= M and
+// columns >= N read a clamped (valid) row or column and are never stored.
+//
+// Workgroup tile (32 WAVES) x (16 WN): the waves are stacked along M, each
+// owning 32 rows (two 16-row blocks) and all 16 WN columns.  A rows belong to
+// a single wave, so A fragments go from HBM straight into registers (one
+// 32-byte load per lane and block covers two MFMA k-steps, prefetched one
+// tile ahead); the panel tile, shared by the waves, is staged through LDS
+// (double-buffered, 16-byte row padding so the 16 columns of a fragment read
+// fall in distinct banks).  Within a 64-deep tile, MFMA k-step s takes, for
+// lane group g = lane / 16, the tile rows 16 g + 8 s + [0, 8): the same
+// permutation of k for both operands, so the sum is unchanged.
+//
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2); the linear workgroup id is remapped so that each XCD works through a
+// contiguous range of (row tile, column tile, split) items with the row tile
+// fastest: the panel chunk of one (column tile, split) then stays in one L2.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
+
+template <typename T16>
+struct Mfma16;
+template <>
+struct Mfma16<__bf16> {
+  typedef bf16x8_t v8;
+  static __device__ __forceinline__ float4_t mma(v8 a, v8 b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+  }
+};
+template <>
+struct Mfma16<_Float16> {
+  typedef f16x8_t v8;
+  static __device__ __forceinline__ float4_t mma(v8 a, v8 b, float4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  }
+};
+
+__device__ __forceinline__ __bf16 to16(float x, __bf16*) {
+  // round to nearest even on the upper 16 bits (NaN kept quiet)
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return __builtin_bit_cast(__bf16, (unsigned short)((u >> 16) | 0x40));
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return __builtin_bit_cast(__bf16, (unsigned short)(u >> 16));
+}
+__device__ __forceinline__ _Float16 to16(float x, _Float16*) { return (_Float16)x; }
+
+constexpr int k16BK = 64;     // contraction depth of one tile (and the zero padding unit)
+constexpr int k16Waves = 4;   // waves per workgroup (32 rows each)
+constexpr int k16BM = 32 * k16Waves;
+constexpr int k16MaxWN = 17;  // up to 272 columns per workgroup
+constexpr int kXcds = 8;
+
+// Linear workgroup id -> work item such that the ids one XCD receives
+// (those congruent to x mod 8) form one contiguous range of work items.
+__device__ __forceinline__ int64_t xcd_remap(int64_t L, int64_t T) {
+  const int64_t x = L % kXcds, j = L / kXcds;
+  const int64_t per = T / kXcds, rem = T % kXcds;
+  return (x < rem) ? x * (per + 1) + j : rem * (per + 1) + (x - rem) * per + j;
+}
+
+template <typename T16, int WN>
+__global__ __launch_bounds__(64 * k16Waves, 2) void gemm16_kernel(
+    const T16* __restrict__ A, int64_t lda, const T16* __restrict__ B, int64_t ldb,
+    float* __restrict__ C, int64_t ldc, int64_t strideS, int64_t M, int64_t N, int64_t Kp,
+    int64_t kchunk, int tiles_m, int tiles_n) {
+  constexpr int NT = 64 * k16Waves;
+  constexpr int WM = 2, BK = k16BK, LK = BK + 8, CH = BK / 8;
+  constexpr int BN = 16 * WN;
+  constexpr int CB = BN * CH, NB = (CB + NT - 1) / NT;
+  typedef typename Mfma16<T16>::v8 v8;
+  __shared__ __attribute__((aligned(16))) T16 Bs[2][BN][LK];
+
+  const int64_t T = (int64_t)gridDim.x;
+  const int64_t w = xcd_remap(blockIdx.x, T);
+  const int tile_m = (int)(w % tiles_m);
+  const int tile_n = (int)((w / tiles_m) % tiles_n);
+  const int split = (int)(w / ((int64_t)tiles_m * tiles_n));
+  const int64_t i0 = (int64_t)tile_m * k16BM, j0 = (int64_t)tile_n * BN;
+  const int64_t kbeg = (int64_t)split * kchunk;
+  const int64_t kend = (kbeg + kchunk < Kp) ? kbeg + kchunk : Kp;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int grp = lane >> 4, r16 = lane & 15;
+
+  // this lane's A rows (clamped); its 16 k of a tile start at 16 * grp
+  const T16* arow[WM];
+#pragma unroll
+  for (int a = 0; a < WM; ++a) {
+    int64_t row = i0 + wave * 32 + a * 16 + r16;
+    row = row < M ? row : M - 1;
+    arow[a] = A + row * lda + 16 * grp;
+  }
+  // this thread's panel chunks (clamped columns)
+  const T16* bsrc[NB];
+  int bdst[NB];
+#pragma unroll
+  for (int e = 0; e < NB; ++e) {
+    const int ch = tid + e * NT;
+    const int col = (ch < CB ? ch : CB - 1) / CH, kc = (ch % CH) * 8;
+    int64_t gj = j0 + col;
+    gj = gj < N ? gj : N - 1;
+    bsrc[e] = B + gj * ldb + kc;
+    bdst[e] = col * LK + kc;
+  }
+
+  float4_t acc[WM][WN];
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b) acc[a][b] = float4_t{0, 0, 0, 0};
+
+  v8 acur[WM][2], anext[WM][2], rb[NB];
+  auto loadA = [&](v8 (&dst)[WM][2], int64_t k0) {
+#pragma unroll
+    for (int a = 0; a < WM; ++a) {
+      dst[a][0] = *(const v8*)(arow[a] + k0);
+      dst[a][1] = *(const v8*)(arow[a] + k0 + 8);
+    }
+  };
+  auto loadB = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < NB; ++e)
+      if (NB * NT == CB || tid + e * NT < CB) rb[e] = *(const v8*)(bsrc[e] + k0);
+  };
+  auto storeB = [&](int buf) {
+#pragma unroll
+    for (int e = 0; e < NB; ++e)
+      if (NB * NT == CB || tid + e * NT < CB) *(v8*)(&Bs[buf][0][0] + bdst[e]) = rb[e];
+  };
+
+  const int64_t nk = (kend - kbeg) / BK;  // whole tiles (kbeg, kend multiples of BK)
+  if (nk > 0) {
+    loadA(acur, kbeg);
+    loadB(kbeg);
+    storeB(0);
+    __syncthreads();
+    for (int64_t it = 0; it < nk; ++it) {
+      const int buf = (int)(it & 1);
+      const bool more = it + 1 < nk;
+      if (more) {
+        const int64_t k1 = kbeg + (it + 1) * BK;
+        loadB(k1);
+        loadA(anext, k1);
+      }
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
+#pragma unroll
+        for (int b = 0; b < WN; ++b) {
+          const v8 bf = *(const v8*)&Bs[buf][b * 16 + r16][16 * grp + 8 * s];
+#pragma unroll
+          for (int a = 0; a < WM; ++a) acc[a][b] = Mfma16<T16>::mma(acur[a][s], bf, acc[a][b]);
+        }
+      if (more) {
+        storeB(buf ^ 1);
+#pragma unroll
+        for (int a = 0; a < WM; ++a) {
+          acur[a][0] = anext[a][0];
+          acur[a][1] = anext[a][1];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  float* Cs = C + (int64_t)split * strideS;
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b) {
+      const int64_t col = j0 + b * 16 + r16;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = i0 + wave * 32 + a * 16 + acc_row_f32(lane, r);
+        if (row < M && col < N) Cs[row + col * ldc] = acc[a][b][r];
+      }
+    }
+}
+
+// X (rows x d fp32, ldx) -> X16 (rows x d, ldy), rounded to nearest even;
+// rows [rows, ldy) of X16 are set to zero (contraction padding).
+template <typename T16>
+__global__ __launch_bounds__(256) void convert_panel16_kernel(const float* __restrict__ X,
+                                                              int64_t rows, int64_t d,
+                                                              int64_t ldx, T16* __restrict__ Y,
+                                                              int64_t ldy) {
+  const int64_t total = ldy * d;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx % ldy, j = idx / ldy;
+    Y[idx] = i < rows ? to16(X[i + j * ldx], (T16*)nullptr) : (T16)0.0f;
+  }
+}
+
+// A (m x n fp32, lda) -> A16 (m x n, ld16) and At16 = A^T (n x m, ldt16), both
+// rounded to 16 bits (nearest even).  ld16 and ldt16 are m and n rounded up
+// to multiples of 64; the padding rows of both copies are written as zeros
+// (the contraction padding of gemm16_kernel).  64 x 64 tiles through LDS keep
+// the transposed writes coalesced; the grid covers exactly the padded sizes.
+// If rerr is given, each workgroup also writes the sum of squared rounding
+// errors (a - a16)^2 of its tile (fp64) to rerr[its linear index].
+template <typename T16>
+__global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict__ A, int64_t m,
+                                                        int64_t n, int64_t lda,
+                                                        T16* __restrict__ A16, int64_t ld16,
+                                                        T16* __restrict__ At16, int64_t ldt16,
+                                                        double* __restrict__ rerr) {
+  __shared__ T16 tile[64][66];
+  __shared__ double red[256];
+  const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  double err = 0.0;
+  for (int jj = ty; jj < 64; jj += 4) {
+    const int64_t i = i0 + tx, j = j0 + jj;
+    T16 v = (T16)0.0f;
+    if (i < m && j < n) {
+      const float a = A[i + j * lda];
+      v = to16(a, (T16*)nullptr);
+      const double e = (double)a - (double)(float)v;
+      err += e * e;
+    }
+    if (j < n) A16[i + j * ld16] = v;  // i < ld16 always
+    tile[jj][tx] = v;
+  }
+  __syncthreads();
+  for (int ii = ty; ii < 64; ii += 4) {
+    const int64_t j = j0 + tx, i = i0 + ii;
+    if (i < m) At16[j + i * ldt16] = tile[tx][ii];  // j < ldt16 always
+  }
+  if (rerr) {
+    red[threadIdx.x] = err;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) rerr[blockIdx.x + (int64_t)blockIdx.y * gridDim.x] = red[0];
+  }
+}
+
+}  // namespace
+
+// Precision-form plan: k16BM-row tiles, N covered by as few tiles of at most
+// 16 k16MaxWN columns as possible (A is read once per N tile), split-K up to
+// ~1024 workgroups with at least four whole tiles per split.  Kp is the
+// padded contraction length (a multiple of k16BK).
+struct Plan16 {
+  int wn;
+  int64_t tiles_m, tiles_n;
+  int splits;
+  int64_t kchunk;
+};
+
+int64_t pad16(int64_t K) { return (K + k16BK - 1) / k16BK * k16BK; }
+
+template <typename T16, int WN>
+int gemm16_occupancy() {
+  static const int nb = occupancy_of(gemm16_kernel<T16, WN>, 64 * k16Waves);
+  return nb;
+}
+
+template <typename T16, int WN>
+int gemm16_occupancy_wn(int wn) {
+  if constexpr (WN > 1) {
+    if (wn < WN) return gemm16_occupancy_wn<T16, WN - 1>(wn);
+  }
+  return gemm16_occupancy<T16, WN>();
+}
+
+Plan16 make_plan16(int64_t M, int64_t N, int64_t K, bool f16) {
+  Plan16 p;
+  const int64_t Kp = pad16(K);
+  const int64_t nblk = (N + 15) / 16;
+  p.tiles_n = (nblk + k16MaxWN - 1) / k16MaxWN;
+  p.wn = (int)((nblk + p.tiles_n - 1) / p.tiles_n);
+  p.tiles_m = (M + k16BM - 1) / k16BM;
+  const int64_t tiles = p.tiles_m * p.tiles_n;
+  const int64_t max_s = std::max<int64_t>(1, Kp / (4 * k16BK));
+  const int occ = f16 ? gemm16_occupancy_wn<_Float16, k16MaxWN>(p.wn)
+                      : gemm16_occupancy_wn<__bf16, k16MaxWN>(p.wn);
+  choose_splits(tiles, Kp, k16BK, max_s, (int64_t)occ * cu_count(), 2.0 * k16BM * 16 * p.wn,
+                900e12, 4.0 * (double)M * (double)N, &p.kchunk, &p.splits);
+  return p;
+}
+
+template <typename T16, int WN>
+static void run_gemm16(const Gemm16Args& g, const Plan16& p, float* dst, int64_t lddst,
+                       int64_t strideS, hipStream_t st) {
+  const unsigned T = (unsigned)(p.tiles_m * p.tiles_n * p.splits);
+  hipLaunchKernelGGL((gemm16_kernel<T16, WN>), dim3(T), dim3(64 * k16Waves), 0, st,
+                     (const T16*)g.A, g.lda, (const T16*)g.B, g.ldb, dst, lddst, strideS, g.M,
+                     g.N, pad16(g.K), p.kchunk, (int)p.tiles_m, (int)p.tiles_n);
+}
+
+template <typename T16, int WN>
+static void dispatch16(const Gemm16Args& g, const Plan16& p, float* dst, int64_t lddst,
+                       int64_t strideS, hipStream_t st) {
+  if constexpr (WN > 1) {
+    if (p.wn < WN) return dispatch16<T16, WN - 1>(g, p, dst, lddst, strideS, st);
+  }
+  run_gemm16<T16, WN>(g, p, dst, lddst, strideS, st);
+}
+
+template <typename T16>
+static hipError_t gemm16_typed(const Gemm16Args& g, hipStream_t st) {
+  const Plan16 p = make_plan16(g.M, g.N, g.K, g.f16);
+  const bool direct = (p.splits == 1);
+  float* dst = direct ? g.C : (float*)g.partial;
+  const int64_t lddst = direct ? g.ldc : g.M;
+  const int64_t strideS = g.M * g.N;
+  if (!direct && (g.partial == nullptr ||
+                  g.partial_bytes < (size_t)p.splits * (size_t)strideS * sizeof(float)))
+    return hipErrorInvalidValue;
+  // whole 16-byte fragment loads over the zero-padded contraction
+  if (g.lda < pad16(g.K) || g.ldb < pad16(g.K) || (g.lda % 8) != 0 || (g.ldb % 8) != 0 ||
+      (((uintptr_t)g.A | (uintptr_t)g.B) & 15) != 0)
+    return hipErrorInvalidValue;
+  if (g.ev_begin) (void)hipEventRecord((hipEvent_t)g.ev_begin, st);
+  dispatch16<T16, k16MaxWN>(g, p, dst, lddst, strideS, st);
+  if (g.ev_end) (void)hipEventRecord((hipEvent_t)g.ev_end, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || direct) return e;
+  return launch_splitk_reduce_f32((const float*)g.partial, g.M, g.N, p.splits, g.C, g.ldc, st);
+}
+
+hipError_t launch_gemm16(const Gemm16Args& g, hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  return g.f16 ? gemm16_typed<_Float16>(g, st) : gemm16_typed<__bf16>(g, st);
+}
+
+size_t gemm16_partial_bytes(int64_t M, int64_t N, int64_t K, bool f16) {
+  const Plan16 p = make_plan16(M, N, K, f16);
+  return p.splits == 1 ? 0 : (size_t)p.splits * (size_t)M * (size_t)N * 4;
+}
+
+int64_t gemm16_ld(int64_t K) { return pad16(K); }
+
+hipError_t launch_convert_panel16(const float* X, int64_t rows, int64_t d, int64_t ldx, void* Y,
+                                  int64_t ldy, bool f16, hipStream_t st) {
+  if (rows <= 0 || d <= 0) return hipSuccess;
+  if (ldy < pad16(rows) || ldy % k16BK != 0) return hipErrorInvalidValue;
+  const int64_t total = ldy * d;
+  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
+  if (f16)
+    hipLaunchKernelGGL(convert_panel16_kernel<_Float16>, dim3(blocks), dim3(256), 0, st, X, rows,
+                       d, ldx, (_Float16*)Y, ldy);
+  else
+    hipLaunchKernelGGL(convert_panel16_kernel<__bf16>, dim3(blocks), dim3(256), 0, st, X, rows, d,
+                       ldx, (__bf16*)Y, ldy);
+  return hipGetLastError();
+}
+
+int64_t convert16_blocks(int64_t m, int64_t n) { return ((m + 63) / 64) * ((n + 63) / 64); }
+
+hipError_t launch_convert16(const float* A, int64_t m, int64_t n, int64_t lda, void* A16,
+                            int64_t ld16, void* At16, int64_t ldt16, bool f16, hipStream_t st,
+                            double* rerr) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  if (ld16 < pad16(m) || ldt16 < pad16(n)) return hipErrorInvalidValue;
+  dim3 grid((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64));
+  if (f16)
+    hipLaunchKernelGGL(convert16_kernel<_Float16>, grid, dim3(256), 0, st, A, m, n, lda,
+                       (_Float16*)A16, ld16, (_Float16*)At16, ldt16, rerr);
+  else
+    hipLaunchKernelGGL(convert16_kernel<__bf16>, grid, dim3(256), 0, st, A, m, n, lda,
+                       (__bf16*)A16, ld16, (__bf16*)At16, ldt16, rerr);
+  return hipGetLastError();
+}
+
+}  // namespace rqlp

@@ -155,6 +155,27 @@ hipError_t launch_count_flags(const int* col_flags, int64_t d, int* count, hipSt
 hipError_t launch_check_finite(const void* A, int64_t m, int64_t n, int64_t lda, Dtype dt,
                                int* flags, hipStream_t st);
 
+// ---- launch planning shared by the product kernels (gemm.hip) ----
+int cu_count();
+void choose_splits(int64_t tiles, int64_t K, int bk, int64_t max_s, int64_t slots,
+                   double tile_flops_per_k, double rate, double out_bytes, int64_t* chunk_out,
+                   int* splits_out);
+constexpr int kTargetWG = 1024;
+// Workgroups of one kernel instantiation that fit on a CU at once (from its
+// register and LDS use; 1 when the query fails, e.g. without a device).
+template <typename F>
+inline int occupancy_of(F kernel, int threads) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess ||
+      nb < 1)
+    nb = 1;
+  return nb;
+}
+
+// C (M x N, ldc) = sum over s < S of P[s] (each M x N, tight), fixed order.
+hipError_t launch_splitk_reduce_f32(const float* P, int64_t M, int64_t N, int S, float* C,
+                                    int64_t ldc, hipStream_t st);
+
 // ---- grouped launches (many independent problems in one launch) ----
 // One product C = op(A) B of a grouped launch (whole contraction, no split).
 struct GroupGemm {
