@@ -13,6 +13,7 @@
 // contraction.  Partial sums are reduced in a fixed order (bitwise
 // reproducible).  Gram products compute only upper tiles and mirror them.
 #include <algorithm>
+#include <type_traits>
 #include <vector>
 
 #include "rqlp_internal.h"
@@ -37,17 +38,24 @@ struct Mfma<float> {
   }
 };
 
+// REMV > 0 (with WAVES_N = 1): the tile is 16 WN + REMV columns wide; the
+// last REMV columns (the ragged end of a skinny product, e.g. d = 210 =
+// 13 x 16 + 2) are computed on the vector ALUs from the same A fragments
+// the MFMAs use, instead of padding them to a whole 16-column MFMA block.
+// Each lane sums its quarter of the k values; the four quarters are added
+// across lanes (fixed order) at the end.
 template <typename TI, typename TC, typename TO, bool TA, int WAVES_M, int WAVES_N, int WM,
-          int WN, int BK>
+          int WN, int BK, int REMV = 0>
 __device__ __forceinline__ void gemm_body(const TI* __restrict__ A, int64_t lda,
                                           const TI* __restrict__ B, int64_t ldb,
                                           TO* __restrict__ C, int64_t ldc, int64_t strideS,
                                           int64_t M, int64_t N, int64_t K, int64_t kchunk,
                                           int gram, const int tile_m, const int tile_n,
                                           const int split) {
+  static_assert(REMV == 0 || WAVES_N == 1, "vector-ALU columns need one wave column");
   constexpr int NT = 64 * WAVES_M * WAVES_N;
   constexpr int BM = 16 * WM * WAVES_M;
-  constexpr int BN = 16 * WN * WAVES_N;
+  constexpr int BN = 16 * WN * WAVES_N + REMV;
   constexpr int LA = BM + 1;
   constexpr int LB = BN + 1;
   constexpr int NA = (BM * BK + NT - 1) / NT;
@@ -69,6 +77,11 @@ __device__ __forceinline__ void gemm_body(const TI* __restrict__ A, int64_t lda,
   for (int a = 0; a < WM; ++a)
 #pragma unroll
     for (int b = 0; b < WN; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+  TC vacc[WM][REMV > 0 ? REMV : 1];
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int c = 0; c < (REMV > 0 ? REMV : 1); ++c) vacc[a][c] = (TC)0;
 
   TI ra[NA], rb[NB];
 
@@ -146,6 +159,14 @@ __device__ __forceinline__ void gemm_body(const TI* __restrict__ A, int64_t lda,
         for (int a = 0; a < WM; ++a)
 #pragma unroll
           for (int b = 0; b < WN; ++b) acc[a][b] = Mfma<TC>::mma(af[a], bf[b], acc[a][b]);
+        if constexpr (REMV > 0) {
+#pragma unroll
+          for (int c = 0; c < REMV; ++c) {
+            const TC bv = (TC)Bs[buf][kr][16 * WN + c];
+#pragma unroll
+            for (int a = 0; a < WM; ++a) vacc[a][c] = af[a] * bv + vacc[a][c];
+          }
+        }
       }
       if (it + 1 < nk) sstore(buf ^ 1);
       __syncthreads();
@@ -164,6 +185,19 @@ __device__ __forceinline__ void gemm_body(const TI* __restrict__ A, int64_t lda,
         if (row < M && col < N) Cs[row + col * ldc] = (TO)acc[a][b][r];
       }
     }
+  if constexpr (REMV > 0) {
+#pragma unroll
+    for (int a = 0; a < WM; ++a)
+#pragma unroll
+      for (int c = 0; c < REMV; ++c) {
+        TC v = vacc[a][c];
+        v += __shfl_xor(v, 16);
+        v += __shfl_xor(v, 32);
+        const int64_t row = i0 + (wave_m * WM + a) * 16 + (lane & 15);
+        const int64_t col = j0 + 16 * WN + c;
+        if (lane < 16 && row < M && col < N) Cs[row + col * ldc] = (TO)v;
+      }
+  }
 }
 
 template <typename TI, typename TC, typename TO, bool TA, int WAVES_M, int WAVES_N, int WM,
@@ -175,6 +209,21 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(
   gemm_body<TI, TC, TO, TA, WAVES_M, WAVES_N, WM, WN, BK>(A, lda, B, ldb, C, ldc, strideS, M, N,
                                                           K, kchunk, gram, blockIdx.x,
                                                           blockIdx.y, blockIdx.z);
+}
+
+// Skinny products with a ragged width: 4 waves stacked along M (16 rows
+// each), WN MFMA blocks of 16 columns plus 4 vector-ALU columns per tile.
+constexpr int kRemWavesM = 4, kRemV = 4;
+template <typename TI, typename TC, typename TO, bool TA, int WN>
+__global__ __launch_bounds__(64 * kRemWavesM) void gemm_rem_kernel(
+    const TI* __restrict__ A, int64_t lda, const TI* __restrict__ B, int64_t ldb,
+    TO* __restrict__ C, int64_t ldc, int64_t strideS, int64_t M, int64_t N, int64_t K,
+    int64_t kchunk) {
+  // 8-deep tiles for A X (row tiles of A strided in memory: keeps the
+  // register count within two waves per SIMD) and for the widest tiles
+  // (keeps the LDS of one workgroup under the per-workgroup limit)
+  gemm_body<TI, TC, TO, TA, kRemWavesM, 1, 1, WN, (TA && WN <= 13) ? 16 : 8, kRemV>(
+      A, lda, B, ldb, C, ldc, strideS, M, N, K, kchunk, 0, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // Grouped form: workgroup b computes tile (bmap[b].y, bmap[b].z) of product
@@ -259,11 +308,28 @@ int gemm_slots(Dtype in_t, Dtype out_t, int trans_a, bool gram, int wn) {
 }
 
 struct Plan {
-  int wn;          // 16-column blocks per wave along N (BN = 32 * wn)
+  int wn;          // 16-column blocks per wave along N (BN = 32 * wn; rem: 16 * wn + 4)
   int64_t tiles_m, tiles_n;
   int splits;
   int64_t kchunk;
+  bool rem = false;  // gemm_rem_kernel layout
 };
+
+template <typename TI, typename TC, typename TO, bool TA, int WN>
+int rem_occupancy() {
+  static const int nb = occupancy_of(gemm_rem_kernel<TI, TC, TO, TA, WN>, 64 * kRemWavesM);
+  return nb;
+}
+
+template <typename T, bool TA, int WN = 16>
+int rem_occupancy_wn(int wn) {
+  if constexpr (WN > 1) {
+    if (wn < WN) return rem_occupancy_wn<T, TA, WN - 1>(wn);
+  }
+  return rem_occupancy<T, T, T, TA, WN>();
+}
+
+constexpr int kRemMaxWN = 16;
 
 // Tile and split choice.  The A-streaming products (K = m or n, long) get
 // one N tile covering d when d <= 256 (A is then read once), except that
@@ -284,6 +350,28 @@ Plan make_plan(int trans_a, int64_t M, int64_t N, int64_t K, bool gram, Dtype in
   }
   p.tiles_m = gram ? (M + kGramBM - 1) / kGramBM : (M + kBM - 1) / kBM;
   const int64_t max_s = std::max<int64_t>(1, K / (kBK * 8));
+  if (!gram && max_s > 1 && in_t == out_t) {
+    // A-streaming product: MFMA blocks plus vector-ALU columns, as few N
+    // tiles (of at most 16 x 16 + 4 columns) as possible.
+    const int64_t wmax = 16 * kRemMaxWN + kRemV;
+    const int64_t ntn = (N + wmax - 1) / wmax;
+    const int64_t per = (N + ntn - 1) / ntn;
+    int64_t wn = per / 16;
+    if (per % 16 > kRemV) ++wn;
+    p.wn = (int)std::max<int64_t>(1, std::min<int64_t>(wn, kRemMaxWN));
+    p.rem = true;
+    const int64_t BN = 16 * p.wn + kRemV;
+    p.tiles_n = (N + BN - 1) / BN;
+    const int occ = in_t == DT_F64
+                        ? (trans_a ? rem_occupancy_wn<double, true>(p.wn)
+                                   : rem_occupancy_wn<double, false>(p.wn))
+                        : (trans_a ? rem_occupancy_wn<float, true>(p.wn)
+                                   : rem_occupancy_wn<float, false>(p.wn));
+    choose_splits(p.tiles_m * p.tiles_n, K, kBK, max_s, (int64_t)occ * cu_count(),
+                  2.0 * kBM * BN, in_t == DT_F64 ? 45e12 : 110e12,
+                  (out_t == DT_F64 ? 8.0 : 4.0) * (double)M * (double)N, &p.kchunk, &p.splits);
+    return p;
+  }
   if (!gram && max_s == 1) {
     while (p.wn > 1 && p.tiles_m * ((N + 32 * p.wn - 1) / (32 * p.wn)) < kTargetWG / 2)
       p.wn = (p.wn + 1) / 2;
@@ -325,6 +413,18 @@ void dispatch_wn(const GemmArgs& g, const Plan& p, TO* dst, int64_t lddst, int64
   }
 }
 
+template <typename TI, typename TC, typename TO, bool TA, int WN>
+void dispatch_rem(const GemmArgs& g, const Plan& p, TO* dst, int64_t lddst, int64_t strideS,
+                  hipStream_t st) {
+  if constexpr (WN > 1) {
+    if (p.wn < WN) return dispatch_rem<TI, TC, TO, TA, WN - 1>(g, p, dst, lddst, strideS, st);
+  }
+  dim3 grid((unsigned)p.tiles_m, (unsigned)p.tiles_n, (unsigned)p.splits);
+  hipLaunchKernelGGL((gemm_rem_kernel<TI, TC, TO, TA, WN>), grid, dim3(64 * kRemWavesM), 0, st,
+                     (const TI*)g.A, g.lda, (const TI*)g.B, g.ldb, dst, lddst, strideS, g.M, g.N,
+                     g.K, p.kchunk);
+}
+
 template <typename TI, typename TC, typename TO>
 hipError_t gemm_typed(const GemmArgs& g, hipStream_t st) {
   const Plan p = make_plan(g.trans_a, g.M, g.N, g.K, g.gram, g.in_t, g.out_t);
@@ -341,6 +441,11 @@ hipError_t gemm_typed(const GemmArgs& g, hipStream_t st) {
     hipLaunchKernelGGL((gemm_kernel<TI, TC, TO, true, kWavesM, kWavesN, kGramWM, 1, kBK>), grid,
                        dim3(64 * kWavesM * kWavesN), 0, st, (const TI*)g.A, g.lda,
                        (const TI*)g.B, g.ldb, dst, lddst, strideS, g.M, g.N, g.K, p.kchunk, 1);
+  } else if (p.rem) {
+    if constexpr (std::is_same<TI, TO>::value) {
+      if (g.trans_a) dispatch_rem<TI, TC, TO, true, kRemMaxWN>(g, p, dst, lddst, strideS, st);
+      else dispatch_rem<TI, TC, TO, false, kRemMaxWN>(g, p, dst, lddst, strideS, st);
+    }
   } else if (g.trans_a) {
     dispatch_wn<TI, TC, TO, true>(g, p, dst, lddst, strideS, st);
   } else {
