@@ -2,7 +2,8 @@
 //
 // Features: the singular values of the 64-column sketch Y = A^T Omega[:, :64]
 // (the leading Philox columns of the method's own sketch) from the
-// eigenvalues of its fp64 Gram matrix, by cyclic Jacobi in one workgroup,
+// eigenvalues of its fp64 Gram matrix (tridiagonal reduction and bisection
+// in one workgroup),
 // turned into 65 numbers: log10(sigma_i / sigma_1) clamped to [-6, 0] and
 // divided by 6 (i = 1..64), then k / 256.
 //
@@ -26,112 +27,132 @@ constexpr int kNs = 64;            // sketch columns read by the predictor
 constexpr int kJacobiThreads = 256;
 
 // ---------------------------------------------------------------- features
-// Cyclic Jacobi eigenvalues of the symmetric 64 x 64 G (column-major, ldg),
-// round-robin ordering: in each of the 63 steps of a sweep the 32 disjoint
-// pairs are rotated at once (rotations first, then rows, then columns).
-// Sweeps stop when the off-diagonal mass falls below (1e-14)^2 of the
-// diagonal's or after 30 sweeps.  Then the features as described above.
+// Eigenvalues of the symmetric 64 x 64 G (column-major, ldg) in one
+// workgroup: Householder reduction to tridiagonal form (62 reflections,
+// each a reduction for the vector, a symmetric matrix-vector product and a
+// rank-2 update on the trailing block in LDS), then bisection with Sturm
+// counts, one thread per eigenvalue (thread i finds the i-th smallest, so
+// the order comes for free).  Both steps are backward stable: the
+// eigenvalues carry an absolute error of a few units of roundoff times
+// ||G||, which resolves sigma_i / sigma_1 = sqrt(lambda_i / lambda_1) well
+// below the features' clamp at 1e-6.  Then the features as described above.
+__device__ __forceinline__ int sturm_count(const double* dg, const double* eo2, int n,
+                                           double x, double pivmin) {
+  // number of eigenvalues of the tridiagonal (dg, off-diagonal^2 eo2) below x
+  int cnt = 0;
+  double q = dg[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0.0) ++cnt;
+  for (int j = 1; j < n; ++j) {
+    q = (dg[j] - x) - eo2[j - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+
 __global__ __launch_bounds__(kJacobiThreads) void features_kernel(const double* __restrict__ G,
                                                                  int64_t ldg, int k,
                                                                  float* __restrict__ feat) {
   __shared__ double a[kNs][kNs + 1];
-  __shared__ double cs[kNs / 2], sn[kNs / 2];
-  __shared__ int pp[kNs / 2], qq[kNs / 2];
-  __shared__ double red[kJacobiThreads];
+  __shared__ double v[kNs], pw[kNs];
+  __shared__ double dg[kNs], eo2[kNs];
   __shared__ double lam[kNs];
-  __shared__ int stop;
-  const int tid = threadIdx.x;
+  __shared__ double scal[4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int e = tid; e < kNs * kNs; e += kJacobiThreads) {
     const int i = e % kNs, j = e / kNs;
     a[i][j] = G[i + (int64_t)j * ldg];
   }
-  if (tid == 0) stop = 0;
   __syncthreads();
-  for (int sweep = 0; sweep < 30; ++sweep) {
-    // convergence test on the current matrix
-    double off = 0.0, dia = 0.0;
-    for (int e = tid; e < kNs * kNs; e += kJacobiThreads) {
-      const int i = e % kNs, j = e / kNs;
-      const double v = a[i][j] * a[i][j];
-      if (i == j) dia += v; else off += v;
-    }
-    red[tid] = off;
-    __syncthreads();
-    for (int s = kJacobiThreads / 2; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
-    }
-    const double off_all = red[0];
-    __syncthreads();
-    red[tid] = dia;
-    __syncthreads();
-    for (int s = kJacobiThreads / 2; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
-    }
-    if (tid == 0) stop = (off_all <= 1e-28 * red[0]) ? 1 : 0;
-    __syncthreads();
-    if (stop) break;
-    for (int step = 0; step < kNs - 1; ++step) {
-      if (tid < kNs / 2) {
-        // tournament pairing: slot 0 fixed, slots 1..63 rotate by `step`
-        const int s1 = tid, s2 = kNs - 1 - tid;
-        const int p = (s1 == 0) ? 0 : ((s1 - 1 + step) % (kNs - 1)) + 1;
-        const int q = ((s2 - 1 + step) % (kNs - 1)) + 1;
-        const double apq = a[p][q];
-        double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          const double tau = (a[q][q] - a[p][p]) / (2.0 * apq);
-          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = t * c;
-        }
-        cs[tid] = c;
-        sn[tid] = s;
-        pp[tid] = p;
-        qq[tid] = q;
+  for (int kk = 0; kk < kNs - 2; ++kk) {
+    const int r0 = kk + 1, len = kNs - r0;  // reflect rows r0..63 of column kk
+    if (wave == 0) {
+      const double x = lane < len ? a[r0 + lane][kk] : 0.0;
+      double ss = x * x;
+      for (int w = 32; w > 0; w >>= 1) ss += __shfl_xor(ss, w);
+      const double x0 = __shfl(x, 0);
+      const double nrm = sqrt(ss);
+      const double alpha = x0 >= 0.0 ? -nrm : nrm;
+      const double vv = lane == 0 ? x0 - alpha : x;
+      double v2 = vv * vv;
+      for (int w = 32; w > 0; w >>= 1) v2 += __shfl_xor(v2, w);
+      if (lane < len) v[lane] = vv;
+      if (lane == 0) {
+        scal[0] = v2 > 0.0 ? 2.0 / v2 : 0.0;   // beta
+        scal[1] = v2 > 0.0 ? alpha : x0;         // the new off-diagonal entry
       }
-      __syncthreads();
-      // rows: (A_p, A_q) <- (c A_p - s A_q, s A_p + c A_q)
-      for (int e = tid; e < (kNs / 2) * kNs; e += kJacobiThreads) {
-        const int r = e / kNs, j = e % kNs;
-        const int p = pp[r], q = qq[r];
-        const double c = cs[r], s = sn[r];
-        const double x = a[p][j], y = a[q][j];
-        a[p][j] = c * x - s * y;
-        a[q][j] = s * x + c * y;
-      }
-      __syncthreads();
-      // columns: (A_:p, A_:q) <- (c A_:p - s A_:q, s A_:p + c A_:q)
-      for (int e = tid; e < (kNs / 2) * kNs; e += kJacobiThreads) {
-        const int r = e / kNs, i = e % kNs;
-        const int p = pp[r], q = qq[r];
-        const double c = cs[r], s = sn[r];
-        const double x = a[i][p], y = a[i][q];
-        a[i][p] = c * x - s * y;
-        a[i][q] = s * x + c * y;
-      }
-      __syncthreads();
     }
+    __syncthreads();
+    const double beta = scal[0];
+    // p = beta A22 v: four threads per row, 16 columns each, summed across lanes
+    if (tid < 4 * kNs) {
+      const int row = tid >> 2, part = tid & 3;
+      double sacc = 0.0;
+      if (row < len) {
+        for (int j = part; j < len; j += 4) sacc += a[r0 + row][r0 + j] * v[j];
+      }
+      sacc += __shfl_xor(sacc, 1);
+      sacc += __shfl_xor(sacc, 2);
+      if (part == 0 && row < len) pw[row] = beta * sacc;
+    }
+    __syncthreads();
+    // w = p - (beta / 2) (p^T v) v
+    if (wave == 0) {
+      double pv = lane < len ? pw[lane] * v[lane] : 0.0;
+      for (int w = 32; w > 0; w >>= 1) pv += __shfl_xor(pv, w);
+      const double K = 0.5 * beta * pv;
+      if (lane < len) pw[lane] -= K * v[lane];
+    }
+    __syncthreads();
+    // A22 -= v w^T + w v^T; column kk becomes (alpha, 0, ..., 0) below the diagonal
+    for (int e = tid; e < len * len; e += kJacobiThreads) {
+      const int i = e % len, j = e / len;
+      a[r0 + i][r0 + j] -= v[i] * pw[j] + pw[i] * v[j];
+    }
+    if (tid < len) {
+      const double val = tid == 0 ? scal[1] : 0.0;
+      a[r0 + tid][kk] = val;
+      a[kk][r0 + tid] = val;
+    }
+    __syncthreads();
   }
-  // sigma_i = sqrt(max(lambda_i, 0)), sorted descending by rank counting
-  if (tid < kNs) lam[tid] = sqrt(fmax(a[tid][tid], 0.0));
+  if (tid < kNs) {
+    dg[tid] = a[tid][tid];
+    const double o = tid + 1 < kNs ? a[tid + 1][tid] : 0.0;
+    eo2[tid] = o * o;
+  }
   __syncthreads();
   if (tid < kNs) {
-    const double v = lam[tid];
-    int rank = 0;
+    // Gershgorin interval and a pivot floor relative to ||T||
+    double lo = 1e300, hi = -1e300, tn = 0.0;
     for (int j = 0; j < kNs; ++j) {
-      const double w = lam[j];
-      rank += (w > v || (w == v && j < tid)) ? 1 : 0;
+      const double r = (j > 0 ? sqrt(eo2[j - 1]) : 0.0) + (j + 1 < kNs ? sqrt(eo2[j]) : 0.0);
+      lo = fmin(lo, dg[j] - r);
+      hi = fmax(hi, dg[j] + r);
+      tn = fmax(tn, fabs(dg[j]) + r);
     }
-    double s1 = 0.0;
-    for (int j = 0; j < kNs; ++j) s1 = fmax(s1, lam[j]);
+    const double pivmin = fmax(tn, 1e-300) * 1e-300 + 1e-300;
+    const double tol = 4.0 * 2.220446049250313e-16 * fmax(tn, 1e-300);
+    // the (tid)-th smallest eigenvalue: count(x) <= tid < count(hi)
+    double l = lo, h = hi;
+    for (int it = 0; it < 200 && h - l > tol; ++it) {
+      const double mid = 0.5 * (l + h);
+      if (sturm_count(dg, eo2, kNs, mid, pivmin) <= tid) l = mid;
+      else h = mid;
+    }
+    lam[tid] = sqrt(fmax(0.5 * (l + h), 0.0));
+  }
+  __syncthreads();
+  if (tid < kNs) {
+    const double s1 = lam[kNs - 1];   // the largest (ascending order)
+    const double v0 = lam[tid];
     float f = -1.0f;
-    if (s1 > 0.0 && v > 0.0) {
-      const double lg = log10(v / s1);
+    if (s1 > 0.0 && v0 > 0.0) {
+      const double lg = log10(v0 / s1);
       f = (float)(fmin(fmax(lg, -6.0), 0.0) / 6.0);
     }
-    feat[rank] = f;
+    feat[kNs - 1 - tid] = f;            // descending order
   }
   if (tid == 0) feat[kNs] = (float)k / 256.0f;
 }

@@ -91,6 +91,7 @@ struct Layout {
   int64_t ldp16;        // leading dimension of the 16-bit copy of a panel
   // predictor and error judge (randqlp_factor_auto only)
   size_t om64, y64, g64, feat, mlp, cls, jd, sums, sres, rerr;
+  size_t part2, part2_bytes;  // split-K scratch of the predictor's products
   size_t flags_bytes;  // status words cleared at the start of a call
 };
 
@@ -124,14 +125,19 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
       part = std::max(part, gemm16_partial_bytes(m, d, n, f16));
     }
   }
+  size_t part2 = 0;
   if (autoq) {
-    part = std::max(part, gemm_partial_bytes(1, n, kPredCols, m, dt, dt, false));
-    part = std::max(part, gemm_partial_bytes(1, kPredCols, kPredCols, n, dt, DT_F64, true));
+    // the predictor runs on a second stream beside the first sketch: its
+    // products get their own split-K scratch
+    part2 = std::max(part2, gemm_partial_bytes(1, n, kPredCols, m, dt, dt, false));
+    part2 = std::max(part2, gemm_partial_bytes(1, kPredCols, kPredCols, n, dt, DT_F64, true));
     part = std::max(part, gemm_partial_bytes(1, d, d, m, dt, dt, false));
     part = std::max(part, gemm_partial_bytes(0, m, d, d, dt, dt, false));
   }
   L.part = take(part);
   L.part_bytes = part;
+  L.part2 = autoq ? take(std::max<size_t>(part2, 256)) : 0;
+  L.part2_bytes = autoq ? std::max<size_t>(part2, 256) : 0;
   L.G = take((size_t)d * d * 8);
   for (int i = 0; i < 4; ++i) L.R[i] = take((size_t)d * d * 8);
   for (int i = 0; i < 2; ++i) L.Racc[i] = take((size_t)d * d * 8);
@@ -767,17 +773,37 @@ hipError_t feature_sketch(Ctx& c, const void* A, int64_t m, int64_t n, int64_t l
   return launch_features(g64, kPredCols, k, feat, c.st);
 }
 
-// Features -> MLP -> predicted class (read back to the host).
-hipError_t predict_q(Ctx& c, const FactorArgs& f, int k, const float* params, int* cls) {
+// A second stream per device (default priority) for work that can run
+// beside the main sequence; created once, kept for the process.
+hipError_t aux_stream(hipStream_t* out) {
+  static std::mutex mu;
+  static hipStream_t streams[64] = {};
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> g(mu);
+  if (!streams[dev]) HIP_TRY(hipStreamCreateWithFlags(&streams[dev], hipStreamNonBlocking));
+  *out = streams[dev];
+  return hipSuccess;
+}
+
+// Features -> MLP -> predicted class, enqueued on stream `st` with the
+// predictor's own scratch (it may run beside the main sequence), then read
+// back to the host (waits for `st` only).
+hipError_t predict_q(Ctx& c, const FactorArgs& f, int k, const float* params, int* cls,
+                     hipStream_t st) {
+  Ctx cp = c;
+  cp.st = st;
+  cp.lay.part = c.lay.part2;
+  cp.lay.part_bytes = c.lay.part2_bytes;
   float* mlp = c.at<float>(c.lay.mlp);
   int* dcls = c.at<int>(c.lay.cls);
-  HIP_TRY(feature_sketch(c, f.A, f.m, f.n, f.lda, k, c.seed, c.ws + c.lay.om64,
+  HIP_TRY(feature_sketch(cp, f.A, f.m, f.n, f.lda, k, c.seed, c.ws + c.lay.om64,
                          c.ws + c.lay.y64, c.at<double>(c.lay.g64), c.at<float>(c.lay.feat)));
-  HIP_TRY(mlp_forward_dev(params, c.at<float>(c.lay.feat), 1, mlp, mlp + kNH, mlp + 2 * kNH,
-                          c.st));
-  HIP_TRY(launch_argmax(mlp + 2 * kNH, kNC, dcls, c.st));
-  HIP_TRY(hipMemcpyAsync(cls, dcls, sizeof(int), hipMemcpyDeviceToHost, c.st));
-  return hipStreamSynchronize(c.st);
+  HIP_TRY(mlp_forward_dev(params, c.at<float>(c.lay.feat), 1, mlp, mlp + kNH, mlp + 2 * kNH, st));
+  HIP_TRY(launch_argmax(mlp + 2 * kNH, kNC, dcls, st));
+  HIP_TRY(hipMemcpyAsync(cls, dcls, sizeof(int), hipMemcpyDeviceToHost, st));
+  return hipStreamSynchronize(st);
 }
 
 // Error judge after a run with q_hat rounds: sums = {||A||^2, ||L||^2,
@@ -876,20 +902,29 @@ rqlp_status randqlp_factor_auto(const void* A, int64_t m, int64_t n, int k, int 
   rqlp_auto_info ai;
   std::memset(&ai, 0, sizeof ai);
   int cls = 0;
-  hipError_t e = predict_q(c, f, k, params, &cls);
-  if (e != hipSuccess) return fail(RQLP_E_HIP, "predictor: %s", hipGetErrorString(e));
-  ai.q_predicted = cls;
   Outcome r;
   int q_used = q_fallback;
   bool done = false;
   const PanelMode mode0 = start_mode(o);
+  // The first sketch and its orth() do not depend on q: enqueue them, and
+  // run the predictor on the second stream beside them.
+  hipStream_t aux = nullptr;
+  hipEvent_t ready = nullptr;
+  c.orth_calls = 0;
+  hipError_t e = aux_stream(&aux);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(ready, c.st);           // A is ready here
+  if (e == hipSuccess) e = hipMemsetAsync(c.flags(), 0, c.lay.flags_bytes, c.st);
+  if (e == hipSuccess) e = stage_start(c, f, mode0);
+  if (e == hipSuccess) e = hipStreamWaitEvent(aux, ready, 0);
+  if (e == hipSuccess) e = predict_q(c, f, k, params, &cls, aux);
+  if (ready) (void)hipEventDestroy(ready);
+  if (e != hipSuccess) return fail(RQLP_E_HIP, "predictor: %s", hipGetErrorString(e));
+  ai.q_predicted = cls;
   if (cls < q_fallback) {
     // the method with q_hat, then the judge
     f.q = cls;
-    c.orth_calls = 0;
-    e = hipMemsetAsync(c.flags(), 0, c.lay.flags_bytes, c.st);
-    if (e == hipSuccess) e = stage_start(c, f, mode0);
-    if (e == hipSuccess) e = stage_rounds(c, f, mode0, cls);
+    e = stage_rounds(c, f, mode0, cls);
     if (e == hipSuccess) e = stage_finish(c, f, mode0);
     double sums[4] = {0, 0, 0, 0};
     if (e == hipSuccess) e = judge(c, f, sums);
@@ -919,10 +954,22 @@ rqlp_status randqlp_factor_auto(const void* A, int64_t m, int64_t n, int k, int 
         }
       }
     }
+  } else {
+    // q_hat >= q_fallback: continue the plain method with q_fallback
+    f.q = q_fallback;
+    e = stage_rounds(c, f, mode0, q_fallback);
+    if (e == hipSuccess) e = stage_finish(c, f, mode0);
+    if (e != hipSuccess) return fail(RQLP_E_HIP, "launch failed: %s", hipGetErrorString(e));
+    int fl[4] = {0, 0, 0, 0};
+    if ((s = read_flags(c, fl)) != RQLP_OK) return s;
+    if ((fl[0] & (FLAG_NONPOS_PIVOT | FLAG_NONFINITE | FLAG_SECOND_PASS)) == 0) {
+      r.completed = fl[2];
+      done = true;
+    }
   }
   if (!done) {
-    // q_hat >= q_fallback, or a panel needed the stronger treatment:
-    // the plain method with q_fallback (escalating as randqlp_factor does)
+    // a panel needed the stronger treatment: the plain method with
+    // q_fallback from the start, escalating as randqlp_factor does
     f.q = q_fallback;
     q_used = q_fallback;
     if ((s = run_with_escalation(c, f, o, mode0, r)) != RQLP_OK) return s;
