@@ -236,7 +236,7 @@ rqlp_status randqlp_mlp_train(float* params, float* m, float* v, const float* X,
  * randqlp_factor after the grouped run.  tune != 0 times the candidate tile
  * widths of the products with A on this batch and records the fastest in
  * the process-wide table (see randqlp_tune_save); tune = 0 takes the table's
- * entry, else per-matrix widths.  The plan owns its device
+ * entry, else the per-matrix MFMA + vector-ALU layout.  The plan owns its device
  * memory (allocated here, freed by randqlp_batch_destroy). */
 typedef struct rqlp_batch rqlp_batch;
 
@@ -276,7 +276,8 @@ rqlp_status randqlp_factor_batched(int count, const void* const* A, const int64_
 /* The tile-width table: text lines "dtype trans dbucket wn" (dtype 0 = f64,
  * 1 = f32; trans 1 = A^T X, 0 = A X; dbucket = 32, 64, 128 or 256, the
  * bucket of the largest d; wn = 1, 2, 4 or 8 for one width everywhere, 0 for
- * each matrix's own width covering its d).  load merges into the table. */
+ * each matrix's own width covering its d, 16 for the MFMA + vector-ALU
+ * layout with each matrix's own width).  load merges into the table. */
 rqlp_status randqlp_tune_save(const char* path);
 rqlp_status randqlp_tune_load(const char* path);
 

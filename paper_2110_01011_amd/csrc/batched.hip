@@ -18,7 +18,8 @@
 // (precision, product orientation, bucket of the largest d), and saved to /
 // loaded from a text file.  Candidates: one width for every matrix, or
 // width 0 = per class (each matrix gets the width that covers its d in one
-// tile, one launch per width present, so A is read once).
+// tile, one launch per width present, so A is read once), or 16 = the
+// remainder layout per class (MFMA blocks plus vector-ALU columns).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -63,12 +64,15 @@ struct Launch {
   int64_t count = 0, nblocks = 0;
 };
 
-// A product step: one launch per tile width used.  wn > 0: every matrix
+// A product step: one launch per tile width used.  wn in 1..8: every matrix
 // with that width; wn = 0 ("per class"): each matrix with the width that
 // covers its d in one tile (1, 2, 4 or 8 blocks of 32 columns), one launch
-// per width present.
+// per width present; wn = kRemSet: the remainder layout (16 c MFMA columns
+// plus 4 vector-ALU columns, c from grouped_rem_class), one launch per class.
+constexpr int kRemSet = 16;
 struct ProdSet {
   int wn = 2;
+  bool rem = false;
   std::vector<std::pair<int, Launch>> parts;  // (width, launch)
 };
 
@@ -138,6 +142,22 @@ Launch gemm_launch(std::vector<char>& buf, const std::vector<GroupGemm>& descs, 
 ProdSet prod_set(std::vector<char>& buf, const std::vector<GroupGemm>& descs, int wn) {
   ProdSet ps;
   ps.wn = wn;
+  if (wn == kRemSet) {
+    ps.rem = true;
+    for (int c : {2, 4, 6, 9, 13}) {
+      std::vector<int4> map;
+      for (size_t i = 0; i < descs.size(); ++i)
+        if (grouped_rem_class(descs[i].N) == c) gemm_rem_grouped_blocks(descs[i], (int)i, c, map);
+      if (map.empty()) continue;
+      Launch l;
+      l.desc = put(buf, descs);
+      l.map = put(buf, map);
+      l.count = (int64_t)descs.size();
+      l.nblocks = (int64_t)map.size();
+      ps.parts.push_back({c, l});
+    }
+    return ps;
+  }
   if (wn > 0) {
     ps.parts.push_back({wn, gemm_launch(buf, descs, false, wn)});
     return ps;
@@ -176,7 +196,10 @@ hipError_t run_gemm(const rqlp_batch* b, const Launch& l, Dtype in_t, Dtype out_
 
 hipError_t run_prod(const rqlp_batch* b, const ProdSet& ps, int trans, hipStream_t st) {
   for (const auto& pl : ps.parts) {
-    hipError_t e = run_gemm(b, pl.second, b->dt, b->dt, trans, false, pl.first, st);
+    hipError_t e =
+        ps.rem ? launch_gemm_rem_grouped(b->dt, trans, pl.first, at<GroupGemm>(b, pl.second.desc),
+                                         at<int4>(b, pl.second.map), pl.second.nblocks, st)
+               : run_gemm(b, pl.second, b->dt, b->dt, trans, false, pl.first, st);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -403,8 +426,8 @@ rqlp_status randqlp_batch_create(int count, const void* const* A, const int64_t*
   std::sort(ds.begin(), ds.end());
   const int64_t dmed = ds.empty() ? 1 : ds[ds.size() / 2];
   (void)dmed;
-  b->wn_tn = lookup_wn(b->dt, 1, b->dmax, 0);
-  b->wn_nn = lookup_wn(b->dt, 0, b->dmax, 0);
+  b->wn_tn = lookup_wn(b->dt, 1, b->dmax, kRemSet);
+  b->wn_nn = lookup_wn(b->dt, 0, b->dmax, kRemSet);
   std::vector<char>& buf = b->host_tab;
   {
     std::vector<int2> map;
@@ -414,11 +437,11 @@ rqlp_status randqlp_batch_create(int count, const void* const* A, const int64_t*
     b->gauss.count = (int64_t)gg.size();
     b->gauss.nblocks = (int64_t)map.size();
   }
-  for (int wn : {0, 1, 2, 4, 8}) {
+  for (int wn : {0, 1, 2, 4, 8, kRemSet}) {
     b->tn_alt[wn] = prod_set(buf, tn, wn);
     b->tnf_alt[wn] = prod_set(buf, tnf, wn);
   }
-  for (int wn : {0, 1, 2, 4}) b->nn_alt[wn] = prod_set(buf, nn, wn);
+  for (int wn : {0, 1, 2, 4, kRemSet}) b->nn_alt[wn] = prod_set(buf, nn, wn);
   if (!b->tn_alt.count(b->wn_tn)) b->wn_tn = 0;
   if (!b->nn_alt.count(b->wn_nn)) b->wn_nn = 0;
   b->tn = b->tn_alt[b->wn_tn];
@@ -590,8 +613,8 @@ rqlp_status randqlp_tune_load(const char* path) {
     if (line[0] == '#') continue;
     int dt = 0, tr = 0, bk = 0, wn = 0;
     if (std::sscanf(line, "%d %d %d %d", &dt, &tr, &bk, &wn) == 4 && (dt == 0 || dt == 1) &&
-        (tr == 0 || tr == 1) && wn >= 0 && wn <= 8) {
-      g_tune[{dt, tr, bk}] = wn == 0 ? 0 : grouped_wn_round(wn);
+        (tr == 0 || tr == 1) && wn >= 0 && (wn <= 8 || wn == kRemSet)) {
+      g_tune[{dt, tr, bk}] = (wn == 0 || wn == kRemSet) ? wn : grouped_wn_round(wn);
       ++nread;
     }
   }

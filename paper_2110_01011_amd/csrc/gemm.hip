@@ -226,6 +226,17 @@ __global__ __launch_bounds__(64 * kRemWavesM) void gemm_rem_kernel(
       A, lda, B, ldb, C, ldc, strideS, M, N, K, kchunk, 0, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
+// Grouped form of gemm_rem_kernel (whole contraction, no split).
+template <typename TI, typename TC, typename TO, bool TA, int WN>
+__global__ __launch_bounds__(64 * kRemWavesM) void gemm_rem_grouped_kernel(
+    const GroupGemm* __restrict__ descs, const int4* __restrict__ bmap) {
+  const int4 b = bmap[blockIdx.x];
+  const GroupGemm g = descs[b.x];
+  gemm_body<TI, TC, TO, TA, kRemWavesM, 1, 1, WN, (TA && WN <= 13) ? 16 : 8, kRemV>(
+      (const TI*)g.A, g.lda, (const TI*)g.B, g.ldb, (TO*)g.C, g.ldc, 0, g.M, g.N, g.K, g.K, 0,
+      b.y, b.z, 0);
+}
+
 // Grouped form: workgroup b computes tile (bmap[b].y, bmap[b].z) of product
 // descs[bmap[b].x] over its whole contraction (no split).
 template <typename TI, typename TC, typename TO, bool TA, int WAVES_M, int WAVES_N, int WM,
@@ -544,6 +555,52 @@ void grouped_wn(int wn, const GroupGemm* descs, const int4* bmap, int64_t nblock
 }  // namespace
 
 int grouped_wn_round(int wn) { return wn <= 1 ? 1 : wn <= 2 ? 2 : wn <= 4 ? 4 : 8; }
+
+// Remainder-layout classes of the grouped products: 16 wn + 4 columns.
+int grouped_rem_class(int64_t d) {
+  for (int c : {2, 4, 6, 9, 13})
+    if (d <= 16 * c + 4) return c;
+  return 13;
+}
+
+void gemm_rem_grouped_blocks(const GroupGemm& g, int idx, int wn, std::vector<int4>& out) {
+  const int64_t BN = 16 * wn + kRemV;
+  const int64_t tm = (g.M + kBM - 1) / kBM, tn = (g.N + BN - 1) / BN;
+  for (int64_t j = 0; j < tn; ++j)
+    for (int64_t i = 0; i < tm; ++i) out.push_back(int4{idx, (int)i, (int)j, 0});
+}
+
+namespace {
+template <typename T, bool TA, int WN>
+void run_rem_grouped(const GroupGemm* descs, const int4* bmap, int64_t nblocks, hipStream_t st) {
+  hipLaunchKernelGGL((gemm_rem_grouped_kernel<T, T, T, TA, WN>), dim3((unsigned)nblocks),
+                     dim3(64 * kRemWavesM), 0, st, descs, bmap);
+}
+template <typename T, bool TA>
+void rem_grouped_wn(int wn, const GroupGemm* descs, const int4* bmap, int64_t nblocks,
+                    hipStream_t st) {
+  switch (wn) {
+    case 2: run_rem_grouped<T, TA, 2>(descs, bmap, nblocks, st); break;
+    case 4: run_rem_grouped<T, TA, 4>(descs, bmap, nblocks, st); break;
+    case 6: run_rem_grouped<T, TA, 6>(descs, bmap, nblocks, st); break;
+    case 9: run_rem_grouped<T, TA, 9>(descs, bmap, nblocks, st); break;
+    default: run_rem_grouped<T, TA, 13>(descs, bmap, nblocks, st); break;
+  }
+}
+}  // namespace
+
+hipError_t launch_gemm_rem_grouped(Dtype dt, int trans_a, int wn, const GroupGemm* descs,
+                                   const int4* bmap, int64_t nblocks, hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  if (dt == DT_F64) {
+    if (trans_a) rem_grouped_wn<double, true>(wn, descs, bmap, nblocks, st);
+    else rem_grouped_wn<double, false>(wn, descs, bmap, nblocks, st);
+  } else {
+    if (trans_a) rem_grouped_wn<float, true>(wn, descs, bmap, nblocks, st);
+    else rem_grouped_wn<float, false>(wn, descs, bmap, nblocks, st);
+  }
+  return hipGetLastError();
+}
 
 void gemm_grouped_blocks(const GroupGemm& g, int idx, bool gram, int wn,
                          std::vector<int4>& out) {
