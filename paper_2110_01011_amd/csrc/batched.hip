@@ -127,10 +127,19 @@ const T* at(const rqlp_batch* b, size_t off) {
   return (const T*)(b->tab + off);
 }
 
+// Longest contraction first: the workgroups of the big matrices start in
+// the first rounds and the short ones fill the tail.
+void longest_first(const std::vector<GroupGemm>& descs, std::vector<int4>& map) {
+  std::stable_sort(map.begin(), map.end(), [&](const int4& x, const int4& y) {
+    return descs[x.x].K > descs[y.x].K;
+  });
+}
+
 Launch gemm_launch(std::vector<char>& buf, const std::vector<GroupGemm>& descs, bool gram,
                    int wn) {
   std::vector<int4> map;
   for (size_t i = 0; i < descs.size(); ++i) gemm_grouped_blocks(descs[i], (int)i, gram, wn, map);
+  longest_first(descs, map);
   Launch l;
   l.desc = put(buf, descs);
   l.map = put(buf, map);
@@ -149,6 +158,7 @@ ProdSet prod_set(std::vector<char>& buf, const std::vector<GroupGemm>& descs, in
       for (size_t i = 0; i < descs.size(); ++i)
         if (grouped_rem_class(descs[i].N) == c) gemm_rem_grouped_blocks(descs[i], (int)i, c, map);
       if (map.empty()) continue;
+      longest_first(descs, map);
       Launch l;
       l.desc = put(buf, descs);
       l.map = put(buf, map);
@@ -167,6 +177,7 @@ ProdSet prod_set(std::vector<char>& buf, const std::vector<GroupGemm>& descs, in
     for (size_t i = 0; i < descs.size(); ++i)
       if (class_wn(descs[i].N) == c) gemm_grouped_blocks(descs[i], (int)i, false, c, map);
     if (map.empty()) continue;
+    longest_first(descs, map);
     Launch l;
     l.desc = put(buf, descs);
     l.map = put(buf, map);
