@@ -120,3 +120,18 @@ def test_tune_table_roundtrip(rq, tmp_path):
                   list(range(6)))
     assert b2.info()["wn_tn"] == info["wn_tn"] and b2.info()["wn_nn"] == info["wn_nn"]
     b2.close()
+
+
+def test_batched_wide_and_full_width(rq):
+    """m < n matrices and full-width sketches (d = min(m, n)) in one batch."""
+    mats = [W.poly_decay(80, 200, 1.0, seed=31)[0], W.poly_decay(60, 60, 0.8, seed=32)[0],
+            W.fast_decay(150, 500, seed=33)[0], W.uniform01(40, 90, seed=34)]
+    ks, seeds = [10, 60, 150, 40], [11, 12, 13, 14]
+    Qs, Ls, Ps, info = rq.factor_batched([to_dev(A) for A in mats], ks, 5, 1, seeds)
+    log(f"  wide/full info {info}")
+    for A, k, sd, Qg, Lg, Pg in zip(mats, ks, seeds, Qs, Ls, Ps):
+        Qo, Lo, Po = randqlp(A, k, 5, 1, sd)
+        c = compare(A, to_np(Qg), to_np(Lg), to_np(Pg), Qo, Lo, Po, min(k, Lo.shape[0]))
+        assert c["de"] <= TOL and c["dsigma"] <= TOL, c
+        if Lo.shape[0] == min(A.shape):
+            assert rel_error(A, to_np(Qg), to_np(Lg), to_np(Pg)) < 1e-11

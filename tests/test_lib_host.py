@@ -98,3 +98,55 @@ def test_step_entry_points_validate(L):
 def test_status_strings(L):
     for code, name in rq.STATUS.items():
         assert L.randqlp_status_string(code).decode() == name
+
+
+def test_predictor_entry_points_validate(L):
+    dummy = ctypes.c_void_p(256)
+    nul = None
+    # randqlp_factor_auto: null parameters, bad k, bad q_fallback
+    assert L.randqlp_factor_auto(dummy, 10, 10, 3, 1, 2, 0, nul, dummy, dummy, dummy, None,
+                                 None) == 1
+    assert L.randqlp_factor_auto(dummy, 10, 10, 0, 1, 2, 0, dummy, dummy, dummy, dummy, None,
+                                 None) == 1
+    assert L.randqlp_factor_auto(dummy, 10, 10, 3, 1, -1, 0, dummy, dummy, dummy, dummy, None,
+                                 None) == 1
+    assert L.randqlp_features(dummy, 10, 10, 5, 3, 0, 0, dummy, None) == 1       # lda < m
+    assert L.randqlp_features(dummy, 10, 10, 10, 3, 0, 2, dummy, None) == 1      # precision
+    assert L.randqlp_mlp_forward(dummy, dummy, 0, dummy, None) == 1              # batch
+    assert L.randqlp_mlp_loss_grad(dummy, dummy, nul, 4, dummy, dummy, None) == 1
+    assert L.randqlp_mlp_adam(dummy, dummy, dummy, dummy, 0, ctypes.c_float(1e-3), None) == 1
+    assert L.randqlp_mlp_adam(dummy, dummy, dummy, dummy, 1, ctypes.c_float(0.0), None) == 1
+    step = ctypes.c_int64(0)
+    assert L.randqlp_mlp_train(dummy, dummy, dummy, dummy, dummy, 0, 1, 8,
+                               ctypes.c_float(1e-3), 0, ctypes.byref(step), dummy, None) == 1
+    assert L.randqlp_mlp_train(dummy, dummy, dummy, dummy, dummy, 10, 1, 0,
+                               ctypes.c_float(1e-3), 0, ctypes.byref(step), dummy, None) == 1
+
+
+def test_batched_entry_points_validate(L):
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    d = vp(256)
+    A = (vp * 2)(d, d)
+    m = (i64 * 2)(100, 80)
+    n = (i64 * 2)(90, 70)
+    k = (i32 * 2)(5, 4)
+    seeds = (ctypes.c_uint64 * 2)(1, 2)
+    h = vp()
+    # bad count, bad precision, bad p / q, k = 0 in one matrix, lda < m
+    assert L.randqlp_batch_create(0, A, m, n, None, k, 2, 1, seeds, A, None, A, None, A, None,
+                                  1, 0, ctypes.byref(h)) == 1
+    assert L.randqlp_batch_create(2, A, m, n, None, k, 2, 1, seeds, A, None, A, None, A, None,
+                                  2, 0, ctypes.byref(h)) == 1
+    assert L.randqlp_batch_create(2, A, m, n, None, k, -1, 1, seeds, A, None, A, None, A, None,
+                                  1, 0, ctypes.byref(h)) == 1
+    k0 = (i32 * 2)(5, 0)
+    assert L.randqlp_batch_create(2, A, m, n, None, k0, 2, 1, seeds, A, None, A, None, A, None,
+                                  1, 0, ctypes.byref(h)) == 1
+    assert "matrix 1" in L.randqlp_last_error().decode()
+    lda = (i64 * 2)(100, 10)
+    assert L.randqlp_batch_create(2, A, m, n, lda, k, 2, 1, seeds, A, None, A, None, A, None,
+                                  1, 0, ctypes.byref(h)) == 1
+    assert h.value is None
+    assert L.randqlp_batch_run(None, 1, None) == 1
+    assert L.randqlp_tune_save(None) == 1
+    assert L.randqlp_tune_load(b"/nonexistent/dir/tune.txt") == 1
