@@ -210,7 +210,8 @@ __global__ __launch_bounds__(256) void convert_panel16_kernel(const float* __res
 // (the contraction padding of gemm16_kernel).  64 x 64 tiles through LDS keep
 // the transposed writes coalesced; the grid covers exactly the padded sizes.
 // If rerr is given, each workgroup also writes the sum of squared rounding
-// errors (a - a16)^2 of its tile (fp64) to rerr[its linear index].
+// errors (a - a16)^2 of its tile (fp64) to rerr[its linear index] and the
+// tile's sum of squares a^2 to rerr[nblocks + its linear index].
 template <typename T16>
 __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict__ A, int64_t m,
                                                         int64_t n, int64_t lda,
@@ -221,7 +222,7 @@ __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict_
   __shared__ double red[256];
   const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  double err = 0.0;
+  double err = 0.0, nrm = 0.0;
   for (int jj = ty; jj < 64; jj += 4) {
     const int64_t i = i0 + tx, j = j0 + jj;
     T16 v = (T16)0.0f;
@@ -230,6 +231,7 @@ __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict_
       v = to16(a, (T16*)nullptr);
       const double e = (double)a - (double)(float)v;
       err += e * e;
+      nrm += (double)a * (double)a;
     }
     if (j < n) A16[i + j * ld16] = v;  // i < ld16 always
     tile[jj][tx] = v;
@@ -240,13 +242,18 @@ __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict_
     if (i < m) At16[j + i * ldt16] = tile[tx][ii];  // j < ldt16 always
   }
   if (rerr) {
-    red[threadIdx.x] = err;
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    const int64_t nb = (int64_t)gridDim.x * gridDim.y;
+    const int64_t bid = blockIdx.x + (int64_t)blockIdx.y * gridDim.x;
+    for (int pass = 0; pass < 2; ++pass) {
+      red[threadIdx.x] = pass == 0 ? err : nrm;
+      __syncthreads();
+      for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) rerr[bid + pass * nb] = red[0];
       __syncthreads();
     }
-    if (threadIdx.x == 0) rerr[blockIdx.x + (int64_t)blockIdx.y * gridDim.x] = red[0];
   }
 }
 

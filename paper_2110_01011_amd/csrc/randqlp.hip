@@ -166,7 +166,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
     L.jd = take((size_t)d * d * es);
     L.sums = take(sumsq_scratch_bytes());
     L.sres = take(4 * 8);
-    L.rerr = mixed ? take((size_t)convert16_blocks(m, n) * 8) : 0;
+    L.rerr = mixed ? take((size_t)convert16_blocks(m, n) * 2 * 8) : 0;
   } else {
     L.om64 = L.y64 = L.g64 = L.feat = L.mlp = L.cls = L.jd = L.sums = L.sres = L.rerr = 0;
   }
@@ -812,25 +812,32 @@ hipError_t predict_q(Ctx& c, const FactorArgs& f, int k, const float* params, in
 // product, which carries the rounding error dA = A16 - A of A; more rounds
 // cannot remove it, so `floor` = (d / n) ||dA||_F^2 -- the expected energy of
 // dA P for an orthonormal P -- is what Delta holds beyond the round's gain.
-hipError_t judge(Ctx& c, const FactorArgs& f, double sums[4]) {
+hipError_t judge(Ctx& c, const FactorArgs& f, double sums[4], int flags_out[4]) {
   const int64_t m = f.m, d = c.d;
   void* Zm = c.ws + c.lay.m1;
   void* Tm = c.ws + c.lay.m2;
   void* C1 = c.ws + c.lay.jd;
   double* scr = c.at<double>(c.lay.sums);
   double* res = c.at<double>(c.lay.sres);
-  HIP_TRY(launch_sumsq(f.A, f.lda, nullptr, 0, f.m, f.n, c.dt, scr, res, c.st));
+  const int64_t nb16 = convert16_blocks(f.m, f.n);
+  if (c.mixed && c.lay.rerr)  // ||A||^2 came with the 16-bit conversion
+    HIP_TRY(launch_sum_f64(c.at<double>(c.lay.rerr) + nb16, nb16, res, c.st));
+  else
+    HIP_TRY(launch_sumsq(f.A, f.lda, nullptr, 0, f.m, f.n, c.dt, scr, res, c.st));
   HIP_TRY(launch_sumsq(f.L, f.ldl, nullptr, 0, d, d, DT_F64, scr, res + 1, c.st));
   HIP_TRY(prod(c, f, 0, f.P, f.ldp, Zm, m));                                   // Z = A P
   HIP_TRY(gemm(c, 1, f.Q, f.ldq, Zm, m, C1, d, d, d, m, c.dt, c.dt, false));   // Q^T Z
   HIP_TRY(gemm(c, 0, f.Q, f.ldq, C1, d, Tm, m, m, d, d, c.dt, c.dt, false));   // Q Q^T Z
   HIP_TRY(launch_sumsq(Zm, m, Tm, m, m, d, c.dt, scr, res + 2, c.st));
   if (c.mixed && c.lay.rerr)
-    HIP_TRY(launch_sum_f64(c.at<double>(c.lay.rerr), convert16_blocks(f.m, f.n), res + 3, c.st));
+    HIP_TRY(launch_sum_f64(c.at<double>(c.lay.rerr), nb16, res + 3, c.st));
   else
     HIP_TRY(launch_zero_block(res + 3, 1, 1, 1, c.st));
+  // the four sums and the status words in one read-back
   HIP_TRY(hipMemcpyAsync(sums, res, 4 * sizeof(double), hipMemcpyDeviceToHost, c.st));
+  HIP_TRY(hipMemcpyAsync(flags_out, c.flags(), 4 * sizeof(int), hipMemcpyDeviceToHost, c.st));
   HIP_TRY(hipStreamSynchronize(c.st));
+  if (g_prof.on) prof_collect();
   sums[3] *= (double)d / (double)f.n;
   return hipSuccess;
 }
@@ -927,10 +934,9 @@ rqlp_status randqlp_factor_auto(const void* A, int64_t m, int64_t n, int k, int 
     e = stage_rounds(c, f, mode0, cls);
     if (e == hipSuccess) e = stage_finish(c, f, mode0);
     double sums[4] = {0, 0, 0, 0};
-    if (e == hipSuccess) e = judge(c, f, sums);
-    if (e != hipSuccess) return fail(RQLP_E_HIP, "launch failed: %s", hipGetErrorString(e));
     int fl[4] = {0, 0, 0, 0};
-    if ((s = read_flags(c, fl)) != RQLP_OK) return s;
+    if (e == hipSuccess) e = judge(c, f, sums, fl);
+    if (e != hipSuccess) return fail(RQLP_E_HIP, "launch failed: %s", hipGetErrorString(e));
     const bool clean = (fl[0] & (FLAG_NONPOS_PIVOT | FLAG_NONFINITE | FLAG_SECOND_PASS)) == 0;
     if (clean) {
       const double e2 = sums[0] - sums[1], delta = std::max(0.0, sums[2] - sums[3]);

@@ -97,7 +97,8 @@ hipError_t launch_convert_panel16(const float* X, int64_t rows, int64_t d, int64
 // A (m x n fp32) -> A16 (m x n, ld16) and At16 = A^T (n x m, ldt16), 16-bit,
 // with ld16 >= gemm16_ld(m), ldt16 >= gemm16_ld(n) and zero padding rows.
 // rerr (optional): per-workgroup sums of the squared rounding errors, one
-// double for each of convert16_blocks(m, n) workgroups.
+// double for each of the nb = convert16_blocks(m, n) workgroups, followed by
+// the nb per-workgroup sums of squares of A (2 nb doubles in all).
 hipError_t launch_convert16(const float* A, int64_t m, int64_t n, int64_t lda, void* A16,
                             int64_t ld16, void* At16, int64_t ldt16, bool f16, hipStream_t st,
                             double* rerr = nullptr);
