@@ -30,6 +30,9 @@ __device__ __forceinline__ double readlane_d(double v, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// two doubles at an 8-byte aligned address (one 16-byte vector store)
+typedef double double2_a8 __attribute__((ext_vector_type(2), aligned(8)));
+
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
   __builtin_amdgcn_wave_barrier();
@@ -46,91 +49,117 @@ __device__ __forceinline__ int tile_wave_id(int idx) { return idx < 3 ? idx + 1 
 __device__ __forceinline__ int tile_wave_idx(int wave) { return wave < 4 ? wave - 1 : wave - 2; }
 
 // Factor the 16 x 16 diagonal tile held in dg (row-major, full symmetric) in
-// place into its lower Cholesky factor L_JJ, and write the inverse of that
-// factor into dgi (and R_JJ^{-1} = L_JJ^{-T} into dinv).  Run by one wave:
-// lanes 0..15 own one row each; pivots travel by readlane, so the chain of
-// 16 pivots needs no LDS round trips.  1/l_ss comes from rsqrt (no divide on
-// the chain).  A dependent pivot (<= tol_dep of the column's original
-// diagonal, or non-finite) gives a zero column of L and a zero row of the
-// inverse.
-__device__ __forceinline__ void factor_diag_tile(double (*dg)[17], double (*dgi)[17], double* invd,
-                                 const double* odiag, int J, int d, double tol_dep,
-                                 double tol_warn, int* __restrict__ col_flags,
-                                 double* __restrict__ dinv, int* sflag) {
+// place into its lower Cholesky factor L_JJ and write X = L_JJ^{-1} into dgi.
+// Run by one wave.  Lanes 0..15 own one row of the tile each; lanes 16..31
+// own one column of X, which they build in the same pivot steps by forward
+// substitution (X row s = Y row s / l_ss, then Y row j -= l_js X row s), so
+// both use the same broadcast column of L.  Every lane evaluates the pivot
+// test and 1/sqrt on its own diagonal entry; the pivot step only moves 1/l_ss
+// (from lane s) and the new column of L (one readlane per row) across lanes,
+// and nothing on the pivot chain touches memory.  A dependent pivot (<=
+// tol_dep of the column's original diagonal, or non-finite) gives a zero
+// column of L and a zero row of X.  The pivot tests are evaluated after the
+// chain: flags go to *sflag, the per-column dependence marks to colf (LDS).
+__device__ __forceinline__ void factor_diag_tile(double (*dg)[17], double (*dgi)[17],
+                                                 const double* odiag, int J, int d,
+                                                 double tol_dep, double tol_warn, int* colf,
+                                                 int* sflag) {
   const int lane = threadIdx.x & 63;
   const int i = lane & 15;
-  int bits = 0;
-  {
-    double a[16];
+  const bool rowlane = lane < 16;
+  const double orig = odiag[16 * J + i];
+  const double thr = tol_dep * orig;
+  double mypiv = 0.0;
+  double a[16];
 #pragma unroll
-    for (int c = 0; c < 16; ++c) a[c] = dg[i][c];
+  for (int c = 0; c < 16; ++c) a[c] = rowlane ? dg[i][c] : ((c == i) ? 1.0 : 0.0);
+  double p = a[0];  // the next pivot, on lane s
 #pragma unroll
-    for (int s = 0; s < 16; ++s) {
-      const double piv = readlane_d(a[s], s);
-      const int gj = 16 * J + s;
-      const double orig = odiag[gj];
-      const bool nonfinite = !__builtin_isfinite(piv);
-      const bool dep = nonfinite || !(piv > tol_dep * orig);
-      if (gj < d) {
-        if (nonfinite) bits |= FLAG_NONFINITE;
-        if (dep) bits |= FLAG_NONPOS_PIVOT;
-        if (!dep && piv < tol_warn * orig) bits |= FLAG_SECOND_PASS;
-        if (col_flags != nullptr && lane == 0) col_flags[gj] = dep ? 1 : 0;
-      }
-      const double y = dep ? 0.0 : rsqrt(piv);  // 1 / l_ss
-      const double lss = piv * y;
-      if (lane == 0) invd[s] = y;
-      const double lis = (i > s) ? a[s] * y : ((i == s) ? lss : 0.0);
-      a[s] = lis;
+  for (int s = 0; s < 16; ++s) {
+    mypiv = (i == s) ? p : mypiv;
+    const double yl = (p > thr) ? rsqrt(p) : 0.0;  // NaN and dependent pivots: 0
+    const double y = readlane_d(yl, s);              // 1 / l_ss
+    // rows: l_is (l_ss itself on lane s, 0 above the diagonal); columns of
+    // X: the finished entry X[s][c]
+    const double w = a[s] * y;
+    const double v = (!rowlane || i >= s) ? w : 0.0;
+    a[s] = v;
+    if (s + 1 < 16) {
+      // lane s + 1 updates its own diagonal entry from its own l (the same
+      // value the broadcast gives it), which keeps the broadcast off the
+      // pivot chain
+      p = fma(-w, w, a[s + 1]);
 #pragma unroll
-      for (int j = s + 1; j < 16; ++j) {
-        const double ljs = readlane_d(lis, j);
-        a[j] = fma(-lis, ljs, a[j]);
-      }
-    }
-    if (lane < 16) {
-#pragma unroll
-      for (int c = 0; c < 16; ++c) dg[i][c] = (c > i) ? 0.0 : a[c];
-    }
-    wave_sync_lds();
-  }
-  // Inverse by forward substitution, one column per lane:
-  // X[r][c] = (delta_rc - sum_{t<r} L[r][t] X[t][c]) / L[r][r]  (0 if dependent).
-  const int c = lane & 15;
-  double x[16];
-#pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    double v0 = (r == c) ? 1.0 : 0.0, v1 = 0.0;
-#pragma unroll
-    for (int t = 0; t < r; t += 2) {
-      v0 = fma(-dg[r][t], x[t], v0);
-      if (t + 1 < r) v1 = fma(-dg[r][t + 1], x[t + 1], v1);
-    }
-    x[r] = (v0 + v1) * invd[r];
-  }
-  if (lane < 16) {
-#pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      dgi[r][c] = x[r];
-      dinv[(int64_t)J * 256 + c + r * 16] = x[r];  // (L^{-1})^T, column-major block
+      for (int j = s + 1; j < 16; ++j) a[j] = fma(-v, readlane_d(v, j), a[j]);
     }
   }
-  if (lane == 0 && bits) *sflag |= bits;
+  if (lane < 32) {
+    // rows of L to dg (zeros above the diagonal), columns of X to dgi: one
+    // store per entry for both halves
+    double* base = rowlane ? &dg[i][0] : &dgi[0][i];
+    const int step = rowlane ? 1 : 17;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) base[c * step] = (rowlane && c > i) ? 0.0 : a[c];
+  }
+  const int gj = 16 * J + i;
+  if (rowlane && gj < d) {
+    const bool nonfinite = !__builtin_isfinite(mypiv);
+    const bool dep = nonfinite || !(mypiv > thr);
+    int bits = 0;
+    if (nonfinite) bits |= FLAG_NONFINITE;
+    if (dep) bits |= FLAG_NONPOS_PIVOT;
+    if (!dep && mypiv < tol_warn * orig) bits |= FLAG_SECOND_PASS;
+    colf[gj] = dep ? 1 : 0;
+    if (bits) atomicOr(sflag, bits);
+  }
 }
 
-// Tile-wave part of the Cholesky kernel: holds its lower tiles of G in MFMA
-// layout, applies panel solves and trailing updates, hands each updated
-// diagonal tile to the factor wave, and finally writes its part of R.
+// Tile-wave part of the Cholesky kernel.  Each lower tile (I, J), I >= J, is
+// held transposed, T = G_IJ^T, in MFMA accumulator layout: register r of
+// lane l holds T[(l >> 4) + 4 r][l & 15] = G[16 I + (l & 15)][16 J + (l >> 4)
+// + 4 r], so the loads from the column-major G are contiguous along lanes,
+// and register r is also the B operand of k-step r of a product X T.  With
+// this layout the panel solve is L_IJ^T = L_JJ^{-1} T (four MFMAs from
+// registers), and the trailing update is T_IK -= L_KJ L_IJ^T.  Each updated
+// diagonal tile goes to the factor wave.  R = L^T is written as the tiles
+// become final (the zero tiles below its diagonal at the start), so no
+// store is left for the end of the kernel.
 __device__ __forceinline__ void chol_tile_wave(
     const double* __restrict__ G, int d, int64_t ldg, double sh, double (*dg)[17],
-    double (*dgi)[17], double (*pan)[17], int* ready, int wave, double* __restrict__ R,
+    double (*dgi_all)[16][17], double (*pan)[17], int* ready, int wave, double* __restrict__ R,
     int64_t ldr) {
   const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
   const int nt = (d + 15) / 16;
   const int T = nt * (nt + 1) / 2;
   const int twi = tile_wave_idx(wave);
   double4_t acc[kCholSlots];
   int tI[kCholSlots], tJ[kCholSlots];
+  // Byte offsets stay 32-bit (d <= 224 and the leading dimensions are small)
+  // so that the loads and stores use a scalar base and one vector offset.
+  const char* Gb = reinterpret_cast<const char*>(G);
+  const unsigned ldg8 = 8u * (unsigned)ldg;
+  char* Rb = reinterpret_cast<char*>(R);
+  const unsigned ldr8 = 8u * (unsigned)ldr;
+  const int q0 = 4 * lk;  // R stores: each lane writes rows q0 .. q0 + 3 of one column
+  // Four consecutive rows (row0 ..) of column col of R; rows past d dropped.
+  auto store4 = [&](int row0, int col, double v0, double v1, double v2, double v3) {
+    if (col >= d) return;
+    double* dst =
+        reinterpret_cast<double*>(Rb + (8u * (unsigned)row0 + __umul24((unsigned)col, ldr8)));
+    if (row0 + 3 < d) {
+      *reinterpret_cast<double2_a8*>(dst) = double2_a8{v0, v1};
+      *reinterpret_cast<double2_a8*>(dst + 2) = double2_a8{v2, v3};
+    } else {
+      if (row0 < d) dst[0] = v0;
+      if (row0 + 1 < d) dst[1] = v1;
+      if (row0 + 2 < d) dst[2] = v2;
+    }
+  };
+  // All loads first (addresses clamped into G), so that every slot's loads
+  // are in flight together.  Slot s holds tile t = twi + 6 s; its row index
+  // I only grows with s.
+  int I = 0;
 #pragma unroll
   for (int s = 0; s < kCholSlots; ++s) {
     const int t = twi + kTileWaves * s;
@@ -138,66 +167,76 @@ __device__ __forceinline__ void chol_tile_wave(
     tJ[s] = -1;
     acc[s] = double4_t{0, 0, 0, 0};
     if (t < T) {
-      int I = 0;
       while ((I + 1) * (I + 2) / 2 <= t) ++I;
       const int Jt = t - I * (I + 1) / 2;
       tI[s] = I;
       tJ[s] = Jt;
-      const int col = 16 * Jt + (lane & 15);
+      const unsigned grow8 = 8u * (unsigned)min(16 * I + li, d - 1);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int row = 16 * I + acc_row_f64(lane, r);
-        double v;
-        if (row < d && col < d) {
-          v = G[row + (int64_t)col * ldg];
-          if (row == col) v += sh;
-        } else {
-          v = (row == col) ? 1.0 : 0.0;
-        }
-        acc[s][r] = v;
+        const unsigned gcol = (unsigned)min(16 * Jt + acc_row_f64(lane, r), d - 1);
+        acc[s][r] = *reinterpret_cast<const double*>(Gb + (grow8 + __umul24(gcol, ldg8)));
       }
     }
   }
-  // Diagonal tile J lives at t = J (J + 3) / 2.
+  // Padding and the shift, slot by slot (slot 0 first: it may hold tile 0,
+  // which goes to the factor wave as soon as it is in).
   auto owner = [&](int J) { return tile_wave_id((J * (J + 3) / 2) % kTileWaves); };
   auto slot = [&](int J) { return (J * (J + 3) / 2) / kTileWaves; };
-  auto publish = [&](int J, double4_t c) {
+  auto publish = [&](int J, double4_t c) {  // dg = T^T (row-major)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) dg[acc_row_f64(lane, r)][lane & 15] = c[r];
+    for (int r = 0; r < 4; ++r) dg[li][acc_row_f64(lane, r)] = c[r];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
     if (lane == 0) __hip_atomic_store(ready, J, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
   };
-  __syncthreads();  // odiag and the flags are initialised
-  if (wave == owner(0)) {
 #pragma unroll
-    for (int s = 0; s < kCholSlots; ++s)
-      if (s == slot(0)) publish(0, acc[s]);
+  for (int s = 0; s < kCholSlots; ++s) {
+    if (tI[s] < 0) continue;
+    const int grow = 16 * tI[s] + li;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gcol = 16 * tJ[s] + acc_row_f64(lane, r);
+      if (grow >= d || gcol >= d)
+        acc[s][r] = (grow == gcol) ? 1.0 : 0.0;
+      else if (grow == gcol)
+        acc[s][r] += sh;
+    }
+    if (s == slot(0) && wave == owner(0)) publish(0, acc[s]);
   }
+  // Every load has landed; an explicit wait on all counters tells the
+  // compiler so, and keeps it from waiting on pending stores of R before
+  // later uses of these registers.
+  __builtin_amdgcn_s_waitcnt(0);
+  // R below the diagonal tiles is zero: tile (I, J), I > J, of R.
+#pragma unroll
+  for (int s = 0; s < kCholSlots; ++s)
+    if (tI[s] > tJ[s]) store4(16 * tI[s] + q0, 16 * tJ[s] + li, 0.0, 0.0, 0.0, 0.0);
   for (int J = 0; J < nt; ++J) {
     __syncthreads();  // L_JJ and its inverse are ready
-    // Panel: L_IJ = G_IJ L_JJ^{-T} for the tiles below the diagonal.
+    double (*dgi)[17] = dgi_all[J];
+    // Panel: L_IJ^T = L_JJ^{-1} G_IJ^T for the tiles below the diagonal; pan
+    // receives L_IJ (row-major rows 16 I ..), and the final tiles go to R.
 #pragma unroll
     for (int s = 0; s < kCholSlots; ++s) {
       if (tJ[s] != J) continue;
       const int I = tI[s];
       if (I == J) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[s][r] = dg[acc_row_f64(lane, r)][lane & 15];
+        for (int r = 0; r < 4; ++r) acc[s][r] = dg[li][acc_row_f64(lane, r)];  // L_JJ^T
+        // R tile (J, J) = L_JJ^T: R[16 J + q][16 J + li] = L_JJ[li][q]
+        store4(16 * J + q0, 16 * J + li, dg[li][q0], dg[li][q0 + 1], dg[li][q0 + 2],
+               dg[li][q0 + 3]);
       } else {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) pan[16 * I + acc_row_f64(lane, r)][lane & 15] = acc[s][r];
-        wave_sync_lds();
         double4_t res = {0, 0, 0, 0};
 #pragma unroll
-        for (int kq = 0; kq < 4; ++kq) {
-          const double a = pan[16 * I + (lane & 15)][kq * 4 + (lane >> 4)];
-          const double b = dgi[lane & 15][kq * 4 + (lane >> 4)];
-          res = mma64(a, b, res);
-        }
+        for (int kq = 0; kq < 4; ++kq) res = mma64(dgi[li][kq * 4 + lk], acc[s][kq], res);
         acc[s] = res;
-        wave_sync_lds();
 #pragma unroll
-        for (int r = 0; r < 4; ++r) pan[16 * I + acc_row_f64(lane, r)][lane & 15] = res[r];
+        for (int r = 0; r < 4; ++r) pan[16 * I + li][acc_row_f64(lane, r)] = res[r];
+        wave_sync_lds();
+        // R tile (J, I) = L_IJ^T: R[16 J + q][16 I + li] = L_IJ[li][q]
+        const double* pr = pan[16 * I + li];
+        store4(16 * J + q0, 16 * I + li, pr[q0], pr[q0 + 1], pr[q0 + 2], pr[q0 + 3]);
       }
     }
     __syncthreads();  // panel J is ready
@@ -212,7 +251,7 @@ __device__ __forceinline__ void chol_tile_wave(
         const int I = J + 1;
 #pragma unroll
         for (int kq = 0; kq < 4; ++kq) {
-          const double a = pan[16 * I + (lane & 15)][kq * 4 + (lane >> 4)];
+          const double a = pan[16 * I + li][kq * 4 + lk];
           c = mma64(-a, a, c);
         }
         acc[s] = c;
@@ -227,26 +266,11 @@ __device__ __forceinline__ void chol_tile_wave(
       double4_t c = acc[s];
 #pragma unroll
       for (int kq = 0; kq < 4; ++kq) {
-        const double a = pan[16 * I + (lane & 15)][kq * 4 + (lane >> 4)];
-        const double b = pan[16 * K + (lane & 15)][kq * 4 + (lane >> 4)];
+        const double a = pan[16 * K + li][kq * 4 + lk];
+        const double b = pan[16 * I + li][kq * 4 + lk];
         c = mma64(-a, b, c);
       }
       acc[s] = c;
-    }
-  }
-  // R = L^T (upper), with explicit zeros in the lower triangle.
-#pragma unroll
-  for (int s = 0; s < kCholSlots; ++s) {
-    if (tI[s] < 0) continue;
-    const int I = tI[s], Jt = tJ[s];
-    const int col = 16 * Jt + (lane & 15);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * I + acc_row_f64(lane, r);
-      if (row < d && col < d) {
-        R[col + (int64_t)row * ldr] = acc[s][r];
-        if (I > Jt) R[row + (int64_t)col * ldr] = 0.0;
-      }
     }
   }
 }
@@ -254,8 +278,9 @@ __device__ __forceinline__ void chol_tile_wave(
 // Cholesky of G + shift I (d <= 224) on one workgroup of 8 waves.  Wave 0
 // factors each 16 x 16 diagonal tile as soon as its owner publishes it
 // (an LDS flag; the owner never waits on wave 0, so the wait always ends);
-// wave 4 shares wave 0's SIMD and stays idle so no MFMA issue competes with
-// the pivot chain; the six other waves hold the tiles.
+// wave 4 shares wave 0's SIMD and issues no MFMA, so nothing competes with
+// the pivot chain; it writes each diagonal-block inverse out as soon as it
+// is ready.  The six other waves hold the tiles.
 __device__ __forceinline__ void cholesky_body(
     const double* __restrict__ G, int d, int64_t ldg, double shift,
     const double* __restrict__ shift_dev, double tol_dep, double tol_warn,
@@ -263,45 +288,59 @@ __device__ __forceinline__ void cholesky_body(
     int* __restrict__ col_flags, int* __restrict__ flags,
     const double* __restrict__ odiag_src, int64_t odiag_stride) {
   __shared__ double dg[16][17];
-  __shared__ double dgi[16][17];
-  __shared__ double invd[16];
+  __shared__ double dgi_all[CHOL_MAX_D / 16][16][17];  // inverse of L_JJ for every J
   __shared__ double pan[CHOL_MAX_D][17];
   __shared__ double odiag[CHOL_MAX_D];
+  __shared__ int colf[CHOL_MAX_D];
   __shared__ int sflag;
   __shared__ int ready;  // index of the last diagonal tile published in dg
 
   const int nt = (d + 15) / 16;
   const int tid = threadIdx.x;
+  const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const double sh = (shift_dev != nullptr) ? *shift_dev : shift;
-  // Pivots are judged against the original diagonal (of the whole matrix
-  // when this call factors a trailing Schur complement).
-  for (int j = tid; j < CHOL_MAX_D; j += blockDim.x)
-    odiag[j] = (j >= d) ? 1.0
-               : (odiag_src ? odiag_src[(int64_t)j * odiag_stride] + sh
-                            : G[j + (int64_t)j * ldg] + sh);
   if (tid == 0) {
     sflag = 0;
     ready = -1;
   }
+  __syncthreads();  // the flags are initialised
   if (wave == 0) {
-    __syncthreads();
+    // Pivots are judged against the original diagonal (of the whole matrix
+    // when this call factors a trailing Schur complement); the factor wave
+    // reads it while the tile waves load their tiles.
+    double ov[CHOL_MAX_D / 64 + 1];
+#pragma unroll
+    for (int u = 0; u * 64 < CHOL_MAX_D; ++u) {  // all loads in flight together
+      const int j = min(lane + 64 * u, d - 1);
+      ov[u] = odiag_src ? odiag_src[(int64_t)j * odiag_stride] : G[j + (int64_t)j * ldg];
+    }
+#pragma unroll
+    for (int u = 0; u * 64 < CHOL_MAX_D; ++u) {
+      const int j = lane + 64 * u;
+      if (j < CHOL_MAX_D) odiag[j] = (j >= d) ? 1.0 : ov[u] + sh;
+    }
     for (int J = 0; J < nt; ++J) {
       while (__hip_atomic_load(&ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < J)
         __builtin_amdgcn_s_sleep(1);
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      factor_diag_tile(dg, dgi, invd, odiag, J, d, tol_dep, tol_warn, col_flags, dinv, &sflag);
+      factor_diag_tile(dg, dgi_all[J], odiag, J, d, tol_dep, tol_warn, colf, &sflag);
       __syncthreads();  // L_JJ and its inverse are ready
       __syncthreads();  // panel J is ready
     }
   } else if (wave == 4) {
-    __syncthreads();
     for (int J = 0; J < nt; ++J) {
       __syncthreads();
+      // the inverse of block J ((L_JJ^{-1})^T, column-major) and its marks
+      const double (*x)[17] = dgi_all[J];
+#pragma unroll
+      for (int e = lane; e < 256; e += 64) dinv[J * 256 + e] = x[(e >> 4) & 15][e & 15];
+      if (col_flags != nullptr && lane < 16 && 16 * J + lane < d)
+        col_flags[16 * J + lane] = colf[16 * J + lane];
       __syncthreads();
     }
   } else {
-    chol_tile_wave(G, d, ldg, sh, dg, dgi, pan, &ready, wave, R, ldr);
+    chol_tile_wave(G, d, ldg, sh, dg, dgi_all, pan, &ready, wave, R, ldr);
   }
   __syncthreads();
   if (tid == 0 && sflag) atomicOr(flags, sflag);
@@ -325,65 +364,90 @@ __global__ __launch_bounds__(512) void cholesky_grouped_kernel(const GroupChol* 
 }
 
 // Qx = X R^+ by block forward substitution.  One wave (one workgroup) owns 16
-// rows: for each 16-column block J it forms V_J = X_J - sum_{K<J} Q_K R_KJ
-// with MFMA (A fragments from its finished columns kept in LDS, B fragments
-// of R read from L2), then Q_J = V_J R_JJ^{-1}.  The k-steps run in batches
-// of 16 whose next batch of fragments is loaded while the current batch's
-// MFMAs execute (two accumulator chains).  No workgroup barriers; X and Q
-// move through the wave's LDS panel so global accesses stay coalesced.  X
-// and Qx may be the same array (each wave reads a block of its rows before
-// overwriting it).
+// rows.  Their whole block of X goes to the wave's LDS panel first (all
+// loads in flight together); then for each 16-column block J the wave forms
+// V_J = X_J - sum_{K<J} Q_K R_KJ with MFMA (A fragments from its finished
+// columns in LDS, B fragments of R from L2) and Q_J = V_J R_JJ^{-1} in
+// place.  The B fragments come in batches of 16 k-steps, each loaded while
+// the previous batch's MFMAs run, the prefetch running on into the first
+// batch of the next block; the next diagonal-block inverse is loaded at the
+// start of each block.  Q leaves LDS at the end, so no global access waits
+// inside the block loop.  X and Qx may be the same array (a wave reads all
+// of its rows before it writes any).
 template <typename TX, typename TO>
 __device__ __forceinline__ void trsm_body(const TX* X, int64_t rows, int d, int64_t ldx,
                                           const double* __restrict__ R, int64_t ldr,
                                           const double* __restrict__ dinv, TO* Qx, int64_t ldq,
                                           const int64_t r0) {
   extern __shared__ double Qw[];
-  constexpr int B = 16;
+  constexpr int B = 16;   // k-steps per batch of B fragments
+  constexpr int XC = 16;  // X values per lane per load round
   const int nt = (d + 15) / 16, dp = nt * 16, lq = dp + 1;
   const int lane = threadIdx.x;
   const int li = lane & 15, lk = lane >> 4;
-  for (int J = 0; J < nt; ++J) {
-    const int kk = 16 * J;
-    const int colR = kk + li;
+  // X block -> LDS: lane (li, lk) takes row r0 + li of columns lk, lk + 4, ...
+  {
+    const bool rowok = r0 + li < rows;
+    const TX* xr = X + (rowok ? r0 + li : r0);
+    for (int c0 = 0; c0 < dp; c0 += 4 * XC) {
+      double xv[XC];
+#pragma unroll
+      for (int u = 0; u < XC; ++u) {
+        const int c = c0 + lk + 4 * u;
+        xv[u] = (rowok && c < d) ? (double)xr[(int64_t)c * ldx] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < XC; ++u) {
+        const int c = c0 + lk + 4 * u;
+        if (c < dp) Qw[li * lq + c] = xv[u];
+      }
+    }
+  }
+  // B fragment of k-step q of block Jb: R[4 q + lk][16 Jb + li]
+  auto load_batch = [&](int Jb, int base, double* dst) {
+    const int colR = 16 * Jb + li;
     const bool colok = colR < d;
     const double* Rc = R + (int64_t)(colok ? colR : 0) * ldr + lk;
-    const int nk = 4 * J;
-    double bc[B], bn[B];
+    const int nk = 4 * Jb;
 #pragma unroll
-    for (int q = 0; q < B; ++q) bc[q] = (q < nk && colok) ? Rc[q * 4] : 0.0;
+    for (int q = 0; q < B; ++q) dst[q] = (base + q < nk && colok) ? Rc[(base + q) * 4] : 0.0;
+  };
+  auto load_inv = [&](int Jb, double* dst) {
+    const double* T = dinv + (int64_t)Jb * 256;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = lane + 64 * e;
-      const int rr = idx & 15, cc = idx >> 4;
-      const int64_t row = r0 + rr;
-      const int col = kk + cc;
-      Qw[rr * lq + col] = (row < rows && col < d) ? (double)X[row + (int64_t)col * ldx] : 0.0;
-    }
-    wave_sync_lds();
-    double4_t acc0, acc1 = {0, 0, 0, 0};
+    for (int q4 = 0; q4 < 4; ++q4) dst[q4] = T[q4 * 4 + lk + li * 16];
+  };
+  double bc[B], bn[B], tb[4], tn[4];
+  load_inv(0, tb);
+  if (nt > 1) load_batch(1, 0, bc);
+  wave_sync_lds();
+  for (int J = 0; J < nt; ++J) {
+    const int kk = 16 * J, nk = 4 * J;
+    if (J + 1 < nt) load_inv(J + 1, tn);
+    double4_t acc0, acc1 = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0}, acc3 = {0, 0, 0, 0};
 #pragma unroll
     for (int r = 0; r < 4; ++r) acc0[r] = Qw[acc_row_f64(lane, r) * lq + kk + li];
     for (int base = 0; base < nk; base += B) {
-      const int nb = base + B;
-#pragma unroll
-      for (int q = 0; q < B; ++q) bn[q] = (nb + q < nk && colok) ? Rc[(nb + q) * 4] : 0.0;
+      if (base + B < nk)
+        load_batch(J, base + B, bn);
+      else if (J + 1 < nt)
+        load_batch(J + 1, 0, bn);
       double ac[B];
 #pragma unroll
       for (int q = 0; q < B; ++q) ac[q] = (base + q < nk) ? Qw[li * lq + (base + q) * 4 + lk] : 0.0;
 #pragma unroll
-      for (int q = 0; q < B; q += 2) {
+      for (int q = 0; q < B; q += 4) {
         acc0 = mma64(-ac[q], bc[q], acc0);
         acc1 = mma64(-ac[q + 1], bc[q + 1], acc1);
+        acc2 = mma64(-ac[q + 2], bc[q + 2], acc2);
+        acc3 = mma64(-ac[q + 3], bc[q + 3], acc3);
       }
 #pragma unroll
       for (int q = 0; q < B; ++q) bc[q] = bn[q];
     }
     acc0 += acc1;
-    double tb[4];
-    const double* T = dinv + (int64_t)J * 256;
-#pragma unroll
-    for (int q4 = 0; q4 < 4; ++q4) tb[q4] = T[q4 * 4 + lk + li * 16];
+    acc2 += acc3;
+    acc0 += acc2;
 #pragma unroll
     for (int r = 0; r < 4; ++r) Qw[acc_row_f64(lane, r) * lq + kk + li] = acc0[r];
     wave_sync_lds();
@@ -395,13 +459,12 @@ __device__ __forceinline__ void trsm_body(const TX* X, int64_t rows, int d, int6
     for (int r = 0; r < 4; ++r) Qw[acc_row_f64(lane, r) * lq + kk + li] = res[r];
     wave_sync_lds();
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int idx = lane + 64 * e;
-      const int rr = idx & 15, cc = idx >> 4;
-      const int64_t row = r0 + rr;
-      const int col = kk + cc;
-      if (row < rows && col < d) Qx[row + (int64_t)col * ldq] = (TO)Qw[rr * lq + col];
-    }
+    for (int q4 = 0; q4 < 4; ++q4) tb[q4] = tn[q4];
+  }
+  // Q block -> Qx
+  if (r0 + li < rows) {
+    TO* qr = Qx + r0 + li;
+    for (int c = lk; c < d; c += 4) qr[(int64_t)c * ldq] = (TO)Qw[li * lq + c];
   }
 }
 
@@ -594,7 +657,8 @@ hipError_t launch_cholesky_tile(const double* G, int64_t d, int64_t ldg, double 
                                 double* R, int64_t ldr, double* dinv, int* col_flags,
                                 int* flags, const double* odiag_src, int64_t odiag_stride,
                                 hipStream_t st) {
-  if (d > CHOL_MAX_D) return hipErrorInvalidValue;
+  // the kernel addresses G and R with 32-bit byte offsets
+  if (d > CHOL_MAX_D || ldg > (1 << 20) || ldr > (1 << 20)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(cholesky_kernel, dim3(1), dim3(512), 0, st, G, (int)d, ldg, shift,
                      shift_dev, tol_dep, tol_warn, R, ldr, dinv, col_flags, flags, odiag_src,
                      odiag_stride);
