@@ -468,6 +468,143 @@ __device__ __forceinline__ void trsm_body(const TX* X, int64_t rows, int d, int6
   }
 }
 
+// Qx = X R^+ for d <= CHOL_MAX_D, right-looking, two waves per 16-row block.
+// Column block K belongs to wave K & 1, which keeps V_K (X_K less the
+// contributions of the finished blocks) in MFMA accumulators.  Step J: once
+// Q_J is in LDS, each wave subtracts Q_J R_JK from its blocks K > J; the
+// owner of block J + 1 does that block first and turns it into Q_{J+1} =
+// V_{J+1} R_{J+1,J+1}^{-1} at once, so the chain between steps is one
+// barrier and eight MFMAs while the rest of the update runs beside it.  The
+// R fragments of the next step are loaded during the current one.  X (the
+// whole row block) passes through LDS on the way in and Q on the way out.
+constexpr int kTrsmOwn = CHOL_MAX_D / 32;  // column blocks per wave
+
+template <typename TX, typename TO>
+__global__ __launch_bounds__(128) void trsm_rl_kernel(const TX* X, int64_t rows, int d,
+                                                      int64_t ldx, const double* __restrict__ R,
+                                                      int64_t ldr, const double* __restrict__ dinv,
+                                                      TO* Qx, int64_t ldq) {
+  extern __shared__ double Qw[];
+  const int nt = (d + 15) / 16, dp = nt * 16, lq = dp + 1;
+  const int tid = threadIdx.x;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int lane = tid & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t r0 = (int64_t)blockIdx.x * 16;
+  // X block -> LDS: thread t takes row r0 + (t & 15) of columns t >> 4, + 8, ...
+  {
+    const int xr_i = tid & 15, xc0 = tid >> 4;
+    const bool rowok = r0 + xr_i < rows;
+    const TX* xr = X + (rowok ? r0 + xr_i : r0);
+    for (int c0 = 0; c0 < dp; c0 += 8 * 16) {
+      double xv[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int c = c0 + xc0 + 8 * u;
+        xv[u] = (rowok && c < d) ? (double)xr[(int64_t)c * ldx] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int c = c0 + xc0 + 8 * u;
+        if (c < dp) Qw[xr_i * lq + c] = xv[u];
+      }
+    }
+  }
+  // B fragment (k-step q) of R_JK: R[16 J + 4 q + lk][16 K + li]; only the
+  // blocks K > J are used (their rows 16 J .. 16 J + 15 are all below d)
+  auto load_rf = [&](int J, int K, double* dst) {
+    const int col = 16 * K + li;
+    const bool ok = K > J && K < nt && col < d;
+    const double* Rc = R + (int64_t)(ok ? col : 0) * ldr + 16 * J + lk;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = ok ? Rc[4 * q] : 0.0;
+  };
+  auto load_inv = [&](int K, double* dst) {
+    const double* T = dinv + (int64_t)(K < nt ? K : 0) * 256;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) dst[q] = T[q * 4 + lk + li * 16];
+  };
+  // Q_K = V_K R_KK^{-1}, through this wave's columns of the LDS panel.
+  auto solve = [&](int K, double4_t v, const double* tb) {
+    const int kk = 16 * K;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Qw[acc_row_f64(lane, r) * lq + kk + li] = v[r];
+    wave_sync_lds();
+    double4_t r0v = {0, 0, 0, 0}, r1v = {0, 0, 0, 0};  // two short chains
+    r0v = mma64(Qw[li * lq + kk + lk], tb[0], r0v);
+    r1v = mma64(Qw[li * lq + kk + 4 + lk], tb[1], r1v);
+    r0v = mma64(Qw[li * lq + kk + 8 + lk], tb[2], r0v);
+    r1v = mma64(Qw[li * lq + kk + 12 + lk], tb[3], r1v);
+    const double4_t res = r0v + r1v;
+    wave_sync_lds();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Qw[acc_row_f64(lane, r) * lq + kk + li] = res[r];
+  };
+  double rf[kTrsmOwn][4], rn[kTrsmOwn][4], tb[4];
+#pragma unroll
+  for (int j = 0; j < kTrsmOwn; ++j) load_rf(0, w + 2 * j, rf[j]);  // step 0
+  load_inv(w, tb);  // the first block this wave solves: w (step -1 or 0)
+  __syncthreads();  // X is in LDS
+  double4_t V[kTrsmOwn];
+#pragma unroll
+  for (int j = 0; j < kTrsmOwn; ++j) {
+    const int K = w + 2 * j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      V[j][r] = (K < nt) ? Qw[acc_row_f64(lane, r) * lq + 16 * K + li] : 0.0;
+  }
+  if (w == 0) solve(0, V[0], tb);  // Q_0
+  if (w == 0) load_inv(2, tb);     // wave 0 solves 0, 2, 4, ...; wave 1 solves 1, 3, ...
+  for (int J = 0; J + 1 < nt; ++J) {
+    __syncthreads();  // Q_J is in LDS
+#pragma unroll
+    for (int j = 0; j < kTrsmOwn; ++j) load_rf(J + 1, w + 2 * j, rn[j]);
+    double aq[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) aq[q] = Qw[li * lq + 16 * J + 4 * q + lk];
+    // the owner of block J + 1: that block first (two short MFMA chains),
+    // then its solve
+    const int jn = (J + 1 - w) >> 1;  // V index of block J + 1 if this wave owns it
+    if (((J + 1) & 1) == w) {
+#pragma unroll
+      for (int j = 0; j < kTrsmOwn; ++j) {
+        if (j != jn) continue;
+        double4_t c0 = V[j], c1 = {0, 0, 0, 0};
+        c0 = mma64(-aq[0], rf[j][0], c0);
+        c1 = mma64(-aq[1], rf[j][1], c1);
+        c0 = mma64(-aq[2], rf[j][2], c0);
+        c1 = mma64(-aq[3], rf[j][3], c1);
+        V[j] = c0 + c1;
+        solve(J + 1, V[j], tb);
+      }
+      load_inv(J + 3, tb);
+    }
+    // the remaining blocks K > J + 1, k-step outermost so that consecutive
+    // MFMAs are independent
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int j = 0; j < kTrsmOwn; ++j) {
+        const int K = w + 2 * j;
+        if (K <= J + 1 || K >= nt) continue;
+        V[j] = mma64(-aq[q], rf[j][q], V[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kTrsmOwn; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) rf[j][q] = rn[j][q];
+  }
+  __syncthreads();  // every Q_K is in LDS
+  {
+    const int xr_i = tid & 15, xc0 = tid >> 4;
+    if (r0 + xr_i < rows) {
+      TO* qr = Qx + r0 + xr_i;
+      for (int c = xc0; c < d; c += 8) qr[(int64_t)c * ldq] = (TO)Qw[xr_i * lq + c];
+    }
+  }
+}
+
 template <typename TX, typename TO>
 __global__ __launch_bounds__(64) void trsm_kernel(const TX* X, int64_t rows, int d, int64_t ldx,
                                                   const double* __restrict__ R, int64_t ldr,
@@ -694,6 +831,11 @@ static hipError_t trsm_typed(const void* X, int64_t rows, int64_t d, int64_t ldx
   const int nt = (int)((d + 15) / 16), dp = nt * 16;
   const size_t lds = sizeof(double) * (size_t)16 * (dp + 1);
   const int64_t blocks = (rows + 15) / 16;
+  if (d <= CHOL_MAX_D) {
+    hipLaunchKernelGGL((trsm_rl_kernel<TX, TO>), dim3((unsigned)blocks), dim3(128), lds, st,
+                       (const TX*)X, rows, (int)d, ldx, R, ldr, dinv, (TO*)Qx, ldq);
+    return hipGetLastError();
+  }
   hipLaunchKernelGGL((trsm_kernel<TX, TO>), dim3((unsigned)blocks), dim3(64), lds, st,
                      (const TX*)X, rows, (int)d, ldx, R, ldr, dinv, (TO*)Qx, ldq);
   return hipGetLastError();
