@@ -26,25 +26,70 @@ namespace {
 constexpr int kNs = 64;            // sketch columns read by the predictor
 constexpr int kJacobiThreads = 256;
 
+// LDS writes of this wave are visible to its own later reads
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// a double from another lane through DPP (two 32-bit moves); lanes whose
+// source is out of range or masked off get 0
+template <int CTRL, int ROW_MASK, int BANK_MASK>
+__device__ __forceinline__ double dpp_d(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)u, CTRL, ROW_MASK, BANK_MASK, true);
+  const int hi =
+      __builtin_amdgcn_update_dpp(0, (int)(unsigned)(u >> 32), CTRL, ROW_MASK, BANK_MASK, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)u, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the 64 lanes of a wave, on every lane: a prefix sum within each
+// row of 16 lanes (row_shr 1, 2, 4, 8), then the row totals carried across
+// rows (row_bcast 15 and 31) into lane 63, which is read back.
+__device__ __forceinline__ double wave_sum_d(double v) {
+  v += dpp_d<0x111, 0xf, 0xf>(v);  // row_shr:1
+  v += dpp_d<0x112, 0xf, 0xf>(v);  // row_shr:2
+  v += dpp_d<0x114, 0xf, 0xf>(v);  // row_shr:4
+  v += dpp_d<0x118, 0xf, 0xf>(v);  // row_shr:8
+  v += dpp_d<0x142, 0xa, 0xf>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_d<0x143, 0xc, 0xf>(v);  // row_bcast:31 into rows 2 and 3
+  return readlane_d(v, 63);
+}
+
 // ---------------------------------------------------------------- features
 // Eigenvalues of the symmetric 64 x 64 G (column-major, ldg) in one
 // workgroup: Householder reduction to tridiagonal form (62 reflections,
 // each a reduction for the vector, a symmetric matrix-vector product and a
-// rank-2 update on the trailing block in LDS), then bisection with Sturm
-// counts, one thread per eigenvalue (thread i finds the i-th smallest, so
-// the order comes for free).  Both steps are backward stable: the
+// rank-2 update on the trailing block in LDS, all on one wave), then
+// bisection with Sturm
+// counts, four threads per eigenvalue (the quad for eigenvalue i finds the
+// i-th smallest, so the order comes for free; each round cuts its interval
+// to a fifth).  Both steps are backward stable: the
 // eigenvalues carry an absolute error of a few units of roundoff times
 // ||G||, which resolves sigma_i / sigma_1 = sqrt(lambda_i / lambda_1) well
 // below the features' clamp at 1e-6.  Then the features as described above.
 __device__ __forceinline__ int sturm_count(const double* dg, const double* eo2, int n,
                                            double x, double pivmin) {
-  // number of eigenvalues of the tridiagonal (dg, off-diagonal^2 eo2) below x
+  // number of eigenvalues of the tridiagonal (dg, off-diagonal^2 eo2) below x:
+  // the negative pivots of T - x I = L D L^T.  1 / q is the hardware
+  // reciprocal refined by one Newton step (a relative error of a few units
+  // of roundoff, which the count tolerates as it does the rounding of the
+  // other operations).
   int cnt = 0;
   double q = dg[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   if (q < 0.0) ++cnt;
   for (int j = 1; j < n; ++j) {
-    q = (dg[j] - x) - eo2[j - 1] / q;
+    const double r0 = __builtin_amdgcn_rcp(q);
+    const double r = fma(r0, fma(-q, r0, 1.0), r0);
+    q = (dg[j] - x) - eo2[j - 1] * r;
     if (fabs(q) < pivmin) q = -pivmin;
     if (q < 0.0) ++cnt;
   }
@@ -58,90 +103,118 @@ __global__ __launch_bounds__(kJacobiThreads) void features_kernel(const double* 
   __shared__ double v[kNs], pw[kNs];
   __shared__ double dg[kNs], eo2[kNs];
   __shared__ double lam[kNs];
-  __shared__ double scal[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int e = tid; e < kNs * kNs; e += kJacobiThreads) {
     const int i = e % kNs, j = e / kNs;
     a[i][j] = G[i + (int64_t)j * ldg];
   }
   __syncthreads();
-  for (int kk = 0; kk < kNs - 2; ++kk) {
-    const int r0 = kk + 1, len = kNs - r0;  // reflect rows r0..63 of column kk
-    if (wave == 0) {
-      const double x = lane < len ? a[r0 + lane][kk] : 0.0;
-      double ss = x * x;
-      for (int w = 32; w > 0; w >>= 1) ss += __shfl_xor(ss, w);
-      const double x0 = __shfl(x, 0);
+  // Householder reduction to tridiagonal form by wave 0 alone (no workgroup
+  // barriers).  Lane i keeps row i of A in registers; step kk reflects rows
+  // r0 = kk + 1 .. 63 of column kk: v = x - alpha e_r0 with
+  // alpha = -sign(x_r0) ||x||, beta = 2 / v^T v, p = beta A v,
+  // w = p - (beta / 2) (p^T v) v, A -= v w^T + w v^T.  v and w vanish
+  // outside rows r0 .., so the full-width update leaves the finished part
+  // alone.  Column kk comes from row kk (symmetry) through LDS.  The diagonal
+  // entry a[kk][kk] is final after step kk; the new off-diagonal entry is
+  // alpha.
+  if (wave == 0) {
+    double ar[kNs];
+#pragma unroll
+    for (int j = 0; j < kNs; ++j) ar[j] = a[lane][j];
+    for (int kk = 0; kk < kNs - 2; ++kk) {
+      const int r0 = kk + 1;
+      if (lane == kk) {
+#pragma unroll
+        for (int j = 0; j < kNs; ++j) pw[j] = ar[j];
+      }
+      wave_sync_lds();
+      const bool mine = lane >= r0;
+      const double x = mine ? pw[lane] : 0.0;
+      const double ss = wave_sum_d(x * x);
+      const double x0 = readlane_d(x, r0);
       const double nrm = sqrt(ss);
       const double alpha = x0 >= 0.0 ? -nrm : nrm;
-      const double vv = lane == 0 ? x0 - alpha : x;
-      double v2 = vv * vv;
-      for (int w = 32; w > 0; w >>= 1) v2 += __shfl_xor(v2, w);
-      if (lane < len) v[lane] = vv;
+      const double vv = lane == r0 ? x0 - alpha : x;
+      const double v2 = wave_sum_d(vv * vv);
+      const double beta = v2 > 0.0 ? 2.0 / v2 : 0.0;
       if (lane == 0) {
-        scal[0] = v2 > 0.0 ? 2.0 / v2 : 0.0;   // beta
-        scal[1] = v2 > 0.0 ? alpha : x0;         // the new off-diagonal entry
+        dg[kk] = pw[kk];
+        const double o = v2 > 0.0 ? alpha : x0;
+        eo2[kk] = o * o;
       }
-    }
-    __syncthreads();
-    const double beta = scal[0];
-    // p = beta A22 v: four threads per row, 16 columns each, summed across lanes
-    if (tid < 4 * kNs) {
-      const int row = tid >> 2, part = tid & 3;
-      double sacc = 0.0;
-      if (row < len) {
-        for (int j = part; j < len; j += 4) sacc += a[r0 + row][r0 + j] * v[j];
+      wave_sync_lds();
+      v[lane] = vv;
+      wave_sync_lds();
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+      for (int j = 0; j < kNs; j += 4) {
+        s0 = fma(ar[j], v[j], s0);
+        s1 = fma(ar[j + 1], v[j + 1], s1);
+        s2 = fma(ar[j + 2], v[j + 2], s2);
+        s3 = fma(ar[j + 3], v[j + 3], s3);
       }
-      sacc += __shfl_xor(sacc, 1);
-      sacc += __shfl_xor(sacc, 2);
-      if (part == 0 && row < len) pw[row] = beta * sacc;
+      const double pp = mine ? beta * ((s0 + s1) + (s2 + s3)) : 0.0;
+      const double pv = wave_sum_d(pp * vv);
+      const double wv = pp - 0.5 * beta * pv * vv;
+      pw[lane] = wv;
+      wave_sync_lds();
+#pragma unroll
+      for (int j = 0; j < kNs; ++j) ar[j] -= vv * pw[j] + wv * v[j];
+      wave_sync_lds();
     }
-    __syncthreads();
-    // w = p - (beta / 2) (p^T v) v
-    if (wave == 0) {
-      double pv = lane < len ? pw[lane] * v[lane] : 0.0;
-      for (int w = 32; w > 0; w >>= 1) pv += __shfl_xor(pv, w);
-      const double K = 0.5 * beta * pv;
-      if (lane < len) pw[lane] -= K * v[lane];
+    if (lane == kNs - 2) dg[kNs - 2] = ar[kNs - 2];
+    if (lane == kNs - 1) {
+      dg[kNs - 1] = ar[kNs - 1];
+      eo2[kNs - 2] = ar[kNs - 2] * ar[kNs - 2];
+      eo2[kNs - 1] = 0.0;
     }
-    __syncthreads();
-    // A22 -= v w^T + w v^T; column kk becomes (alpha, 0, ..., 0) below the diagonal
-    for (int e = tid; e < len * len; e += kJacobiThreads) {
-      const int i = e % len, j = e / len;
-      a[r0 + i][r0 + j] -= v[i] * pw[j] + pw[i] * v[j];
-    }
-    if (tid < len) {
-      const double val = tid == 0 ? scal[1] : 0.0;
-      a[r0 + tid][kk] = val;
-      a[kk][r0 + tid] = val;
-    }
-    __syncthreads();
-  }
-  if (tid < kNs) {
-    dg[tid] = a[tid][tid];
-    const double o = tid + 1 < kNs ? a[tid + 1][tid] : 0.0;
-    eo2[tid] = o * o;
   }
   __syncthreads();
-  if (tid < kNs) {
+  {
     // Gershgorin interval and a pivot floor relative to ||T||
-    double lo = 1e300, hi = -1e300, tn = 0.0;
+    double lo = 1e300, hi = -1e300, tn = 0.0, dmax = 0.0;
     for (int j = 0; j < kNs; ++j) {
       const double r = (j > 0 ? sqrt(eo2[j - 1]) : 0.0) + (j + 1 < kNs ? sqrt(eo2[j]) : 0.0);
       lo = fmin(lo, dg[j] - r);
       hi = fmax(hi, dg[j] + r);
       tn = fmax(tn, fabs(dg[j]) + r);
+      dmax = fmax(dmax, dg[j]);
     }
     const double pivmin = fmax(tn, 1e-300) * 1e-300 + 1e-300;
     const double tol = 4.0 * 2.220446049250313e-16 * fmax(tn, 1e-300);
-    // the (tid)-th smallest eigenvalue: count(x) <= tid < count(hi)
+    // Below 1e-13 lambda_max (lambda_max >= every diagonal entry) sigma_i /
+    // sigma_1 < 1e-6 and the feature is clamped; above it a relative width
+    // of 2^-24 is finer than the float features resolve.
+    const double floor_clamp = 1e-13 * dmax;
+    // Four threads per eigenvalue (a quad of lanes): each iteration they
+    // count at the four interior points of five equal parts of [l, h], and
+    // all four keep the part that holds eigenvalue e (the e-th smallest:
+    // count(l) <= e < count(h)).
+    const int e = tid >> 2, sub = tid & 3;
     double l = lo, h = hi;
-    for (int it = 0; it < 200 && h - l > tol; ++it) {
-      const double mid = 0.5 * (l + h);
-      if (sturm_count(dg, eo2, kNs, mid, pivmin) <= tid) l = mid;
-      else h = mid;
+    for (int it = 0; it < 64; ++it) {
+      const double wdt = h - l;
+      const bool done = wdt <= fmax(tol, 0x1p-24 * fmax(fabs(l), fabs(h))) || h <= floor_clamp;
+      if (__all(done)) break;
+      const double x = l + wdt * (double)(sub + 1) * 0.2;
+      const int c = sturm_count(dg, eo2, kNs, x, pivmin);
+      const int c0 = __shfl(c, (lane & ~3) + 0), c1 = __shfl(c, (lane & ~3) + 1);
+      const int c2 = __shfl(c, (lane & ~3) + 2), c3 = __shfl(c, (lane & ~3) + 3);
+      const double x0 = __shfl(x, (lane & ~3) + 0), x1 = __shfl(x, (lane & ~3) + 1);
+      const double x2 = __shfl(x, (lane & ~3) + 2), x3 = __shfl(x, (lane & ~3) + 3);
+      if (!done) {
+        double nl = l, nh = h;
+        if (c0 > e) nh = x0;
+        else if (c1 > e) { nl = x0; nh = x1; }
+        else if (c2 > e) { nl = x1; nh = x2; }
+        else if (c3 > e) { nl = x2; nh = x3; }
+        else nl = x3;
+        l = nl;
+        h = nh;
+      }
     }
-    lam[tid] = sqrt(fmax(0.5 * (l + h), 0.0));
+    if (sub == 0) lam[e] = sqrt(fmax(0.5 * (l + h), 0.0));
   }
   __syncthreads();
   if (tid < kNs) {

@@ -27,7 +27,8 @@ def _t(x, dtype=None):
 
 @pytest.mark.parametrize("case", ["poly", "exp_fast", "rank5", "small_n", "zero"])
 def test_features_match_oracle(rq, case):
-    """Singular values of A^T Omega[:, :64] via the fp64 Gram and Jacobi vs LAPACK's SVD."""
+    """Singular values of A^T Omega[:, :64] via the fp64 Gram (tridiagonal reduction and
+    bisection) vs LAPACK's SVD."""
     log(f"features {case}")
     if case == "poly":
         A, U, s, V = W.poly_decay(700, 500, 0.8, seed=1)
