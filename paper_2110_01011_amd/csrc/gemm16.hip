@@ -16,9 +16,8 @@ namespace {
 // tile is whole and the main loop carries no bounds checks; rows >= M and
 // columns >= N read a clamped (valid) row or column and are never stored.
 //
-// Workgroup tile (16 WM WAVES) x (16 WN): the waves are stacked along M, each
-// owning 16 WM rows (WM 16-row blocks: 2, or 4 for tall products, which
-// halves the panel reads from LDS per MFMA) and all 16 WN columns.  A rows belong to
+// Workgroup tile (32 WAVES) x (16 WN): the waves are stacked along M, each
+// owning 32 rows (two 16-row blocks) and all 16 WN columns.  A rows belong to
 // a single wave, so A fragments go from HBM straight into registers (one
 // 32-byte load per lane and block covers two MFMA k-steps, prefetched one
 // tile ahead); the panel tile, shared by the waves, is staged through LDS
@@ -61,7 +60,8 @@ __device__ __forceinline__ __bf16 to16(float x, __bf16*) {
 __device__ __forceinline__ _Float16 to16(float x, _Float16*) { return (_Float16)x; }
 
 constexpr int k16BK = 64;     // contraction depth of one tile (and the zero padding unit)
-constexpr int k16Waves = 4;   // waves per workgroup (16 WM rows each)
+constexpr int k16Waves = 4;   // waves per workgroup (32 rows each)
+constexpr int k16BM = 32 * k16Waves;
 constexpr int k16MaxWN = 17;  // up to 272 columns per workgroup
 constexpr int kXcds = 8;
 
@@ -73,14 +73,13 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t L, int64_t T) {
   return (x < rem) ? x * (per + 1) + j : rem * (per + 1) + (x - rem) * per + j;
 }
 
-template <typename T16, int WN, int WM>
-__global__ __launch_bounds__(64 * k16Waves, WM == 2 ? 2 : 1) void gemm16_kernel(
+template <typename T16, int WN>
+__global__ __launch_bounds__(64 * k16Waves, 2) void gemm16_kernel(
     const T16* __restrict__ A, int64_t lda, const T16* __restrict__ B, int64_t ldb,
     float* __restrict__ C, int64_t ldc, int64_t strideS, int64_t M, int64_t N, int64_t Kp,
     int64_t kchunk, int tiles_m, int tiles_n) {
   constexpr int NT = 64 * k16Waves;
-  constexpr int BK = k16BK, LK = BK + 8, CH = BK / 8;
-  constexpr int BM = 16 * WM * k16Waves;
+  constexpr int WM = 2, BK = k16BK, LK = BK + 8, CH = BK / 8;
   constexpr int BN = 16 * WN;
   constexpr int CB = BN * CH, NB = (CB + NT - 1) / NT;
   typedef typename Mfma16<T16>::v8 v8;
@@ -91,7 +90,7 @@ __global__ __launch_bounds__(64 * k16Waves, WM == 2 ? 2 : 1) void gemm16_kernel(
   const int tile_m = (int)(w % tiles_m);
   const int tile_n = (int)((w / tiles_m) % tiles_n);
   const int split = (int)(w / ((int64_t)tiles_m * tiles_n));
-  const int64_t i0 = (int64_t)tile_m * BM, j0 = (int64_t)tile_n * BN;
+  const int64_t i0 = (int64_t)tile_m * k16BM, j0 = (int64_t)tile_n * BN;
   const int64_t kbeg = (int64_t)split * kchunk;
   const int64_t kend = (kbeg + kchunk < Kp) ? kbeg + kchunk : Kp;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -101,7 +100,7 @@ __global__ __launch_bounds__(64 * k16Waves, WM == 2 ? 2 : 1) void gemm16_kernel(
   const T16* arow[WM];
 #pragma unroll
   for (int a = 0; a < WM; ++a) {
-    int64_t row = i0 + wave * 16 * WM + a * 16 + r16;
+    int64_t row = i0 + wave * 32 + a * 16 + r16;
     row = row < M ? row : M - 1;
     arow[a] = A + row * lda + 16 * grp;
   }
@@ -184,7 +183,7 @@ __global__ __launch_bounds__(64 * k16Waves, WM == 2 ? 2 : 1) void gemm16_kernel(
       const int64_t col = j0 + b * 16 + r16;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = i0 + wave * 16 * WM + a * 16 + acc_row_f32(lane, r);
+        const int64_t row = i0 + wave * 32 + a * 16 + acc_row_f32(lane, r);
         if (row < M && col < N) Cs[row + col * ldc] = acc[a][b][r];
       }
     }
@@ -260,13 +259,12 @@ __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict_
 
 }  // namespace
 
-// Precision-form plan: 64 WM-row tiles (WM = 4 when M gives every CU a row
-// tile, else 2), N covered by as few tiles of at most 16 k16MaxWN columns as
-// possible (A is read once per N tile), split-K up to ~1024 workgroups with
-// at least four whole tiles per split.  Kp is the padded contraction length
-// (a multiple of k16BK).
+// Precision-form plan: k16BM-row tiles, N covered by as few tiles of at most
+// 16 k16MaxWN columns as possible (A is read once per N tile), split-K up to
+// ~1024 workgroups with at least four whole tiles per split.  Kp is the
+// padded contraction length (a multiple of k16BK).
 struct Plan16 {
-  int wn, wm;
+  int wn;
   int64_t tiles_m, tiles_n;
   int splits;
   int64_t kchunk;
@@ -274,18 +272,18 @@ struct Plan16 {
 
 int64_t pad16(int64_t K) { return (K + k16BK - 1) / k16BK * k16BK; }
 
-template <typename T16, int WN, int WM>
+template <typename T16, int WN>
 int gemm16_occupancy() {
-  static const int nb = occupancy_of(gemm16_kernel<T16, WN, WM>, 64 * k16Waves);
+  static const int nb = occupancy_of(gemm16_kernel<T16, WN>, 64 * k16Waves);
   return nb;
 }
 
 template <typename T16, int WN>
-int gemm16_occupancy_wn(int wn, int wm) {
+int gemm16_occupancy_wn(int wn) {
   if constexpr (WN > 1) {
-    if (wn < WN) return gemm16_occupancy_wn<T16, WN - 1>(wn, wm);
+    if (wn < WN) return gemm16_occupancy_wn<T16, WN - 1>(wn);
   }
-  return wm == 4 ? gemm16_occupancy<T16, WN, 4>() : gemm16_occupancy<T16, WN, 2>();
+  return gemm16_occupancy<T16, WN>();
 }
 
 Plan16 make_plan16(int64_t M, int64_t N, int64_t K, bool f16) {
@@ -294,15 +292,12 @@ Plan16 make_plan16(int64_t M, int64_t N, int64_t K, bool f16) {
   const int64_t nblk = (N + 15) / 16;
   p.tiles_n = (nblk + k16MaxWN - 1) / k16MaxWN;
   p.wn = (int)((nblk + p.tiles_n - 1) / p.tiles_n);
-  // 64-row waves need the registers of 15 column blocks at most
-  p.wm = (M >= 256 * (int64_t)cu_count() / 8 && p.wn <= 15) ? 4 : 2;
-  const int64_t BM = 16 * p.wm * k16Waves;
-  p.tiles_m = (M + BM - 1) / BM;
+  p.tiles_m = (M + k16BM - 1) / k16BM;
   const int64_t tiles = p.tiles_m * p.tiles_n;
   const int64_t max_s = std::max<int64_t>(1, Kp / (4 * k16BK));
-  const int occ = f16 ? gemm16_occupancy_wn<_Float16, k16MaxWN>(p.wn, p.wm)
-                      : gemm16_occupancy_wn<__bf16, k16MaxWN>(p.wn, p.wm);
-  choose_splits(tiles, Kp, k16BK, max_s, (int64_t)occ * cu_count(), 2.0 * BM * 16 * p.wn,
+  const int occ = f16 ? gemm16_occupancy_wn<_Float16, k16MaxWN>(p.wn)
+                      : gemm16_occupancy_wn<__bf16, k16MaxWN>(p.wn);
+  choose_splits(tiles, Kp, k16BK, max_s, (int64_t)occ * cu_count(), 2.0 * k16BM * 16 * p.wn,
                 900e12, 4.0 * (double)M * (double)N, &p.kchunk, &p.splits);
   return p;
 }
@@ -311,14 +306,9 @@ template <typename T16, int WN>
 static void run_gemm16(const Gemm16Args& g, const Plan16& p, float* dst, int64_t lddst,
                        int64_t strideS, hipStream_t st) {
   const unsigned T = (unsigned)(p.tiles_m * p.tiles_n * p.splits);
-  if (p.wm == 4)
-    hipLaunchKernelGGL((gemm16_kernel<T16, WN, 4>), dim3(T), dim3(64 * k16Waves), 0, st,
-                       (const T16*)g.A, g.lda, (const T16*)g.B, g.ldb, dst, lddst, strideS, g.M,
-                       g.N, pad16(g.K), p.kchunk, (int)p.tiles_m, (int)p.tiles_n);
-  else
-    hipLaunchKernelGGL((gemm16_kernel<T16, WN, 2>), dim3(T), dim3(64 * k16Waves), 0, st,
-                       (const T16*)g.A, g.lda, (const T16*)g.B, g.ldb, dst, lddst, strideS, g.M,
-                       g.N, pad16(g.K), p.kchunk, (int)p.tiles_m, (int)p.tiles_n);
+  hipLaunchKernelGGL((gemm16_kernel<T16, WN>), dim3(T), dim3(64 * k16Waves), 0, st,
+                     (const T16*)g.A, g.lda, (const T16*)g.B, g.ldb, dst, lddst, strideS, g.M,
+                     g.N, pad16(g.K), p.kchunk, (int)p.tiles_m, (int)p.tiles_n);
 }
 
 template <typename T16, int WN>
