@@ -394,8 +394,16 @@ __global__ __launch_bounds__(256) void sumsq_partial_kernel(const T* __restrict_
 __global__ __launch_bounds__(256) void sumsq_finish_kernel(const double* __restrict__ part,
                                                            int64_t nparts, double* __restrict__ out) {
   __shared__ double red[256];
-  double s = 0.0;
-  for (int64_t i = threadIdx.x; i < nparts; i += 256) s += part[i];
+  // eight loads in flight per thread, summed in a fixed order
+  double s8[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t i0 = threadIdx.x; i0 < nparts; i0 += 8 * 256) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t i = i0 + 256 * u;
+      s8[u] += i < nparts ? part[i] : 0.0;
+    }
+  }
+  const double s = ((s8[0] + s8[1]) + (s8[2] + s8[3])) + ((s8[4] + s8[5]) + (s8[6] + s8[7]));
   red[threadIdx.x] = s;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {

@@ -90,7 +90,7 @@ struct Layout {
   int64_t ld16, ldt16;  // leading dimensions of the 16-bit copies of A and A^T
   int64_t ldp16;        // leading dimension of the 16-bit copy of a panel
   // predictor and error judge (randqlp_factor_auto only)
-  size_t om64, y64, g64, feat, mlp, cls, jd, sums, sres, rerr;
+  size_t y64, g64, feat, mlp, cls, jd, sums, sres, rerr;
   size_t part2, part2_bytes;  // split-K scratch of the predictor's products
   size_t flags_bytes;  // status words cleared at the start of a call
 };
@@ -157,7 +157,6 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
     L.a16 = L.at16 = L.p16 = 0;
   }
   if (autoq) {
-    L.om64 = take((size_t)m * kPredCols * es);
     L.y64 = take((size_t)n * kPredCols * es);
     L.g64 = take((size_t)kPredCols * kPredCols * 8);
     L.feat = take(RQLP_MLP_INPUTS * 4);
@@ -168,7 +167,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
     L.sres = take(4 * 8);
     L.rerr = mixed ? take((size_t)convert16_blocks(m, n) * 2 * 8) : 0;
   } else {
-    L.om64 = L.y64 = L.g64 = L.feat = L.mlp = L.cls = L.jd = L.sums = L.sres = L.rerr = 0;
+    L.y64 = L.g64 = L.feat = L.mlp = L.cls = L.jd = L.sums = L.sres = L.rerr = 0;
   }
   L.scal = take(64);
   L.flags = take(64);
@@ -448,9 +447,14 @@ hipError_t prod(Ctx& c, const FactorArgs& f, int trans_a, const void* X, int64_t
 
 // Stages of the generalised Algorithm 1.  Panels: Zm / Tm (m x d) and
 // Yn / Tn (n x d) in the workspace; Qbar lives in Yn between stages.
-// start: Omega, Y = A^T Omega, Qbar = orth(Y).
-hipError_t stage_start(Ctx& c, const FactorArgs& f, PanelMode mode) {
-  const int64_t m = f.m, n = f.n, d = c.d;
+// start: Omega (in Zm), then the 16-bit copies of A, Y = A^T Omega and
+// Qbar = orth(Y).
+hipError_t stage_omega(Ctx& c, const FactorArgs& f) {
+  return launch_gaussian(c.ws + c.lay.m1, f.m, c.d, f.m, c.seed, 0, c.dt, c.st);   // randn
+}
+
+hipError_t stage_sketch(Ctx& c, const FactorArgs& f, PanelMode mode) {
+  const int64_t m = f.m, n = f.n;
   void* Zm = c.ws + c.lay.m1;
   void* Yn = c.ws + c.lay.n1;
   void* Tn = c.ws + c.lay.n2;
@@ -458,9 +462,13 @@ hipError_t stage_start(Ctx& c, const FactorArgs& f, PanelMode mode) {
     HIP_TRY(launch_convert16((const float*)f.A, m, n, f.lda, c.ws + c.lay.a16, c.lay.ld16,
                              c.ws + c.lay.at16, c.lay.ldt16, c.mixed == 2, c.st,
                              c.lay.rerr ? c.at<double>(c.lay.rerr) : nullptr));
-  HIP_TRY(launch_gaussian(Zm, m, d, m, c.seed, 0, c.dt, c.st));                // randn
   HIP_TRY(prod(c, f, 1, Zm, m, Yn, n));                                        // A^T Omega
   return orth(c, Yn, n, n, Yn, n, Tn, nullptr, mode, false);                   // Qbar
+}
+
+hipError_t stage_start(Ctx& c, const FactorArgs& f, PanelMode mode) {
+  HIP_TRY(stage_omega(c, f));
+  return stage_sketch(c, f, mode);
 }
 
 // `count` power rounds: Q = orth(A Qbar), Qbar = orth(A^T Q).
@@ -762,11 +770,11 @@ hipError_t mlp_loss_grad_dev(const float* th, const float* X, const int* y, int 
                                        st);
 }
 
-// The 64-column sketch of A (in A's precision), its fp64 Gram and the
-// features.  Omega's columns are the leading columns of the method's sketch.
+// The 64-column sketch of A (in A's precision) with the leading columns om
+// (ld m) of the method's own Gaussian sketch, its fp64 Gram and the
+// features.
 hipError_t feature_sketch(Ctx& c, const void* A, int64_t m, int64_t n, int64_t lda, int k,
-                          uint64_t seed, void* om, void* y64, double* g64, float* feat) {
-  HIP_TRY(launch_gaussian(om, m, kPredCols, m, seed, 0, c.dt, c.st));
+                          const void* om, void* y64, double* g64, float* feat) {
   HIP_TRY(gemm(c, 1, A, lda, om, m, y64, n, n, kPredCols, m, c.dt, c.dt, false));
   HIP_TRY(gemm(c, 1, y64, n, y64, n, g64, kPredCols, kPredCols, kPredCols, n, c.dt, DT_F64,
                true));
@@ -787,23 +795,21 @@ hipError_t aux_stream(hipStream_t* out) {
   return hipSuccess;
 }
 
-// Features -> MLP -> predicted class, enqueued on stream `st` with the
-// predictor's own scratch (it may run beside the main sequence), then read
-// back to the host (waits for `st` only).
-hipError_t predict_q(Ctx& c, const FactorArgs& f, int k, const float* params, int* cls,
-                     hipStream_t st) {
+// Features -> MLP -> predicted class (to the device word at c.lay.cls),
+// enqueued on stream `st` with the predictor's own scratch so that it runs
+// beside the main sequence; Omega (Zm) must be drawn and must stay in place
+// until the class has been computed.
+hipError_t predict_q(Ctx& c, const FactorArgs& f, int k, const float* params, hipStream_t st) {
   Ctx cp = c;
   cp.st = st;
   cp.lay.part = c.lay.part2;
   cp.lay.part_bytes = c.lay.part2_bytes;
   float* mlp = c.at<float>(c.lay.mlp);
   int* dcls = c.at<int>(c.lay.cls);
-  HIP_TRY(feature_sketch(cp, f.A, f.m, f.n, f.lda, k, c.seed, c.ws + c.lay.om64,
-                         c.ws + c.lay.y64, c.at<double>(c.lay.g64), c.at<float>(c.lay.feat)));
+  HIP_TRY(feature_sketch(cp, f.A, f.m, f.n, f.lda, k, c.ws + c.lay.m1, c.ws + c.lay.y64,
+                         c.at<double>(c.lay.g64), c.at<float>(c.lay.feat)));
   HIP_TRY(mlp_forward_dev(params, c.at<float>(c.lay.feat), 1, mlp, mlp + kNH, mlp + 2 * kNH, st));
-  HIP_TRY(launch_argmax(mlp + 2 * kNH, kNC, dcls, st));
-  HIP_TRY(hipMemcpyAsync(cls, dcls, sizeof(int), hipMemcpyDeviceToHost, st));
-  return hipStreamSynchronize(st);
+  return launch_argmax(mlp + 2 * kNH, kNC, dcls, st);
 }
 
 // Error judge after a run with q_hat rounds: sums = {||A||^2, ||L||^2,
@@ -913,18 +919,25 @@ rqlp_status randqlp_factor_auto(const void* A, int64_t m, int64_t n, int k, int 
   int q_used = q_fallback;
   bool done = false;
   const PanelMode mode0 = start_mode(o);
-  // The first sketch and its orth() do not depend on q: enqueue them, and
-  // run the predictor on the second stream beside them.
+  // The first sketch and its orth() do not depend on q.  Omega comes first;
+  // the predictor (whose sketch uses Omega's leading columns) is enqueued on
+  // the second stream right after it, then the rest of the first sketch on
+  // the main stream, and the class is read back when the predictor is done.
   hipStream_t aux = nullptr;
   hipEvent_t ready = nullptr;
   c.orth_calls = 0;
   hipError_t e = aux_stream(&aux);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventRecord(ready, c.st);           // A is ready here
   if (e == hipSuccess) e = hipMemsetAsync(c.flags(), 0, c.lay.flags_bytes, c.st);
-  if (e == hipSuccess) e = stage_start(c, f, mode0);
+  if (e == hipSuccess) e = stage_omega(c, f);
+  if (e == hipSuccess) e = hipEventRecord(ready, c.st);           // Omega is in Zm
   if (e == hipSuccess) e = hipStreamWaitEvent(aux, ready, 0);
-  if (e == hipSuccess) e = predict_q(c, f, k, params, &cls, aux);
+  if (e == hipSuccess) e = predict_q(c, f, k, params, aux);
+  if (e == hipSuccess) e = stage_sketch(c, f, mode0);
+  // (a copy to pageable memory may block the host: enqueue it last)
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&cls, c.at<int>(c.lay.cls), sizeof(int), hipMemcpyDeviceToHost, aux);
+  if (e == hipSuccess) e = hipStreamSynchronize(aux);
   if (ready) (void)hipEventDestroy(ready);
   if (e != hipSuccess) return fail(RQLP_E_HIP, "predictor: %s", hipGetErrorString(e));
   ai.q_predicted = cls;
@@ -1012,8 +1025,9 @@ rqlp_status randqlp_features(const void* A, int64_t m, int64_t n, int64_t lda, i
   c.ws = ws;
   c.lay.part = o_p;
   c.lay.part_bytes = part;
-  hipError_t e = feature_sketch(c, A, m, n, lda, k, seed, ws + o_om, ws + o_y,
-                                (double*)(ws + o_g), feat);
+  hipError_t e = launch_gaussian(ws + o_om, m, kPredCols, m, seed, 0, dt, c.st);
+  if (e == hipSuccess)
+    e = feature_sketch(c, A, m, n, lda, k, ws + o_om, ws + o_y, (double*)(ws + o_g), feat);
   if (e == hipSuccess) e = hipStreamSynchronize(c.st);
   if (e != hipSuccess) return fail(RQLP_E_HIP, "features: %s", hipGetErrorString(e));
   return RQLP_OK;
