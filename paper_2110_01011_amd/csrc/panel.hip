@@ -122,12 +122,12 @@ __device__ __forceinline__ void factor_diag_tile(double (*dg)[17], double (*dgi)
 // this layout the panel solve is L_IJ^T = L_JJ^{-1} T (four MFMAs from
 // registers), and the trailing update is T_IK -= L_KJ L_IJ^T.  Each updated
 // diagonal tile goes to the factor wave.  R = L^T is written as the tiles
-// become final (the zero tiles below its diagonal at the start), so no
-// store is left for the end of the kernel.
+// become final (the idle wave writes the zero tiles below its diagonal), so
+// no store is left for the end of the kernel.
 __device__ __forceinline__ void chol_tile_wave(
-    const double* __restrict__ G, int d, int64_t ldg, double sh, double (*dg)[17],
-    double (*dgi_all)[16][17], double (*pan)[17], int* ready, int wave, double* __restrict__ R,
-    int64_t ldr) {
+    const double* __restrict__ G, int d, int64_t ldg, double sh, double (*dg2)[16][17],
+    double (*dgi_all)[16][17], double (*pan)[17], double (*tpan)[17], double (*tdia)[17],
+    int* ready, int wave, double* __restrict__ R, int64_t ldr) {
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
   const int nt = (d + 15) / 16;
@@ -183,11 +183,23 @@ __device__ __forceinline__ void chol_tile_wave(
   // which goes to the factor wave as soon as it is in).
   auto owner = [&](int J) { return tile_wave_id((J * (J + 3) / 2) % kTileWaves); };
   auto slot = [&](int J) { return (J * (J + 3) / 2) / kTileWaves; };
-  auto publish = [&](int J, double4_t c) {  // dg = T^T (row-major)
+  auto publish0 = [&](double4_t c) {  // tile 0 to the factor wave: dg = T^T (row-major)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) dg[li][acc_row_f64(lane, r)] = c[r];
+    for (int r = 0; r < 4; ++r) dg2[0][li][acc_row_f64(lane, r)] = c[r];
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-    if (lane == 0) __hip_atomic_store(ready, J, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (lane == 0) __hip_atomic_store(ready, 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  };
+  // Tiles (Jn + 1, Jn) and (Jn + 1, Jn + 1), up to date through step Jn - 1,
+  // to LDS (accumulator layout) for the factor wave's lookahead in step Jn.
+  auto stash = [&](int Jn) {
+    if (Jn + 1 >= nt) return;
+#pragma unroll
+    for (int s = 0; s < kCholSlots; ++s) {
+      if (tI[s] != Jn + 1 || tJ[s] < Jn) continue;
+      double (*dst)[17] = (tJ[s] == Jn) ? tpan : tdia;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dst[acc_row_f64(lane, r)][li] = acc[s][r];
+    }
   };
 #pragma unroll
   for (int s = 0; s < kCholSlots; ++s) {
@@ -201,19 +213,17 @@ __device__ __forceinline__ void chol_tile_wave(
       else if (grow == gcol)
         acc[s][r] += sh;
     }
-    if (s == slot(0) && wave == owner(0)) publish(0, acc[s]);
+    if (s == slot(0) && wave == owner(0)) publish0(acc[s]);
   }
+  stash(0);
   // Every load has landed; an explicit wait on all counters tells the
   // compiler so, and keeps it from waiting on pending stores of R before
   // later uses of these registers.
   __builtin_amdgcn_s_waitcnt(0);
-  // R below the diagonal tiles is zero: tile (I, J), I > J, of R.
-#pragma unroll
-  for (int s = 0; s < kCholSlots; ++s)
-    if (tI[s] > tJ[s]) store4(16 * tI[s] + q0, 16 * tJ[s] + li, 0.0, 0.0, 0.0, 0.0);
   for (int J = 0; J < nt; ++J) {
     __syncthreads();  // L_JJ and its inverse are ready
     double (*dgi)[17] = dgi_all[J];
+    double (*dg)[17] = dg2[J & 1];
     // Panel: L_IJ^T = L_JJ^{-1} G_IJ^T for the tiles below the diagonal; pan
     // receives L_IJ (row-major rows 16 I ..), and the final tiles go to R.
 #pragma unroll
@@ -240,29 +250,12 @@ __device__ __forceinline__ void chol_tile_wave(
       }
     }
     __syncthreads();  // panel J is ready
-    // Lookahead: bring tile (J+1, J+1) up to date and hand it to wave 0,
-    // then apply the rest of the trailing update.
-    const bool ahead = (J + 1 < nt) && (wave == owner(J + 1));
-    if (ahead) {
-#pragma unroll
-      for (int s = 0; s < kCholSlots; ++s) {
-        if (s != slot(J + 1)) continue;
-        double4_t c = acc[s];
-        const int I = J + 1;
-#pragma unroll
-        for (int kq = 0; kq < 4; ++kq) {
-          const double a = pan[16 * I + li][kq * 4 + lk];
-          c = mma64(-a, a, c);
-        }
-        acc[s] = c;
-        publish(J + 1, c);
-      }
-    }
+    // Trailing update (the factor wave has already brought tile (J+1, J+1)
+    // up to date for itself; the copy here only feeds the next stash).
 #pragma unroll
     for (int s = 0; s < kCholSlots; ++s) {
       const int I = tI[s], K = tJ[s];
       if (K <= J) continue;
-      if (ahead && I == J + 1 && K == J + 1) continue;
       double4_t c = acc[s];
 #pragma unroll
       for (int kq = 0; kq < 4; ++kq) {
@@ -272,6 +265,7 @@ __device__ __forceinline__ void chol_tile_wave(
       }
       acc[s] = c;
     }
+    stash(J + 1);
   }
 }
 
@@ -287,8 +281,10 @@ __device__ __forceinline__ void cholesky_body(
     double* __restrict__ R, int64_t ldr, double* __restrict__ dinv,
     int* __restrict__ col_flags, int* __restrict__ flags,
     const double* __restrict__ odiag_src, int64_t odiag_stride) {
-  __shared__ double dg[16][17];
+  __shared__ double dg2[2][16][17];  // diagonal tile J in dg2[J & 1]
   __shared__ double dgi_all[CHOL_MAX_D / 16][16][17];  // inverse of L_JJ for every J
+  __shared__ double tpan[16][17], tdia[16][17];       // stashed tiles (J+1, J), (J+1, J+1)
+  __shared__ double wl[16][17];                       // the factor wave's L_{J+1,J}
   __shared__ double pan[CHOL_MAX_D][17];
   __shared__ double odiag[CHOL_MAX_D];
   __shared__ int colf[CHOL_MAX_D];
@@ -320,17 +316,62 @@ __device__ __forceinline__ void cholesky_body(
       const int j = lane + 64 * u;
       if (j < CHOL_MAX_D) odiag[j] = (j >= d) ? 1.0 : ov[u] + sh;
     }
+    const int li = lane & 15, lk = lane >> 4;
+    while (__hip_atomic_load(&ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < 0)
+      __builtin_amdgcn_s_sleep(1);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     for (int J = 0; J < nt; ++J) {
-      while (__hip_atomic_load(&ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < J)
-        __builtin_amdgcn_s_sleep(1);
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      factor_diag_tile(dg, dgi_all[J], odiag, J, d, tol_dep, tol_warn, colf, &sflag);
-      __syncthreads();  // L_JJ and its inverse are ready
+      factor_diag_tile(dg2[J & 1], dgi_all[J], odiag, J, d, tol_dep, tol_warn, colf, &sflag);
+      __syncthreads();  // L_JJ and its inverse are ready; tiles (J+1, J), (J+1, J+1) stashed
+      if (J + 1 < nt) {
+        // Lookahead: L_{J+1,J}^T = L_JJ^{-1} T_{J+1,J}, then tile (J+1, J+1)
+        // less L_{J+1,J} L_{J+1,J}^T, straight into the next diagonal buffer.
+        const double (*x)[17] = dgi_all[J];
+        double4_t t, c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          t[r] = tpan[acc_row_f64(lane, r)][li];
+          c[r] = tdia[acc_row_f64(lane, r)][li];
+        }
+        double4_t res = {0, 0, 0, 0};
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) res = mma64(x[li][kq * 4 + lk], t[kq], res);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) wl[li][acc_row_f64(lane, r)] = res[r];
+        wave_sync_lds();
+#pragma unroll
+        for (int kq = 0; kq < 4; ++kq) {
+          const double a = wl[li][kq * 4 + lk];
+          c = mma64(-a, a, c);
+        }
+        double (*dn)[17] = dg2[(J + 1) & 1];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dn[li][acc_row_f64(lane, r)] = c[r];
+        wave_sync_lds();
+      }
       __syncthreads();  // panel J is ready
     }
   } else if (wave == 4) {
+    const int li = lane & 15, q0 = 4 * (lane >> 4);
     for (int J = 0; J < nt; ++J) {
       __syncthreads();
+      // R below the diagonal tiles is zero: in step J the tiles (J + 1, K),
+      // K <= J (rows and columns past d dropped), four rows of one column
+      // per lane.
+      if (J + 1 < nt) {
+        const int row0 = 16 * (J + 1) + q0;
+        for (int K = 0; K <= J; ++K) {
+          const int col = 16 * K + li;
+          double* dst = R + row0 + (int64_t)col * ldr;
+          if (row0 + 3 < d) {
+            *reinterpret_cast<double2_a8*>(dst) = double2_a8{0.0, 0.0};
+            *reinterpret_cast<double2_a8*>(dst + 2) = double2_a8{0.0, 0.0};
+          } else {
+            for (int q = 0; q < 3; ++q)
+              if (row0 + q < d) dst[q] = 0.0;
+          }
+        }
+      }
       // the inverse of block J ((L_JJ^{-1})^T, column-major) and its marks
       const double (*x)[17] = dgi_all[J];
 #pragma unroll
@@ -340,7 +381,7 @@ __device__ __forceinline__ void cholesky_body(
       __syncthreads();
     }
   } else {
-    chol_tile_wave(G, d, ldg, sh, dg, dgi_all, pan, &ready, wave, R, ldr);
+    chol_tile_wave(G, d, ldg, sh, dg2, dgi_all, pan, tpan, tdia, &ready, wave, R, ldr);
   }
   __syncthreads();
   if (tid == 0 && sflag) atomicOr(flags, sflag);
