@@ -521,17 +521,16 @@ __device__ __forceinline__ void trsm_body(const TX* X, int64_t rows, int d, int6
 constexpr int kTrsmOwn = CHOL_MAX_D / 32;  // column blocks per wave
 
 template <typename TX, typename TO>
-__global__ __launch_bounds__(128) void trsm_rl_kernel(const TX* X, int64_t rows, int d,
-                                                      int64_t ldx, const double* __restrict__ R,
-                                                      int64_t ldr, const double* __restrict__ dinv,
-                                                      TO* Qx, int64_t ldq) {
+__device__ __forceinline__ void trsm_rl_body(const TX* X, int64_t rows, int d, int64_t ldx,
+                                             const double* __restrict__ R, int64_t ldr,
+                                             const double* __restrict__ dinv, TO* Qx, int64_t ldq,
+                                             const int64_t r0) {
   extern __shared__ double Qw[];
   const int nt = (d + 15) / 16, dp = nt * 16, lq = dp + 1;
   const int tid = threadIdx.x;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
-  const int64_t r0 = (int64_t)blockIdx.x * 16;
   // X block -> LDS: thread t takes row r0 + (t & 15) of columns t >> 4, + 8, ...
   {
     const int xr_i = tid & 15, xc0 = tid >> 4;
@@ -644,6 +643,24 @@ __global__ __launch_bounds__(128) void trsm_rl_kernel(const TX* X, int64_t rows,
       for (int c = xc0; c < d; c += 8) qr[(int64_t)c * ldq] = (TO)Qw[xr_i * lq + c];
     }
   }
+}
+
+template <typename TX, typename TO>
+__global__ __launch_bounds__(128) void trsm_rl_kernel(const TX* X, int64_t rows, int d,
+                                                      int64_t ldx, const double* __restrict__ R,
+                                                      int64_t ldr, const double* __restrict__ dinv,
+                                                      TO* Qx, int64_t ldq) {
+  trsm_rl_body<TX, TO>(X, rows, d, ldx, R, ldr, dinv, Qx, ldq, (int64_t)blockIdx.x * 16);
+}
+
+// Grouped form: workgroup b solves rows 16 bmap[b].y.. of problem bmap[b].x.
+template <typename T>
+__global__ __launch_bounds__(128) void trsm_rl_grouped_kernel(const GroupTrsm* __restrict__ descs,
+                                                              const int2* __restrict__ bmap) {
+  const int2 b = bmap[blockIdx.x];
+  const GroupTrsm t = descs[b.x];
+  trsm_rl_body<T, T>((const T*)t.X, t.rows, t.d, t.ldx, t.R, t.ldr, t.dinv, (T*)t.Qx, t.ldq,
+                     (int64_t)b.y * 16);
 }
 
 template <typename TX, typename TO>
@@ -976,6 +993,15 @@ hipError_t launch_trsm_grouped(Dtype dt, const GroupTrsm* descs, const int2* bma
   if (nblocks <= 0) return hipSuccess;
   const int dp = (dmax + 15) / 16 * 16;
   const size_t lds = (size_t)16 * (dp + 1) * sizeof(double);
+  if (dmax <= CHOL_MAX_D) {
+    if (dt == DT_F64)
+      hipLaunchKernelGGL(trsm_rl_grouped_kernel<double>, dim3((unsigned)nblocks), dim3(128), lds,
+                         st, descs, bmap);
+    else
+      hipLaunchKernelGGL(trsm_rl_grouped_kernel<float>, dim3((unsigned)nblocks), dim3(128), lds,
+                         st, descs, bmap);
+    return hipGetLastError();
+  }
   if (dt == DT_F64)
     hipLaunchKernelGGL(trsm_grouped_kernel<double>, dim3((unsigned)nblocks), dim3(64), lds, st,
                        descs, bmap);
