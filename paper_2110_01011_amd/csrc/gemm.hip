@@ -212,8 +212,12 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_kernel(
 }
 
 // Skinny products with a ragged width: 4 waves stacked along M (16 rows
-// each), WN MFMA blocks of 16 columns plus 4 vector-ALU columns per tile.
+// each in fp64, 32 in fp32, whose half-size registers leave room for a
+// second row block that reuses every panel fragment read from LDS), WN MFMA
+// blocks of 16 columns plus 4 vector-ALU columns per tile.
 constexpr int kRemWavesM = 4, kRemV = 4;
+template <typename TI>
+constexpr int rem_wm() { return sizeof(TI) == 4 ? 2 : 1; }
 template <typename TI, typename TC, typename TO, bool TA, int WN>
 __global__ __launch_bounds__(64 * kRemWavesM) void gemm_rem_kernel(
     const TI* __restrict__ A, int64_t lda, const TI* __restrict__ B, int64_t ldb,
@@ -222,7 +226,7 @@ __global__ __launch_bounds__(64 * kRemWavesM) void gemm_rem_kernel(
   // 8-deep tiles for A X (row tiles of A strided in memory: keeps the
   // register count within two waves per SIMD) and for the widest tiles
   // (keeps the LDS of one workgroup under the per-workgroup limit)
-  gemm_body<TI, TC, TO, TA, kRemWavesM, 1, 1, WN, (TA && WN <= 13) ? 16 : 8, kRemV>(
+  gemm_body<TI, TC, TO, TA, kRemWavesM, 1, rem_wm<TI>(), WN, (TA && WN <= 13) ? 16 : 8, kRemV>(
       A, lda, B, ldb, C, ldc, strideS, M, N, K, kchunk, 0, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
@@ -371,6 +375,8 @@ Plan make_plan(int trans_a, int64_t M, int64_t N, int64_t K, bool gram, Dtype in
     if (per % 16 > kRemV) ++wn;
     p.wn = (int)std::max<int64_t>(1, std::min<int64_t>(wn, kRemMaxWN));
     p.rem = true;
+    const int64_t BMr = 16 * kRemWavesM * (in_t == DT_F64 ? rem_wm<double>() : rem_wm<float>());
+    p.tiles_m = (M + BMr - 1) / BMr;
     const int64_t BN = 16 * p.wn + kRemV;
     p.tiles_n = (N + BN - 1) / BN;
     const int occ = in_t == DT_F64
@@ -379,7 +385,7 @@ Plan make_plan(int trans_a, int64_t M, int64_t N, int64_t K, bool gram, Dtype in
                         : (trans_a ? rem_occupancy_wn<float, true>(p.wn)
                                    : rem_occupancy_wn<float, false>(p.wn));
     choose_splits(p.tiles_m * p.tiles_n, K, kBK, max_s, (int64_t)occ * cu_count(),
-                  2.0 * kBM * BN, in_t == DT_F64 ? 45e12 : 110e12,
+                  2.0 * BMr * BN, in_t == DT_F64 ? 45e12 : 110e12,
                   (out_t == DT_F64 ? 8.0 : 4.0) * (double)M * (double)N, &p.kchunk, &p.splits);
     return p;
   }
