@@ -653,16 +653,6 @@ __global__ __launch_bounds__(128) void trsm_rl_kernel(const TX* X, int64_t rows,
   trsm_rl_body<TX, TO>(X, rows, d, ldx, R, ldr, dinv, Qx, ldq, (int64_t)blockIdx.x * 16);
 }
 
-// Grouped form: workgroup b solves rows 16 bmap[b].y.. of problem bmap[b].x.
-template <typename T>
-__global__ __launch_bounds__(128) void trsm_rl_grouped_kernel(const GroupTrsm* __restrict__ descs,
-                                                              const int2* __restrict__ bmap) {
-  const int2 b = bmap[blockIdx.x];
-  const GroupTrsm t = descs[b.x];
-  trsm_rl_body<T, T>((const T*)t.X, t.rows, t.d, t.ldx, t.R, t.ldr, t.dinv, (T*)t.Qx, t.ldq,
-                     (int64_t)b.y * 16);
-}
-
 template <typename TX, typename TO>
 __global__ __launch_bounds__(64) void trsm_kernel(const TX* X, int64_t rows, int d, int64_t ldx,
                                                   const double* __restrict__ R, int64_t ldr,
@@ -993,15 +983,6 @@ hipError_t launch_trsm_grouped(Dtype dt, const GroupTrsm* descs, const int2* bma
   if (nblocks <= 0) return hipSuccess;
   const int dp = (dmax + 15) / 16 * 16;
   const size_t lds = (size_t)16 * (dp + 1) * sizeof(double);
-  if (dmax <= CHOL_MAX_D) {
-    if (dt == DT_F64)
-      hipLaunchKernelGGL(trsm_rl_grouped_kernel<double>, dim3((unsigned)nblocks), dim3(128), lds,
-                         st, descs, bmap);
-    else
-      hipLaunchKernelGGL(trsm_rl_grouped_kernel<float>, dim3((unsigned)nblocks), dim3(128), lds,
-                         st, descs, bmap);
-    return hipGetLastError();
-  }
   if (dt == DT_F64)
     hipLaunchKernelGGL(trsm_grouped_kernel<double>, dim3((unsigned)nblocks), dim3(64), lds, st,
                        descs, bmap);
