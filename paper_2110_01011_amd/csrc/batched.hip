@@ -148,7 +148,7 @@ Launch gemm_launch(std::vector<char>& buf, const std::vector<GroupGemm>& descs, 
   return l;
 }
 
-ProdSet prod_set(std::vector<char>& buf, const std::vector<GroupGemm>& descs, int wn) {
+ProdSet prod_set(std::vector<char>& buf, const std::vector<GroupGemm>& descs, int wn, Dtype dt) {
   ProdSet ps;
   ps.wn = wn;
   if (wn == kRemSet) {
@@ -156,7 +156,8 @@ ProdSet prod_set(std::vector<char>& buf, const std::vector<GroupGemm>& descs, in
     for (int c : {2, 4, 6, 9, 13}) {
       std::vector<int4> map;
       for (size_t i = 0; i < descs.size(); ++i)
-        if (grouped_rem_class(descs[i].N) == c) gemm_rem_grouped_blocks(descs[i], (int)i, c, map);
+        if (grouped_rem_class(descs[i].N) == c)
+          gemm_rem_grouped_blocks(descs[i], (int)i, c, dt, map);
       if (map.empty()) continue;
       longest_first(descs, map);
       Launch l;
@@ -449,10 +450,10 @@ rqlp_status randqlp_batch_create(int count, const void* const* A, const int64_t*
     b->gauss.nblocks = (int64_t)map.size();
   }
   for (int wn : {0, 1, 2, 4, 8, kRemSet}) {
-    b->tn_alt[wn] = prod_set(buf, tn, wn);
-    b->tnf_alt[wn] = prod_set(buf, tnf, wn);
+    b->tn_alt[wn] = prod_set(buf, tn, wn, b->dt);
+    b->tnf_alt[wn] = prod_set(buf, tnf, wn, b->dt);
   }
-  for (int wn : {0, 1, 2, 4, kRemSet}) b->nn_alt[wn] = prod_set(buf, nn, wn);
+  for (int wn : {0, 1, 2, 4, kRemSet}) b->nn_alt[wn] = prod_set(buf, nn, wn, b->dt);
   if (!b->tn_alt.count(b->wn_tn)) b->wn_tn = 0;
   if (!b->nn_alt.count(b->wn_nn)) b->wn_nn = 0;
   b->tn = b->tn_alt[b->wn_tn];

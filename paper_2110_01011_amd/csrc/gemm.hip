@@ -236,7 +236,7 @@ __global__ __launch_bounds__(64 * kRemWavesM) void gemm_rem_grouped_kernel(
     const GroupGemm* __restrict__ descs, const int4* __restrict__ bmap) {
   const int4 b = bmap[blockIdx.x];
   const GroupGemm g = descs[b.x];
-  gemm_body<TI, TC, TO, TA, kRemWavesM, 1, 1, WN, (TA && WN <= 13) ? 16 : 8, kRemV>(
+  gemm_body<TI, TC, TO, TA, kRemWavesM, 1, rem_wm<TI>(), WN, (TA && WN <= 13) ? 16 : 8, kRemV>(
       (const TI*)g.A, g.lda, (const TI*)g.B, g.ldb, (TO*)g.C, g.ldc, 0, g.M, g.N, g.K, g.K, 0,
       b.y, b.z, 0);
 }
@@ -569,9 +569,11 @@ int grouped_rem_class(int64_t d) {
   return 13;
 }
 
-void gemm_rem_grouped_blocks(const GroupGemm& g, int idx, int wn, std::vector<int4>& out) {
+void gemm_rem_grouped_blocks(const GroupGemm& g, int idx, int wn, Dtype dt,
+                             std::vector<int4>& out) {
   const int64_t BN = 16 * wn + kRemV;
-  const int64_t tm = (g.M + kBM - 1) / kBM, tn = (g.N + BN - 1) / BN;
+  const int64_t BMr = 16 * kRemWavesM * (dt == DT_F64 ? rem_wm<double>() : rem_wm<float>());
+  const int64_t tm = (g.M + BMr - 1) / BMr, tn = (g.N + BN - 1) / BN;
   for (int64_t j = 0; j < tn; ++j)
     for (int64_t i = 0; i < tm; ++i) out.push_back(int4{idx, (int)i, (int)j, 0});
 }

@@ -194,7 +194,8 @@ int grouped_wn_round(int wn);
 // The remainder layout (16 wn MFMA columns + 4 vector-ALU columns per tile):
 // class width for a product of width d, block list, and launch.
 int grouped_rem_class(int64_t d);
-void gemm_rem_grouped_blocks(const GroupGemm& g, int idx, int wn, std::vector<int4>& out);
+void gemm_rem_grouped_blocks(const GroupGemm& g, int idx, int wn, Dtype dt,
+                             std::vector<int4>& out);
 hipError_t launch_gemm_rem_grouped(Dtype dt, int trans_a, int wn, const GroupGemm* descs,
                                    const int4* bmap, int64_t nblocks, hipStream_t st);
 hipError_t launch_gemm_grouped(Dtype in_t, Dtype out_t, int trans_a, bool gram, int wn,

@@ -127,12 +127,16 @@ def test_orth_f64_matches_lapack(rq, rows, d, kappa):
     assert np.abs(Rg - Ro).max() <= 1e-13 * kappa * np.abs(Ro).max()
 
 
-def test_orth_f32_orthonormal(rq):
+@pytest.mark.parametrize("rows,d,kappa", [(3000, 64, 1e3), (8001, 210, 1e2), (777, 224, 10.0),
+                                          (40, 33, 5.0)])
+def test_orth_f32_orthonormal(rq, rows, d, kappa):
     import torch
-    X = _panel(3000, 64, 1e3, 5).astype(np.float32)
+    log(f"orth f32 rows={rows} d={d} kappa={kappa}")
+    X = _panel(rows, d, kappa, 5 + d).astype(np.float32)
     Qg, Rg = rq.orth(to_dev(X, torch.float32))
     Qg, Rg = to_np(Qg), to_np(Rg)
-    assert np.abs(Qg.T @ Qg - np.eye(64)).max() < 2e-5
+    assert np.abs(Qg.T @ Qg - np.eye(d)).max() < 2e-5
+    assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) >= 0)
     assert np.abs(Qg @ Rg - X).max() <= 1e-5 * np.abs(X).max()
 
 
