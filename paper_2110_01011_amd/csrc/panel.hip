@@ -517,11 +517,13 @@ __device__ __forceinline__ void trsm_body(const TX* X, int64_t rows, int d, int6
 // V_{J+1} R_{J+1,J+1}^{-1} at once, so the chain between steps is one
 // barrier and eight MFMAs while the rest of the update runs beside it.  The
 // R fragments of the next step are loaded during the current one.  X (the
-// whole row block) passes through LDS on the way in and Q on the way out.
+// whole row block, less P when P is given) passes through LDS on the way in
+// and Q on the way out.
 constexpr int kTrsmOwn = CHOL_MAX_D / 32;  // column blocks per wave
 
 template <typename TX, typename TO>
 __device__ __forceinline__ void trsm_rl_body(const TX* X, int64_t rows, int d, int64_t ldx,
+                                             const TX* P, int64_t ldp,
                                              const double* __restrict__ R, int64_t ldr,
                                              const double* __restrict__ dinv, TO* Qx, int64_t ldq,
                                              const int64_t r0) {
@@ -531,22 +533,41 @@ __device__ __forceinline__ void trsm_rl_body(const TX* X, int64_t rows, int d, i
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int lane = tid & 63;
   const int li = lane & 15, lk = lane >> 4;
-  // X block -> LDS: thread t takes row r0 + (t & 15) of columns t >> 4, + 8, ...
+  // X (- P) block -> LDS: thread t takes row r0 + (t & 15) of columns t >> 4, + 8, ...
   {
     const int xr_i = tid & 15, xc0 = tid >> 4;
     const bool rowok = r0 + xr_i < rows;
     const TX* xr = X + (rowok ? r0 + xr_i : r0);
-    for (int c0 = 0; c0 < dp; c0 += 8 * 16) {
-      double xv[16];
+    if (P == nullptr) {
+      for (int c0 = 0; c0 < dp; c0 += 8 * 16) {
+        double xv[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int c = c0 + xc0 + 8 * u;
-        xv[u] = (rowok && c < d) ? (double)xr[(int64_t)c * ldx] : 0.0;
+        for (int u = 0; u < 16; ++u) {
+          const int c = c0 + xc0 + 8 * u;
+          xv[u] = (rowok && c < d) ? (double)xr[(int64_t)c * ldx] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int c = c0 + xc0 + 8 * u;
+          if (c < dp) Qw[xr_i * lq + c] = xv[u];
+        }
       }
+    } else {
+      const TX* pr = P + (rowok ? r0 + xr_i : r0);
+      for (int c0 = 0; c0 < dp; c0 += 8 * 8) {
+        double xv[8], pv[8];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int c = c0 + xc0 + 8 * u;
-        if (c < dp) Qw[xr_i * lq + c] = xv[u];
+        for (int u = 0; u < 8; ++u) {
+          const int c = c0 + xc0 + 8 * u;
+          const bool ok = rowok && c < d;
+          xv[u] = ok ? (double)xr[(int64_t)c * ldx] : 0.0;
+          pv[u] = ok ? (double)pr[(int64_t)c * ldp] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int c = c0 + xc0 + 8 * u;
+          if (c < dp) Qw[xr_i * lq + c] = xv[u] - pv[u];
+        }
       }
     }
   }
@@ -647,10 +668,12 @@ __device__ __forceinline__ void trsm_rl_body(const TX* X, int64_t rows, int d, i
 
 template <typename TX, typename TO>
 __global__ __launch_bounds__(128) void trsm_rl_kernel(const TX* X, int64_t rows, int d,
-                                                      int64_t ldx, const double* __restrict__ R,
+                                                      int64_t ldx, const TX* P, int64_t ldp,
+                                                      const double* __restrict__ R,
                                                       int64_t ldr, const double* __restrict__ dinv,
                                                       TO* Qx, int64_t ldq) {
-  trsm_rl_body<TX, TO>(X, rows, d, ldx, R, ldr, dinv, Qx, ldq, (int64_t)blockIdx.x * 16);
+  trsm_rl_body<TX, TO>(X, rows, d, ldx, P, ldp, R, ldr, dinv, Qx, ldq,
+                       (int64_t)blockIdx.x * 16);
 }
 
 template <typename TX, typename TO>
@@ -875,13 +898,14 @@ hipError_t launch_zero_block(double* Z, int64_t rows, int64_t cols, int64_t ldz,
 template <typename TX, typename TO>
 static hipError_t trsm_typed(const void* X, int64_t rows, int64_t d, int64_t ldx,
                              const double* R, int64_t ldr, const double* dinv, void* Qx,
-                             int64_t ldq, hipStream_t st) {
+                             int64_t ldq, hipStream_t st, const void* P, int64_t ldp) {
   const int nt = (int)((d + 15) / 16), dp = nt * 16;
   const size_t lds = sizeof(double) * (size_t)16 * (dp + 1);
   const int64_t blocks = (rows + 15) / 16;
   if (d <= CHOL_MAX_D) {
     hipLaunchKernelGGL((trsm_rl_kernel<TX, TO>), dim3((unsigned)blocks), dim3(128), lds, st,
-                       (const TX*)X, rows, (int)d, ldx, R, ldr, dinv, (TO*)Qx, ldq);
+                       (const TX*)X, rows, (int)d, ldx, (const TX*)P, ldp, R, ldr, dinv,
+                       (TO*)Qx, ldq);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((trsm_kernel<TX, TO>), dim3((unsigned)blocks), dim3(64), lds, st,
@@ -891,12 +915,13 @@ static hipError_t trsm_typed(const void* X, int64_t rows, int64_t d, int64_t ldx
 
 hipError_t launch_trsm(const void* X, int64_t rows, int64_t d, int64_t ldx, const double* R,
                        int64_t ldr, const double* dinv, void* Qx, int64_t ldq, Dtype dt,
-                       hipStream_t st) {
+                       hipStream_t st, const void* P, int64_t ldp) {
   if (d > TRSM_MAX_D) return hipErrorInvalidValue;
+  if (P != nullptr && (d > CHOL_MAX_D || ldp < rows)) return hipErrorInvalidValue;
   if (rows <= 0 || d <= 0) return hipSuccess;
   if (dt == DT_F64)
-    return trsm_typed<double, double>(X, rows, d, ldx, R, ldr, dinv, Qx, ldq, st);
-  return trsm_typed<float, float>(X, rows, d, ldx, R, ldr, dinv, Qx, ldq, st);
+    return trsm_typed<double, double>(X, rows, d, ldx, R, ldr, dinv, Qx, ldq, st, P, ldp);
+  return trsm_typed<float, float>(X, rows, d, ldx, R, ldr, dinv, Qx, ldq, st, P, ldp);
 }
 
 hipError_t launch_first_order_pass(const double* G2, int64_t d, double tol, double* B,

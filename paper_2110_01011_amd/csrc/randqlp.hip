@@ -86,7 +86,7 @@ constexpr double kJudgeSlack = 0.0404;
 
 struct Layout {
   size_t m1, m2, n1, n2, part, part_bytes, G, R[4], Racc[2], Rfin, dinv, colf, scal, flags,
-      chs, a16, at16, p16, total;
+      chs, tsub, tsr, a16, at16, p16, total;
   int64_t ld16, ldt16;  // leading dimensions of the 16-bit copies of A and A^T
   int64_t ldp16;        // leading dimension of the 16-bit copy of a panel
   // predictor and error judge (randqlp_factor_auto only)
@@ -119,6 +119,10 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
   for (int64_t dd = d; dd > CHOL_MAX_D; dd -= CHOL_MAX_D)  // Schur-complement Grams
     part = std::max(part, gemm_partial_bytes(1, dd - CHOL_MAX_D, dd - CHOL_MAX_D, CHOL_MAX_D,
                                              DT_F64, DT_F64, true));
+  for (int64_t j0 = CHOL_MAX_D; j0 < d; j0 += CHOL_MAX_D)  // blocked TRSM products
+    for (int64_t rows : {m, n})
+      part = std::max(part, gemm_partial_bytes(0, rows, std::min<int64_t>(CHOL_MAX_D, d - j0),
+                                               j0, dt, dt, false));
   if (mixed) {
     for (bool f16 : {false, true}) {
       part = std::max(part, gemm16_partial_bytes(n, d, m, f16));
@@ -143,6 +147,12 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
   for (int i = 0; i < 2; ++i) L.Racc[i] = take((size_t)d * d * 8);
   L.Rfin = take((size_t)d * d * 8);
   L.chs = take((size_t)4 * d * d * 8);  // blocked Cholesky: off-diagonal solve + Schur blocks
+  if (d > CHOL_MAX_D) {  // blocked TRSM: P of one column block, fp32 copy of R's block column
+    L.tsub = take((size_t)std::max(m, n) * CHOL_MAX_D * es);
+    L.tsr = take((size_t)d * CHOL_MAX_D * 4);
+  } else {
+    L.tsub = L.tsr = 0;
+  }
   L.dinv = take((size_t)((d + 15) / 16) * 256 * 8);
   L.colf = take((size_t)d * 4);
   if (mixed) {
@@ -332,6 +342,42 @@ hipError_t chol_any(Ctx& c, const double* G, int64_t d, int64_t ldg, double shif
                   S + d2 * d2);
 }
 
+// Qx = X R^+ (rows x d; Qx may be X with the same ld).  Up to CHOL_MAX_D
+// columns this is one TRSM launch.  Wider panels go in column blocks of
+// CHOL_MAX_D: for block j, one product over all finished columns gives
+// P_j = Q_{<j} R_{<j,j}, and the TRSM solves (X_j - P_j) R_jj^{-1}.  The
+// product runs in the panel's precision (fp32 panels use an fp32 copy of
+// R's block column).
+hipError_t trsm_any(Ctx& c, const void* X, int64_t rows, int64_t ldx, const double* R,
+                    int64_t ldr, const double* dinv, void* Qx, int64_t ldq) {
+  const int64_t d = c.d;
+  if (d <= CHOL_MAX_D) return launch_trsm(X, rows, d, ldx, R, ldr, dinv, Qx, ldq, c.dt, c.st);
+  const size_t es = elem_size(c.dt);
+  void* P = c.ws + c.lay.tsub;
+  for (int64_t j0 = 0; j0 < d; j0 += CHOL_MAX_D) {
+    const int64_t bj = std::min<int64_t>(CHOL_MAX_D, d - j0);
+    const void* Xj = (const char*)X + (size_t)j0 * ldx * es;
+    void* Qj = (char*)Qx + (size_t)j0 * ldq * es;
+    const double* Rjj = R + j0 + j0 * ldr;
+    const double* dj = dinv + (j0 / 16) * 256;
+    if (j0 == 0) {
+      HIP_TRY(launch_trsm(Xj, rows, bj, ldx, Rjj, ldr, dj, Qj, ldq, c.dt, c.st));
+      continue;
+    }
+    const void* Rb = R + j0 * ldr;
+    int64_t ldrb = ldr;
+    if (c.dt == DT_F32) {
+      HIP_TRY(launch_copy_panel(R + j0 * ldr, DT_F64, ldr, c.ws + c.lay.tsr, DT_F32, j0, j0, bj,
+                                c.st));
+      Rb = c.ws + c.lay.tsr;
+      ldrb = j0;
+    }
+    HIP_TRY(gemm(c, 0, Qx, ldq, Rb, ldrb, P, rows, rows, bj, j0, c.dt, c.dt, false));
+    HIP_TRY(launch_trsm(Xj, rows, bj, ldx, Rjj, ldr, dj, Qj, ldq, c.dt, c.st, P, rows));
+  }
+  return hipSuccess;
+}
+
 // One Cholesky QR pass: X (rows x d) -> Qx = X R^+, R into Rbuf.
 hipError_t chol_pass(Ctx& c, const void* X, int64_t rows, int64_t ldx, void* Qx, int64_t ldq,
                      double* Rbuf, const double* shift_dev, double tol_dep, double tol_warn,
@@ -342,7 +388,7 @@ hipError_t chol_pass(Ctx& c, const void* X, int64_t rows, int64_t ldx, void* Qx,
   HIP_TRY(gemm(c, 1, X, ldx, X, ldx, G, d, d, d, rows, c.dt, DT_F64, true));
   HIP_TRY(chol_any(c, G, d, d, 0.0, shift_dev, tol_dep, tol_warn, Rbuf, d, dinv, col_flags,
                    nullptr, 0, c.at<double>(c.lay.chs)));
-  return launch_trsm(X, rows, d, ldx, Rbuf, d, dinv, Qx, ldq, c.dt, c.st);
+  return trsm_any(c, X, rows, ldx, Rbuf, d, dinv, Qx, ldq);
 }
 
 // Panel QR strategies, cheapest first.
@@ -403,7 +449,7 @@ hipError_t orth(Ctx& c, const void* X, int64_t rows, int64_t ldx, void* out, int
   double* dinv = c.at<double>(c.lay.dinv);
   HIP_TRY(chol_any(c, G, d, d, 0.0, scal + 1, 0.0, 0.0, R[0], d, dinv, nullptr, nullptr, 0,
                    c.at<double>(c.lay.chs)));
-  HIP_TRY(launch_trsm(X, rows, d, ldx, R[0], d, dinv, tmp, rows, c.dt, c.st));
+  HIP_TRY(trsm_any(c, X, rows, ldx, R[0], d, dinv, tmp, rows));
   // pass 2: detect dependent columns (zeroed), then complete them
   HIP_TRY(chol_pass(c, tmp, rows, rows, out, ldo, R[1], nullptr, kTolDepRobust, 0.0, colf));
   HIP_TRY(launch_count_flags(colf, d, c.flags() + 2, c.st));

@@ -126,11 +126,12 @@ hipError_t launch_transpose(const double* S, int64_t rows, int64_t cols, int64_t
 hipError_t launch_schur(const double* G22, int64_t ldg, const double* C, int64_t n, double shift,
                         const double* shift_dev, double* S, hipStream_t st);
 hipError_t launch_zero_block(double* Z, int64_t rows, int64_t cols, int64_t ldz, hipStream_t st);
-// Qx (rows x d) = X R^+ with R upper (d x d, ldr) and its diagonal-block
-// inverses; Qx may be X itself (same ld).
+// Qx (rows x d) = (X - P) R^+ with R upper (d x d, ldr) and its
+// diagonal-block inverses; Qx may be X itself (same ld).  P (rows x d, ldp,
+// the type of X) is optional and needs d <= CHOL_MAX_D.
 hipError_t launch_trsm(const void* X, int64_t rows, int64_t d, int64_t ldx, const double* R,
                        int64_t ldr, const double* dinv, void* Qx, int64_t ldq, Dtype dt,
-                       hipStream_t st);
+                       hipStream_t st, const void* P = nullptr, int64_t ldp = 0);
 // Second Cholesky QR pass to first order from G2 = Q1^T Q1 = I + E:
 // B = I - F, R2 = I + F with F = triu(E, 1) + diag(E) / 2 (d x d, tight);
 // raises FLAG_SECOND_PASS if max |E| > tol.

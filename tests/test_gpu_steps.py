@@ -128,7 +128,7 @@ def test_orth_f64_matches_lapack(rq, rows, d, kappa):
 
 
 @pytest.mark.parametrize("rows,d,kappa", [(3000, 64, 1e3), (8001, 210, 1e2), (777, 224, 10.0),
-                                          (40, 33, 5.0)])
+                                          (40, 33, 5.0), (5000, 520, 1e2), (1500, 449, 10.0)])
 def test_orth_f32_orthonormal(rq, rows, d, kappa):
     import torch
     log(f"orth f32 rows={rows} d={d} kappa={kappa}")
