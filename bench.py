@@ -168,8 +168,9 @@ def headline(rq, A_c2, k, p, steps):
 
 def workload_c3(args):
     """Precision form: 20000 x 16000, sigma_i = exp(-i/100) (rank 4000, Haar
-    factors), k = 500, p = 20, q = 2 (d = 520); fp64, fp32, bf16 and fp16 forms,
-    each with its error against the fp64 oracle's value for the same matrix."""
+    factors), k = 500, p = 20, q = 2 (d = 520); fp64, fp32, bf16, fp16 and
+    bf16x3 (bf16 with the split bf16 final projection) forms, each with its
+    error against the fp64 form's value for the same matrix."""
     import torch
 
     import paper_2110_01011_amd as rq
@@ -188,7 +189,7 @@ def workload_c3(args):
     flops = randqlp_flops(m, n, d, q)
     opt = float(torch.sqrt(torch.sum(sig[d:] ** 2)).item() / torch.linalg.norm(sig).item())
     forms = {}
-    for prec in ("f64", "f32", "bf16", "f16"):
+    for prec in ("f64", "f32", "bf16", "f16", "bf16x3"):
         A = A64 if prec == "f64" else A32
         for _ in range(args.warmup):
             rq.factor(A, k, p, q, 0, precision=prec)

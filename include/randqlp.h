@@ -60,8 +60,22 @@ typedef enum {
  *                   16-bit copies with fp32 accumulation (panels rounded to
  *                   16 bits as they are read); the final projection A^T Q
  *                   uses the fp32 A.  Panels are fp32.
+ *  RQLP_MIXED_BF16X3  as RQLP_MIXED_BF16, except that the final projection
+ *                   A^T Q runs as a split bfloat16 product: with A = A1 + A2
+ *                   and Q = Q1 + Q2 (A1, Q1 rounded to bfloat16, A2, Q2 their
+ *                   rounded residuals) it sums A1^T Q1 + A1^T Q2 + A2^T Q1
+ *                   with fp32 accumulation: relative error about 2^-16 per
+ *                   product term (fp32 accumulation as in RQLP_F32), on the
+ *                   bfloat16 matrix cores.  A's residual is a third 16-bit
+ *                   copy in the workspace.
  * In every mode the Gram matrices, Cholesky factors and R are double. */
-typedef enum { RQLP_F64 = 0, RQLP_F32 = 1, RQLP_MIXED_BF16 = 2, RQLP_MIXED_F16 = 3 } rqlp_precision;
+typedef enum {
+  RQLP_F64 = 0,
+  RQLP_F32 = 1,
+  RQLP_MIXED_BF16 = 2,
+  RQLP_MIXED_F16 = 3,
+  RQLP_MIXED_BF16X3 = 4
+} rqlp_precision;
 
 /* Panel QR used for every orth():
  *  AUTO    Cholesky QR with a second pass; if any pass reports a non-positive
@@ -153,7 +167,8 @@ rqlp_status randqlp_gaussian(void* out, int64_t m, int64_t d, int64_t ld, uint64
  * RQLP_F32: A, X, C of that type.  RQLP_MIXED_BF16 / RQLP_MIXED_F16: A, X
  * and C are float; A and X are rounded to 16 bits (nearest even) into
  * library scratch and multiplied on the precision-form kernel with fp32
- * accumulation.  Synchronous (the library's scratch may be reused). */
+ * accumulation.  RQLP_MIXED_BF16X3: the split bfloat16 product described
+ * with rqlp_precision.  Synchronous (the library's scratch may be reused). */
 rqlp_status randqlp_gemm(int trans_a, const void* A, int64_t m, int64_t n, int64_t lda,
                          const void* X, int64_t d, int64_t ldx, void* C, int64_t ldc,
                          int precision, void* stream);

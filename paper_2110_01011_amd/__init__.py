@@ -15,14 +15,15 @@ import os
 __all__ = ["factor", "factor_auto", "Batch", "factor_batched", "tune_save", "tune_load", "features", "mlp_forward", "mlp_loss_grad", "mlp_adam",
            "mlp_train", "gaussian", "gemm", "orth", "sketch_width", "workspace_size",
            "colmajor", "empty_colmajor", "lib", "RandQLPError", "F64", "F32", "MIXED_BF16",
-           "MIXED_F16",
+           "MIXED_F16", "MIXED_BF16X3",
            "PANEL_AUTO", "PANEL_CHOLQR2", "PANEL_ROBUST"]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librandqlp.so")
 
-F64, F32, MIXED_BF16, MIXED_F16 = 0, 1, 2, 3
-_PRECISIONS = {"f64": F64, "f32": F32, "bf16": MIXED_BF16, "f16": MIXED_F16}
+F64, F32, MIXED_BF16, MIXED_F16, MIXED_BF16X3 = 0, 1, 2, 3, 4
+_PRECISIONS = {"f64": F64, "f32": F32, "bf16": MIXED_BF16, "f16": MIXED_F16,
+               "bf16x3": MIXED_BF16X3}
 PANEL_AUTO, PANEL_CHOLQR2, PANEL_ROBUST = 0, 1, 2
 _PANELS = {"auto": PANEL_AUTO, "cholqr2": PANEL_CHOLQR2, "robust": PANEL_ROBUST}
 STATUS = {0: "RQLP_OK", 1: "RQLP_E_INVALID_ARG", 2: "RQLP_E_NONFINITE", 3: "RQLP_E_NOMEM",
@@ -241,7 +242,7 @@ def _prepare(A, k, p, q, panel, precision):
         prec = _PRECISIONS[precision] if isinstance(precision, str) else int(precision)
         if (prec == F64) != (A.dtype == torch.float64):
             raise TypeError("precision does not match A's dtype (f64 needs float64, "
-                            "f32/bf16/f16 need float32)")
+                            "f32/bf16/f16/bf16x3 need float32)")
     d = sketch_width(m, n, k, p)
     if d < 1:
         _check(lib().randqlp_factor(None, m, n, k, p, q, 0, None, None, None, None))
@@ -261,7 +262,8 @@ def factor(A, k, p, q, seed, panel="auto", precision=None, return_info=False):
     """Rand-QLP of a device matrix A (m x n, float64 or float32).
 
     precision: None (from A's dtype), "f64", "f32", or the precision forms
-    "bf16" / "f16" (A float32; the products with A run on a 16-bit copy).
+    "bf16" / "f16" (A float32; the products with A run on a 16-bit copy) and
+    "bf16x3" (as "bf16", with the final projection as the split bf16 product).
     Returns (Q, L, P): Q (m x d) and P (n x d) in A's dtype, L (d x d)
     float64, all column-major, with d = min(k + p, m, n).
     """
@@ -477,7 +479,8 @@ def gemm(A, X, trans_a, precision=None):
     """C = A^T X (trans_a) or A X, on the sketch-product kernels.
 
     precision: None (from the dtype), or "bf16" / "f16" for the precision-form
-    kernel (A, X float32, rounded to 16 bits inside; C float32)."""
+    kernel (A, X float32, rounded to 16 bits inside; C float32), or "bf16x3"
+    for the split bf16 product (rounded parts and residuals, three terms)."""
     A = colmajor(A)
     X = colmajor(X)
     m, n = A.shape

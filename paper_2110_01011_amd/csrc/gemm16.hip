@@ -30,6 +30,13 @@ namespace {
 // L2); the linear workgroup id is remapped so that each XCD works through a
 // contiguous range of (row tile, column tile, split) items with the row tile
 // fastest: the panel chunk of one (column tile, split) then stays in one L2.
+//
+// Split bf16 product (A2, B2 given): with A = A16 + A2 and X = B16 + B2 split
+// into a rounded part and its rounding residual (both bf16), the splits
+// come in three segments of seg_splits each, A16 B16, A16 B2 and A2 B16,
+// whose partial sums the fixed-order reduction adds: the three-term bf16
+// product that approximates the fp32 one (the A2 B2 term is below the
+// rounding of the other three).
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8_t __attribute__((ext_vector_type(8)));
 
@@ -77,7 +84,8 @@ template <typename T16, int WN>
 __global__ __launch_bounds__(64 * k16Waves, 2) void gemm16_kernel(
     const T16* __restrict__ A, int64_t lda, const T16* __restrict__ B, int64_t ldb,
     float* __restrict__ C, int64_t ldc, int64_t strideS, int64_t M, int64_t N, int64_t Kp,
-    int64_t kchunk, int tiles_m, int tiles_n) {
+    int64_t kchunk, int tiles_m, int tiles_n, const T16* __restrict__ A2,
+    const T16* __restrict__ B2, int seg_splits) {
   constexpr int NT = 64 * k16Waves;
   constexpr int WM = 2, BK = k16BK, LK = BK + 8, CH = BK / 8;
   constexpr int BN = 16 * WN;
@@ -90,8 +98,11 @@ __global__ __launch_bounds__(64 * k16Waves, 2) void gemm16_kernel(
   const int tile_m = (int)(w % tiles_m);
   const int tile_n = (int)((w / tiles_m) % tiles_n);
   const int split = (int)(w / ((int64_t)tiles_m * tiles_n));
+  const int seg = split / seg_splits;  // 0: A B, 1: A B2, 2: A2 B
+  if (seg == 2) A = A2;
+  if (seg == 1) B = B2;
   const int64_t i0 = (int64_t)tile_m * k16BM, j0 = (int64_t)tile_n * BN;
-  const int64_t kbeg = (int64_t)split * kchunk;
+  const int64_t kbeg = (int64_t)(split - seg * seg_splits) * kchunk;
   const int64_t kend = (kbeg + kchunk < Kp) ? kbeg + kchunk : Kp;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int grp = lane >> 4, r16 = lane & 15;
@@ -190,17 +201,22 @@ __global__ __launch_bounds__(64 * k16Waves, 2) void gemm16_kernel(
 }
 
 // X (rows x d fp32, ldx) -> X16 (rows x d, ldy), rounded to nearest even;
-// rows [rows, ldy) of X16 are set to zero (contraction padding).
+// rows [rows, ldy) of X16 are set to zero (contraction padding).  If Ylo is
+// given it receives the rounded residual x - x16 (exact in fp32) the same way.
 template <typename T16>
 __global__ __launch_bounds__(256) void convert_panel16_kernel(const float* __restrict__ X,
                                                               int64_t rows, int64_t d,
                                                               int64_t ldx, T16* __restrict__ Y,
-                                                              int64_t ldy) {
+                                                              int64_t ldy,
+                                                              T16* __restrict__ Ylo) {
   const int64_t total = ldy * d;
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = idx % ldy, j = idx / ldy;
-    Y[idx] = i < rows ? to16(X[i + j * ldx], (T16*)nullptr) : (T16)0.0f;
+    const float x = i < rows ? X[i + j * ldx] : 0.0f;
+    const T16 hi = to16(x, (T16*)nullptr);
+    Y[idx] = hi;
+    if (Ylo) Ylo[idx] = to16(x - (float)hi, (T16*)nullptr);
   }
 }
 
@@ -211,35 +227,48 @@ __global__ __launch_bounds__(256) void convert_panel16_kernel(const float* __res
 // the transposed writes coalesced; the grid covers exactly the padded sizes.
 // If rerr is given, each workgroup also writes the sum of squared rounding
 // errors (a - a16)^2 of its tile (fp64) to rerr[its linear index] and the
-// tile's sum of squares a^2 to rerr[nblocks + its linear index].
+// tile's sum of squares a^2 to rerr[nblocks + its linear index].  A16lo /
+// At16lo, if given, receive the rounded residual a - a16 (exact in fp32) in
+// the layout of A16 / At16.
 template <typename T16>
 __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict__ A, int64_t m,
                                                         int64_t n, int64_t lda,
                                                         T16* __restrict__ A16, int64_t ld16,
                                                         T16* __restrict__ At16, int64_t ldt16,
-                                                        double* __restrict__ rerr) {
+                                                        double* __restrict__ rerr,
+                                                        T16* __restrict__ A16lo,
+                                                        T16* __restrict__ At16lo) {
   __shared__ T16 tile[64][66];
+  __shared__ T16 tlo[64][66];
   __shared__ double red[256];
   const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   double err = 0.0, nrm = 0.0;
   for (int jj = ty; jj < 64; jj += 4) {
     const int64_t i = i0 + tx, j = j0 + jj;
-    T16 v = (T16)0.0f;
+    T16 v = (T16)0.0f, vl = (T16)0.0f;
     if (i < m && j < n) {
       const float a = A[i + j * lda];
       v = to16(a, (T16*)nullptr);
+      vl = to16(a - (float)v, (T16*)nullptr);
       const double e = (double)a - (double)(float)v;
       err += e * e;
       nrm += (double)a * (double)a;
     }
-    if (j < n) A16[i + j * ld16] = v;  // i < ld16 always
+    if (j < n) {  // i < ld16 always
+      A16[i + j * ld16] = v;
+      if (A16lo) A16lo[i + j * ld16] = vl;
+    }
     tile[jj][tx] = v;
+    tlo[jj][tx] = vl;
   }
   __syncthreads();
   for (int ii = ty; ii < 64; ii += 4) {
     const int64_t j = j0 + tx, i = i0 + ii;
-    if (i < m) At16[j + i * ldt16] = tile[tx][ii];  // j < ldt16 always
+    if (i < m) {  // j < ldt16 always
+      At16[j + i * ldt16] = tile[tx][ii];
+      if (At16lo) At16lo[j + i * ldt16] = tlo[tx][ii];
+    }
   }
   if (rerr) {
     const int64_t nb = (int64_t)gridDim.x * gridDim.y;
@@ -262,7 +291,8 @@ __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict_
 // Precision-form plan: k16BM-row tiles, N covered by as few tiles of at most
 // 16 k16MaxWN columns as possible (A is read once per N tile), split-K up to
 // ~1024 workgroups with at least four whole tiles per split.  Kp is the
-// padded contraction length (a multiple of k16BK).
+// padded contraction length (a multiple of k16BK).  nseg = 3 plans the split
+// bf16 product: splits is then per segment.
 struct Plan16 {
   int wn;
   int64_t tiles_m, tiles_n;
@@ -286,7 +316,7 @@ int gemm16_occupancy_wn(int wn) {
   return gemm16_occupancy<T16, WN>();
 }
 
-Plan16 make_plan16(int64_t M, int64_t N, int64_t K, bool f16) {
+Plan16 make_plan16(int64_t M, int64_t N, int64_t K, bool f16, int nseg) {
   Plan16 p;
   const int64_t Kp = pad16(K);
   const int64_t nblk = (N + 15) / 16;
@@ -297,49 +327,54 @@ Plan16 make_plan16(int64_t M, int64_t N, int64_t K, bool f16) {
   const int64_t max_s = std::max<int64_t>(1, Kp / (4 * k16BK));
   const int occ = f16 ? gemm16_occupancy_wn<_Float16, k16MaxWN>(p.wn)
                       : gemm16_occupancy_wn<__bf16, k16MaxWN>(p.wn);
-  choose_splits(tiles, Kp, k16BK, max_s, (int64_t)occ * cu_count(), 2.0 * k16BM * 16 * p.wn,
+  choose_splits(tiles * nseg, Kp, k16BK, max_s, (int64_t)occ * cu_count(), 2.0 * k16BM * 16 * p.wn,
                 900e12, 4.0 * (double)M * (double)N, &p.kchunk, &p.splits);
   return p;
 }
 
 template <typename T16, int WN>
-static void run_gemm16(const Gemm16Args& g, const Plan16& p, float* dst, int64_t lddst,
-                       int64_t strideS, hipStream_t st) {
-  const unsigned T = (unsigned)(p.tiles_m * p.tiles_n * p.splits);
+static void run_gemm16(const Gemm16Args& g, const Plan16& p, int nseg, float* dst,
+                       int64_t lddst, int64_t strideS, hipStream_t st) {
+  const unsigned T = (unsigned)(p.tiles_m * p.tiles_n * p.splits * nseg);
   hipLaunchKernelGGL((gemm16_kernel<T16, WN>), dim3(T), dim3(64 * k16Waves), 0, st,
                      (const T16*)g.A, g.lda, (const T16*)g.B, g.ldb, dst, lddst, strideS, g.M,
-                     g.N, pad16(g.K), p.kchunk, (int)p.tiles_m, (int)p.tiles_n);
+                     g.N, pad16(g.K), p.kchunk, (int)p.tiles_m, (int)p.tiles_n,
+                     (const T16*)g.A2, (const T16*)g.B2, p.splits);
 }
 
 template <typename T16, int WN>
-static void dispatch16(const Gemm16Args& g, const Plan16& p, float* dst, int64_t lddst,
-                       int64_t strideS, hipStream_t st) {
+static void dispatch16(const Gemm16Args& g, const Plan16& p, int nseg, float* dst,
+                       int64_t lddst, int64_t strideS, hipStream_t st) {
   if constexpr (WN > 1) {
-    if (p.wn < WN) return dispatch16<T16, WN - 1>(g, p, dst, lddst, strideS, st);
+    if (p.wn < WN) return dispatch16<T16, WN - 1>(g, p, nseg, dst, lddst, strideS, st);
   }
-  run_gemm16<T16, WN>(g, p, dst, lddst, strideS, st);
+  run_gemm16<T16, WN>(g, p, nseg, dst, lddst, strideS, st);
 }
 
 template <typename T16>
 static hipError_t gemm16_typed(const Gemm16Args& g, hipStream_t st) {
-  const Plan16 p = make_plan16(g.M, g.N, g.K, g.f16);
-  const bool direct = (p.splits == 1);
+  const int nseg = g.A2 ? 3 : 1;
+  const Plan16 p = make_plan16(g.M, g.N, g.K, g.f16, nseg);
+  const int slabs = p.splits * nseg;
+  const bool direct = (slabs == 1);
   float* dst = direct ? g.C : (float*)g.partial;
   const int64_t lddst = direct ? g.ldc : g.M;
   const int64_t strideS = g.M * g.N;
   if (!direct && (g.partial == nullptr ||
-                  g.partial_bytes < (size_t)p.splits * (size_t)strideS * sizeof(float)))
+                  g.partial_bytes < (size_t)slabs * (size_t)strideS * sizeof(float)))
     return hipErrorInvalidValue;
-  // whole 16-byte fragment loads over the zero-padded contraction
+  // whole 16-byte fragment loads over the zero-padded contraction; the
+  // residual copies share the leading dimensions of A and B
   if (g.lda < pad16(g.K) || g.ldb < pad16(g.K) || (g.lda % 8) != 0 || (g.ldb % 8) != 0 ||
-      (((uintptr_t)g.A | (uintptr_t)g.B) & 15) != 0)
+      (((uintptr_t)g.A | (uintptr_t)g.B | (uintptr_t)g.A2 | (uintptr_t)g.B2) & 15) != 0 ||
+      ((g.A2 == nullptr) != (g.B2 == nullptr)) || (g.A2 && g.f16))
     return hipErrorInvalidValue;
   if (g.ev_begin) (void)hipEventRecord((hipEvent_t)g.ev_begin, st);
-  dispatch16<T16, k16MaxWN>(g, p, dst, lddst, strideS, st);
+  dispatch16<T16, k16MaxWN>(g, p, nseg, dst, lddst, strideS, st);
   if (g.ev_end) (void)hipEventRecord((hipEvent_t)g.ev_end, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || direct) return e;
-  return launch_splitk_reduce_f32((const float*)g.partial, g.M, g.N, p.splits, g.C, g.ldc, st);
+  return launch_splitk_reduce_f32((const float*)g.partial, g.M, g.N, slabs, g.C, g.ldc, st);
 }
 
 hipError_t launch_gemm16(const Gemm16Args& g, hipStream_t st) {
@@ -347,25 +382,26 @@ hipError_t launch_gemm16(const Gemm16Args& g, hipStream_t st) {
   return g.f16 ? gemm16_typed<_Float16>(g, st) : gemm16_typed<__bf16>(g, st);
 }
 
-size_t gemm16_partial_bytes(int64_t M, int64_t N, int64_t K, bool f16) {
-  const Plan16 p = make_plan16(M, N, K, f16);
-  return p.splits == 1 ? 0 : (size_t)p.splits * (size_t)M * (size_t)N * 4;
+size_t gemm16_partial_bytes(int64_t M, int64_t N, int64_t K, bool f16, int nseg) {
+  const Plan16 p = make_plan16(M, N, K, f16, nseg);
+  const int slabs = p.splits * nseg;
+  return slabs == 1 ? 0 : (size_t)slabs * (size_t)M * (size_t)N * 4;
 }
 
 int64_t gemm16_ld(int64_t K) { return pad16(K); }
 
 hipError_t launch_convert_panel16(const float* X, int64_t rows, int64_t d, int64_t ldx, void* Y,
-                                  int64_t ldy, bool f16, hipStream_t st) {
+                                  int64_t ldy, bool f16, hipStream_t st, void* Ylo) {
   if (rows <= 0 || d <= 0) return hipSuccess;
   if (ldy < pad16(rows) || ldy % k16BK != 0) return hipErrorInvalidValue;
   const int64_t total = ldy * d;
   const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
   if (f16)
     hipLaunchKernelGGL(convert_panel16_kernel<_Float16>, dim3(blocks), dim3(256), 0, st, X, rows,
-                       d, ldx, (_Float16*)Y, ldy);
+                       d, ldx, (_Float16*)Y, ldy, (_Float16*)Ylo);
   else
     hipLaunchKernelGGL(convert_panel16_kernel<__bf16>, dim3(blocks), dim3(256), 0, st, X, rows, d,
-                       ldx, (__bf16*)Y, ldy);
+                       ldx, (__bf16*)Y, ldy, (__bf16*)Ylo);
   return hipGetLastError();
 }
 
@@ -373,16 +409,18 @@ int64_t convert16_blocks(int64_t m, int64_t n) { return ((m + 63) / 64) * ((n + 
 
 hipError_t launch_convert16(const float* A, int64_t m, int64_t n, int64_t lda, void* A16,
                             int64_t ld16, void* At16, int64_t ldt16, bool f16, hipStream_t st,
-                            double* rerr) {
+                            double* rerr, void* A16lo, void* At16lo) {
   if (m <= 0 || n <= 0) return hipSuccess;
   if (ld16 < pad16(m) || ldt16 < pad16(n)) return hipErrorInvalidValue;
   dim3 grid((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64));
   if (f16)
     hipLaunchKernelGGL(convert16_kernel<_Float16>, grid, dim3(256), 0, st, A, m, n, lda,
-                       (_Float16*)A16, ld16, (_Float16*)At16, ldt16, rerr);
+                       (_Float16*)A16, ld16, (_Float16*)At16, ldt16, rerr, (_Float16*)A16lo,
+                       (_Float16*)At16lo);
   else
     hipLaunchKernelGGL(convert16_kernel<__bf16>, grid, dim3(256), 0, st, A, m, n, lda,
-                       (__bf16*)A16, ld16, (__bf16*)At16, ldt16, rerr);
+                       (__bf16*)A16, ld16, (__bf16*)At16, ldt16, rerr, (__bf16*)A16lo,
+                       (__bf16*)At16lo);
   return hipGetLastError();
 }
 

@@ -86,7 +86,7 @@ constexpr double kJudgeSlack = 0.0404;
 
 struct Layout {
   size_t m1, m2, n1, n2, part, part_bytes, G, R[4], Racc[2], Rfin, dinv, colf, scal, flags,
-      chs, tsub, tsr, a16, at16, p16, total;
+      chs, tsub, tsr, a16, at16, p16, a16lo, p16lo, total;
   int64_t ld16, ldt16;  // leading dimensions of the 16-bit copies of A and A^T
   int64_t ldp16;        // leading dimension of the 16-bit copy of a panel
   // predictor and error judge (randqlp_factor_auto only)
@@ -97,8 +97,10 @@ struct Layout {
 
 size_t elem_size(Dtype dt) { return dt == DT_F64 ? 8 : 4; }
 
+// mixed: 16-bit copies of A for the sketch and power products; split: also
+// the bf16 residual of A and of the panel for the split final projection.
 Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false,
-                   bool autoq = false) {
+                   bool autoq = false, bool split = false) {
   Layout L;
   const size_t es = elem_size(dt);
   size_t off = 0;
@@ -128,6 +130,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
       part = std::max(part, gemm16_partial_bytes(n, d, m, f16));
       part = std::max(part, gemm16_partial_bytes(m, d, n, f16));
     }
+    if (split) part = std::max(part, gemm16_partial_bytes(n, d, m, false, 3));
   }
   size_t part2 = 0;
   if (autoq) {
@@ -166,6 +169,12 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
     L.ld16 = L.ldt16 = L.ldp16 = 0;
     L.a16 = L.at16 = L.p16 = 0;
   }
+  if (mixed && split) {
+    L.a16lo = take((size_t)L.ld16 * n * 2);
+    L.p16lo = take((size_t)L.ldp16 * d * 2);
+  } else {
+    L.a16lo = L.p16lo = 0;
+  }
   if (autoq) {
     L.y64 = take((size_t)n * kPredCols * es);
     L.g64 = take((size_t)kPredCols * kPredCols * 8);
@@ -197,7 +206,7 @@ WsCache g_ws;
 struct Ctx {
   hipStream_t st;
   Dtype dt;
-  int mixed = 0;  // 0: no; 1: bf16 products; 2: fp16 products
+  int mixed = 0;  // 0: no; 1: bf16 products; 2: fp16 products; 3: bf16 + split projection
   char* ws;
   Layout lay;
   int64_t d;
@@ -276,8 +285,10 @@ hipError_t gemm(Ctx& c, int trans_a, const void* A, int64_t lda, const void* B, 
 // Precision-form product C (rows x d, fp32) = op(A) X on the 16-bit copies:
 // trans_a = 1 uses A16 (C = A^T X, rows = n, K = m), trans_a = 0 uses the
 // copy of A^T (C = A X, rows = m, K = n).  X is rounded to 16 bits first.
+// split (trans_a = 1, bf16): the three-term product with the residuals of A
+// and X, which approximates the fp32 product.
 hipError_t gemm16(Ctx& c, int trans_a, int64_t m, int64_t n, const float* X, int64_t ldx,
-                  float* C, int64_t ldc, int64_t d) {
+                  float* C, int64_t ldc, int64_t d, bool split = false) {
   Gemm16Args g;
   g.f16 = (c.mixed == 2);
   g.A = trans_a ? (const void*)(c.ws + c.lay.a16) : (const void*)(c.ws + c.lay.at16);
@@ -291,7 +302,13 @@ hipError_t gemm16(Ctx& c, int trans_a, int64_t m, int64_t n, const float* X, int
   g.K = trans_a ? m : n;
   g.partial = c.ws + c.lay.part;
   g.partial_bytes = c.lay.part_bytes;
-  hipError_t e = launch_convert_panel16(X, g.K, d, ldx, c.ws + c.lay.p16, c.lay.ldp16, g.f16, c.st);
+  if (split) {
+    if (!trans_a || g.f16 || !c.lay.a16lo) return hipErrorInvalidValue;
+    g.A2 = c.ws + c.lay.a16lo;
+    g.B2 = c.ws + c.lay.p16lo;
+  }
+  hipError_t e = launch_convert_panel16(X, g.K, d, ldx, c.ws + c.lay.p16, c.lay.ldp16, g.f16, c.st,
+                                        split ? c.ws + c.lay.p16lo : nullptr);
   if (e != hipSuccess) return e;
   if (g_prof.on) {
     const size_t i = g_prof.used++;
@@ -481,13 +498,15 @@ struct FactorArgs {
 };
 
 // A product of the power iteration with A: C (rows x d) = op(A) X.  The
-// precision form runs it on the 16-bit copies; `full` forces the input
-// precision (the final projection and the error judge's product).
+// precision form runs it on the 16-bit copies; `full` (the final projection)
+// asks for fp32 accuracy: the fp32 product, or the split bf16 product.
 hipError_t prod(Ctx& c, const FactorArgs& f, int trans_a, const void* X, int64_t ldx, void* C,
                 int64_t ldc, bool full = false) {
   const int64_t rows = trans_a ? f.n : f.m, K = trans_a ? f.m : f.n;
   if (c.mixed && !full)
     return gemm16(c, trans_a, f.m, f.n, (const float*)X, ldx, (float*)C, ldc, c.d);
+  if (c.mixed == 3 && trans_a)
+    return gemm16(c, 1, f.m, f.n, (const float*)X, ldx, (float*)C, ldc, c.d, true);
   return gemm(c, trans_a, f.A, f.lda, X, ldx, C, ldc, rows, c.d, K, c.dt, c.dt, false, true);
 }
 
@@ -507,7 +526,8 @@ hipError_t stage_sketch(Ctx& c, const FactorArgs& f, PanelMode mode) {
   if (c.mixed)
     HIP_TRY(launch_convert16((const float*)f.A, m, n, f.lda, c.ws + c.lay.a16, c.lay.ld16,
                              c.ws + c.lay.at16, c.lay.ldt16, c.mixed == 2, c.st,
-                             c.lay.rerr ? c.at<double>(c.lay.rerr) : nullptr));
+                             c.lay.rerr ? c.at<double>(c.lay.rerr) : nullptr,
+                             c.lay.a16lo ? c.ws + c.lay.a16lo : nullptr));
   HIP_TRY(prod(c, f, 1, Zm, m, Yn, n));                                        // A^T Omega
   return orth(c, Yn, n, n, Yn, n, Tn, nullptr, mode, false);                   // Qbar
 }
@@ -613,8 +633,10 @@ size_t randqlp_workspace_size(int64_t m, int64_t n, int k, int p, int q, const r
   const int64_t d = randqlp_sketch_width(m, n, k, p);
   if (d < 1 || q < 0) return 0;
   const int prec = o ? o->precision : RQLP_F64;
-  if (prec < RQLP_F64 || prec > RQLP_MIXED_F16) return 0;
-  return make_layout(m, n, d, prec == RQLP_F64 ? DT_F64 : DT_F32, prec >= RQLP_MIXED_BF16).total;
+  if (prec < RQLP_F64 || prec > RQLP_MIXED_BF16X3) return 0;
+  return make_layout(m, n, d, prec == RQLP_F64 ? DT_F64 : DT_F32, prec >= RQLP_MIXED_BF16, false,
+                     prec == RQLP_MIXED_BF16X3)
+      .total;
 }
 
 }  // extern "C"
@@ -678,7 +700,7 @@ rqlp_status setup_factor(const void* A, int64_t m, int64_t n, int k, int p, int 
   if (p < 0) return fail(RQLP_E_INVALID_ARG, "p = %d must be >= 0", p);
   if (q < 0) return fail(RQLP_E_INVALID_ARG, "q = %d must be >= 0", q);
   if (!A || !Q || !L || !P) return fail(RQLP_E_INVALID_ARG, "null matrix pointer");
-  if (o.precision < RQLP_F64 || o.precision > RQLP_MIXED_F16)
+  if (o.precision < RQLP_F64 || o.precision > RQLP_MIXED_BF16X3)
     return fail(RQLP_E_INVALID_ARG, "unknown precision %d", o.precision);
   if (o.panel_qr < RQLP_PANEL_AUTO || o.panel_qr > RQLP_PANEL_ROBUST)
     return fail(RQLP_E_INVALID_ARG, "unknown panel_qr %d", o.panel_qr);
@@ -690,11 +712,14 @@ rqlp_status setup_factor(const void* A, int64_t m, int64_t n, int k, int p, int 
   if (d > RQLP_MAX_D)
     return fail(RQLP_E_UNSUPPORTED, "sketch width d = %lld exceeds %d", (long long)d, RQLP_MAX_D);
   const Dtype dt = (o.precision == RQLP_F64) ? DT_F64 : DT_F32;
-  const int mixed = (o.precision == RQLP_MIXED_BF16) ? 1 : (o.precision == RQLP_MIXED_F16) ? 2 : 0;
+  const int mixed = (o.precision == RQLP_MIXED_BF16)     ? 1
+                    : (o.precision == RQLP_MIXED_F16)   ? 2
+                    : (o.precision == RQLP_MIXED_BF16X3) ? 3
+                                                        : 0;
   c.st = (hipStream_t)o.stream;
   c.dt = dt;
   c.mixed = mixed;
-  c.lay = make_layout(m, n, d, dt, mixed != 0, autoq);
+  c.lay = make_layout(m, n, d, dt, mixed != 0, autoq, mixed == 3);
   c.d = d;
   c.seed = seed;
   c.orth_calls = 0;
@@ -1186,7 +1211,7 @@ rqlp_status randqlp_gemm(int trans_a, const void* A, int64_t m, int64_t n, int64
     return fail(RQLP_E_INVALID_ARG, "bad size, pointer or leading dimension");
   const int64_t rows = trans_a ? n : m, K = trans_a ? m : n;
   if (ldx < K || ldc < rows) return fail(RQLP_E_INVALID_ARG, "bad leading dimension");
-  if (precision < RQLP_F64 || precision > RQLP_MIXED_F16)
+  if (precision < RQLP_F64 || precision > RQLP_MIXED_BF16X3)
     return fail(RQLP_E_INVALID_ARG, "unknown precision %d", precision);
   const hipStream_t st = (hipStream_t)stream;
   rqlp_opts o;
@@ -1197,17 +1222,26 @@ rqlp_status randqlp_gemm(int trans_a, const void* A, int64_t m, int64_t n, int64
   if (precision >= RQLP_MIXED_BF16) {
     // 16-bit copies of op(A) (contraction-contiguous) and of X, then the
     // precision-form product kernel.
+    // RQLP_MIXED_BF16X3: the split product, with the residual copies of
+    // op(A) and X after the rounded ones.
     const bool f16 = precision == RQLP_MIXED_F16;
+    const bool split = precision == RQLP_MIXED_BF16X3;
     const int64_t ld16 = gemm16_ld(m), ldt16 = gemm16_ld(n), ldx16 = gemm16_ld(K);
-    const size_t part = gemm16_partial_bytes(rows, d, K, f16);
+    const size_t part = gemm16_partial_bytes(rows, d, K, f16, split ? 3 : 1);
+    const size_t bytes_op = trans_a ? (size_t)ld16 * n * 2 : (size_t)ldt16 * m * 2;
     const size_t off_a = 0, off_at = align_up((size_t)ld16 * n * 2);
     const size_t off_x = off_at + align_up((size_t)ldt16 * m * 2);
-    const size_t off_p = off_x + align_up((size_t)ldx16 * d * 2);
+    const size_t off_alo = off_x + align_up((size_t)ldx16 * d * 2);
+    const size_t off_xlo = off_alo + (split ? align_up(bytes_op) : 0);
+    const size_t off_p = off_xlo + (split ? align_up((size_t)ldx16 * d * 2) : 0);
     rqlp_status s = acquire_ws(o, off_p + std::max<size_t>(part, 256), &ws, lk);
     if (s != RQLP_OK) return s;
-    e = launch_convert16((const float*)A, m, n, lda, ws + off_a, ld16, ws + off_at, ldt16, f16, st);
+    e = launch_convert16((const float*)A, m, n, lda, ws + off_a, ld16, ws + off_at, ldt16, f16, st,
+                         nullptr, (split && trans_a) ? ws + off_alo : nullptr,
+                         (split && !trans_a) ? ws + off_alo : nullptr);
     if (e == hipSuccess)
-      e = launch_convert_panel16((const float*)X, K, d, ldx, ws + off_x, ldx16, f16, st);
+      e = launch_convert_panel16((const float*)X, K, d, ldx, ws + off_x, ldx16, f16, st,
+                                 split ? ws + off_xlo : nullptr);
     if (e == hipSuccess) {
       Gemm16Args g;
       g.f16 = f16;
@@ -1222,6 +1256,10 @@ rqlp_status randqlp_gemm(int trans_a, const void* A, int64_t m, int64_t n, int64
       g.K = K;
       g.partial = ws + off_p;
       g.partial_bytes = part;
+      if (split) {
+        g.A2 = ws + off_alo;
+        g.B2 = ws + off_xlo;
+      }
       e = launch_gemm16(g, st);
     }
   } else {

@@ -74,11 +74,15 @@ size_t gemm_partial_bytes(int trans_a, int64_t M, int64_t N, int64_t K, Dtype in
 // Precision form: C (M x N fp32) = A16^T X, A16 a 16-bit matrix with the
 // contraction index contiguous (A16[k + i*lda]), X fp32 (X[k + j*ldb]) rounded
 // to 16 bits on load; split-K partials in `partial` (fixed-order reduction).
+// With A2 and B2 (bf16 only): the rounding residuals of A and X in the layouts
+// of A and B, and C = A16^T B16 + A16^T B2 + A2^T B16 (split bf16 product).
 struct Gemm16Args {
   bool f16;  // false: bf16, true: fp16
   const void* A; int64_t lda;  // 16-bit, contraction-contiguous, lda % 8 == 0
   const void* B; int64_t ldb;  // 16-bit panel, contraction-contiguous, ldb % 8 == 0
   float* C; int64_t ldc;
+  const void* A2 = nullptr;  // residual of A (lda), or null
+  const void* B2 = nullptr;  // residual of the panel (ldb), or null
   int64_t M, N, K;
   void* partial;
   size_t partial_bytes;
@@ -86,22 +90,25 @@ struct Gemm16Args {
   void* ev_end = nullptr;
 };
 hipError_t launch_gemm16(const Gemm16Args& g, hipStream_t st);
-size_t gemm16_partial_bytes(int64_t M, int64_t N, int64_t K, bool f16);
+size_t gemm16_partial_bytes(int64_t M, int64_t N, int64_t K, bool f16, int nseg = 1);
 // Leading dimension of a 16-bit operand with contraction length K: K rounded
 // up to the kernel's tile depth; the padding must hold zeros.
 int64_t gemm16_ld(int64_t K);
 // X (rows x d fp32, ldx) -> Y (rows x d, 16-bit, ldy), nearest even; ldy a
 // multiple of the tile depth >= gemm16_ld(rows); rows [rows, ldy) zeroed.
+// Ylo (optional, same layout): the rounded residual x - y.
 hipError_t launch_convert_panel16(const float* X, int64_t rows, int64_t d, int64_t ldx, void* Y,
-                                  int64_t ldy, bool f16, hipStream_t st);
+                                  int64_t ldy, bool f16, hipStream_t st, void* Ylo = nullptr);
 // A (m x n fp32) -> A16 (m x n, ld16) and At16 = A^T (n x m, ldt16), 16-bit,
 // with ld16 >= gemm16_ld(m), ldt16 >= gemm16_ld(n) and zero padding rows.
 // rerr (optional): per-workgroup sums of the squared rounding errors, one
 // double for each of the nb = convert16_blocks(m, n) workgroups, followed by
-// the nb per-workgroup sums of squares of A (2 nb doubles in all).
+// the nb per-workgroup sums of squares of A (2 nb doubles in all).  A16lo /
+// At16lo (optional): the rounded residuals a - a16 in the layouts of A16 / At16.
 hipError_t launch_convert16(const float* A, int64_t m, int64_t n, int64_t lda, void* A16,
                             int64_t ld16, void* At16, int64_t ldt16, bool f16, hipStream_t st,
-                            double* rerr = nullptr);
+                            double* rerr = nullptr, void* A16lo = nullptr,
+                            void* At16lo = nullptr);
 int64_t convert16_blocks(int64_t m, int64_t n);
 
 // ---- panel.hip ----

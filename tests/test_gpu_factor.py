@@ -163,7 +163,7 @@ def test_wide_sketch_blocked_cholesky_parity(rq, exp_decay_matrix):
     _check_f64(rq, A, 500, 20, 2, seed=1)
 
 
-@pytest.mark.parametrize("precision", ["bf16", "f16"])
+@pytest.mark.parametrize("precision", ["bf16", "f16", "bf16x3"])
 def test_precision_form_error_within_5_percent(rq, exp_decay_matrix, precision):
     import torch
     log(f"factor exp-decay 5000x4000 d=520 precision={precision}")

@@ -102,6 +102,38 @@ def test_gemm16_within_rounding_bound(rq, m, n, d, trans, precision):
     assert np.all(np.abs(C - ref) <= bound)
 
 
+@pytest.mark.parametrize("m,n,d", [(1000, 700, 25), (333, 517, 210), (5, 7, 3), (2100, 1500, 520),
+                                   (777, 901, 273)])
+@pytest.mark.parametrize("trans", [1, 0])
+def test_gemm16_split_product(rq, m, n, d, trans):
+    """Split bf16 product: A = A1 + A2, X = X1 + X2 with A1, X1 rounded to bf16
+    and A2, X2 the rounded residuals; C = A1 X1 + A1 X2 + A2 X1 (each bf16
+    product exact in fp32), so |C - ref3| <= 2 (3K + 2) u32 sum of |terms|.
+    Against the exact product the three terms leave about 2^-16 relative, far
+    below the plain bf16 product's 2^-9: a dropped term fails the second check."""
+    import torch
+    log(f"gemm16 split trans={trans} m={m} n={n} d={d}")
+    r = np.random.default_rng(m * 7 + n + d)
+    A = np.asfortranarray(r.standard_normal((m, n)).astype(np.float32))
+    X = r.standard_normal((m if trans else n, d)).astype(np.float32)
+    C = to_np(rq.gemm(to_dev(A, torch.float32), to_dev(X, torch.float32), trans,
+                      precision="bf16x3"))
+    A1, X1 = _round16(A, "bf16"), _round16(X, "bf16")
+    A2 = _round16((A.astype(np.float64) - A1).astype(np.float32), "bf16")
+    X2 = _round16((X.astype(np.float64) - X1).astype(np.float32), "bf16")
+    op = (lambda M: M.T) if trans else (lambda M: M)
+    ref3 = op(A1) @ X1 + op(A1) @ X2 + op(A2) @ X1
+    K = op(A).shape[1]
+    absum = np.abs(op(A1)) @ np.abs(X1) + np.abs(op(A1)) @ np.abs(X2) + np.abs(op(A2)) @ np.abs(X1)
+    assert C.shape == ref3.shape
+    assert np.all(np.abs(C - ref3) <= 2 * (3 * K + 2) * U32 * absum)
+    exact = op(A.astype(np.float64)) @ X.astype(np.float64)
+    err3 = np.linalg.norm(C - exact)
+    err1 = np.linalg.norm(op(A1) @ X1 - exact)
+    assert err3 <= 1e-4 * np.linalg.norm(exact)
+    assert err3 * 30 <= err1
+
+
 def _panel(rows, d, kappa, seed):
     r = np.random.default_rng(seed)
     U, _ = np.linalg.qr(r.standard_normal((rows, d)))
