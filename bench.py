@@ -344,10 +344,13 @@ def main():
     log(f"timing {args.steps} steps")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    marks = [t0]
     for i in range(args.steps):
-        Q, L, P = rq.factor(Ad, k, p, q, seed=0)
+        Q, L, P = rq.factor(Ad, k, p, q, seed=0)  # returns after the call's stream is done
+        marks.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    step_ms = np.diff(np.array(marks)) * 1e3
     rq.profile_enable(False)
     kms, launches, kflops, kbytes = rq.profile_read()
     ms = (t1 - t0) * 1e3 / args.steps
@@ -388,6 +391,12 @@ def main():
                    "m": m, "n": n, "k": k, "p": p, "q": q, "d": d,
                    "flops_per_step": flops},
         "roofline": roofline,
+        "step_ms": {"median": round(float(np.median(step_ms)), 4),
+                    "min": round(float(step_ms.min()), 4), "max": round(float(step_ms.max()), 4)},
+        # whole step against the flop model at the published peak: sum of
+        # t_roof over the step's work / measured time per step
+        "step_roofline": {"roof_ms": round(flops / (peak * 1e12) * 1e3, 4),
+                          "frac": round(flops / (peak * 1e12) / (ms * 1e-3), 4)},
         "cpu_baseline": cpu,
         "error": {"e_gpu": e_gpu, "e_oracle": e_orc,
                   "ratio": (e_gpu / e_orc) if e_orc else None},

@@ -225,6 +225,9 @@ __global__ __launch_bounds__(256) void convert_panel16_kernel(const float* __res
 // to multiples of 64; the padding rows of both copies are written as zeros
 // (the contraction padding of gemm16_kernel).  64 x 64 tiles through LDS keep
 // the transposed writes coalesced; the grid covers exactly the padded sizes.
+// Each thread takes two adjacent elements, so every 16-bit store is a 4-byte
+// pair (the even leading dimensions keep pairs aligned), and the fp32 loads
+// are 8-byte pairs when A's address and lda allow.
 // If rerr is given, each workgroup also writes the sum of squared rounding
 // errors (a - a16)^2 of its tile (fp64) to rerr[its linear index] and the
 // tile's sum of squares a^2 to rerr[nblocks + its linear index].  A16lo /
@@ -238,36 +241,53 @@ __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict_
                                                         double* __restrict__ rerr,
                                                         T16* __restrict__ A16lo,
                                                         T16* __restrict__ At16lo) {
+  typedef T16 pair_t __attribute__((ext_vector_type(2)));
   __shared__ T16 tile[64][66];
   __shared__ T16 tlo[64][66];
   __shared__ double red[256];
   const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  const bool pairs = ((((uintptr_t)A) & 7) == 0) && ((lda & 1) == 0);
   double err = 0.0, nrm = 0.0;
-  for (int jj = ty; jj < 64; jj += 4) {
-    const int64_t i = i0 + tx, j = j0 + jj;
-    T16 v = (T16)0.0f, vl = (T16)0.0f;
-    if (i < m && j < n) {
-      const float a = A[i + j * lda];
-      v = to16(a, (T16*)nullptr);
-      vl = to16(a - (float)v, (T16*)nullptr);
-      const double e = (double)a - (double)(float)v;
+  for (int jj = ty; jj < 64; jj += 8) {
+    const int64_t i = i0 + 2 * tx, j = j0 + jj;
+    float a[2] = {0.0f, 0.0f};
+    if (j < n) {
+      const float* src = A + i + j * lda;
+      if (pairs && i + 1 < m) {
+        const float2 t = *(const float2*)src;
+        a[0] = t.x;
+        a[1] = t.y;
+      } else {
+        if (i < m) a[0] = src[0];
+        if (i + 1 < m) a[1] = src[1];
+      }
+    }
+    T16 v[2], vl[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      v[u] = to16(a[u], (T16*)nullptr);
+      vl[u] = to16(a[u] - (float)v[u], (T16*)nullptr);
+      const double e = (double)a[u] - (double)(float)v[u];
       err += e * e;
-      nrm += (double)a * (double)a;
+      nrm += (double)a[u] * (double)a[u];
     }
-    if (j < n) {  // i < ld16 always
-      A16[i + j * ld16] = v;
-      if (A16lo) A16lo[i + j * ld16] = vl;
+    if (j < n) {  // i + 1 < ld16 always
+      *(pair_t*)(A16 + i + j * ld16) = pair_t{v[0], v[1]};
+      if (A16lo) *(pair_t*)(A16lo + i + j * ld16) = pair_t{vl[0], vl[1]};
     }
-    tile[jj][tx] = v;
-    tlo[jj][tx] = vl;
+    tile[jj][2 * tx] = v[0];
+    tile[jj][2 * tx + 1] = v[1];
+    tlo[jj][2 * tx] = vl[0];
+    tlo[jj][2 * tx + 1] = vl[1];
   }
   __syncthreads();
-  for (int ii = ty; ii < 64; ii += 4) {
-    const int64_t j = j0 + tx, i = i0 + ii;
-    if (i < m) {  // j < ldt16 always
-      At16[j + i * ldt16] = tile[tx][ii];
-      if (At16lo) At16lo[j + i * ldt16] = tlo[tx][ii];
+  for (int ii = ty; ii < 64; ii += 8) {
+    const int64_t j = j0 + 2 * tx, i = i0 + ii;
+    if (i < m) {  // j + 1 < ldt16 always
+      *(pair_t*)(At16 + j + i * ldt16) = pair_t{tile[2 * tx][ii], tile[2 * tx + 1][ii]};
+      if (At16lo)
+        *(pair_t*)(At16lo + j + i * ldt16) = pair_t{tlo[2 * tx][ii], tlo[2 * tx + 1][ii]};
     }
   }
   if (rerr) {

@@ -18,13 +18,14 @@
 #include <algorithm>
 #include <cmath>
 
+#include "randqlp.h"
 #include "rqlp_internal.h"
 
 namespace rqlp {
 namespace {
 
 constexpr int kNs = 64;            // sketch columns read by the predictor
-constexpr int kJacobiThreads = 256;
+constexpr int kFeatThreads = 256;
 
 // LDS writes of this wave are visible to its own later reads
 __device__ __forceinline__ void wave_sync_lds() {
@@ -96,7 +97,7 @@ __device__ __forceinline__ int sturm_count(const double* dg, const double* eo2, 
   return cnt;
 }
 
-__global__ __launch_bounds__(kJacobiThreads) void features_kernel(const double* __restrict__ G,
+__global__ __launch_bounds__(kFeatThreads) void features_kernel(const double* __restrict__ G,
                                                                  int64_t ldg, int k,
                                                                  float* __restrict__ feat) {
   __shared__ double a[kNs][kNs + 1];
@@ -104,7 +105,7 @@ __global__ __launch_bounds__(kJacobiThreads) void features_kernel(const double* 
   __shared__ double dg[kNs], eo2[kNs];
   __shared__ double lam[kNs];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < kNs * kNs; e += kJacobiThreads) {
+  for (int e = tid; e < kNs * kNs; e += kFeatThreads) {
     const int i = e % kNs, j = e / kNs;
     a[i][j] = G[i + (int64_t)j * ldg];
   }
@@ -353,6 +354,58 @@ __global__ __launch_bounds__(256) void sum_kernel(const float* __restrict__ x, i
   if (threadIdx.x == 0) *out = (float)(red[0] * scale);
 }
 
+// Predicted class of one feature vector x (RQLP_MLP_INPUTS floats): the
+// three layers of the MLP with the parameters th = [W1 b1 W2 b2 W3 b3] (each
+// W row-major per output unit), in the summation order of
+// linear_forward_kernel, then the argmax of the logits (ties to the lower
+// class); one workgroup of RQLP_MLP_HIDDEN threads.  out (optional) gets the
+// activations h1, h2 and the logits.
+constexpr int kNI = RQLP_MLP_INPUTS, kNH = RQLP_MLP_HIDDEN, kNC = RQLP_MLP_CLASSES;
+static_assert(kNI <= kNH && kNC <= kNH, "one thread per hidden unit covers the inputs and logits");
+__global__ __launch_bounds__(kNH) void predict_class_kernel(const float* __restrict__ th,
+                                                            const float* __restrict__ x,
+                                                            float* __restrict__ out,
+                                                            int* __restrict__ cls) {
+  constexpr int oW1 = 0, oB1 = oW1 + kNI * kNH, oW2 = oB1 + kNH, oB2 = oW2 + kNH * kNH,
+                oW3 = oB2 + kNH, oB3 = oW3 + kNH * kNC;
+  __shared__ float xs[kNI], h1[kNH], h2[kNH], z[kNC];
+  const int t = threadIdx.x;
+  if (t < kNI) xs[t] = x[t];
+  __syncthreads();
+  {
+    const float* w = th + oW1 + t * kNI;
+    float s = th[oB1 + t];
+    for (int i = 0; i < kNI; ++i) s = fmaf(xs[i], w[i], s);
+    h1[t] = fmaxf(s, 0.0f);
+  }
+  __syncthreads();
+  {
+    const float* w = th + oW2 + t * kNH;
+    float s = th[oB2 + t];
+    for (int i = 0; i < kNH; ++i) s = fmaf(h1[i], w[i], s);
+    h2[t] = fmaxf(s, 0.0f);
+  }
+  __syncthreads();
+  if (t < kNC) {
+    const float* w = th + oW3 + t * kNH;
+    float s = th[oB3 + t];
+    for (int i = 0; i < kNH; ++i) s = fmaf(h2[i], w[i], s);
+    z[t] = s;
+  }
+  __syncthreads();
+  if (out) {
+    out[t] = h1[t];
+    out[kNH + t] = h2[t];
+    if (t < kNC) out[2 * kNH + t] = z[t];
+  }
+  if (t == 0) {
+    int best = 0;
+    for (int c = 1; c < kNC; ++c)
+      if (z[c] > z[best]) best = c;
+    *cls = best;
+  }
+}
+
 // argmax of the 6 logits -> predicted class (ties to the lower class).
 __global__ void argmax_kernel(const float* __restrict__ Z, int C, int* __restrict__ out) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -418,7 +471,7 @@ unsigned blocks_for(int64_t n) { return (unsigned)((n + 255) / 256); }
 }  // namespace
 
 hipError_t launch_features(const double* G, int64_t ldg, int k, float* feat, hipStream_t st) {
-  hipLaunchKernelGGL(features_kernel, dim3(1), dim3(kJacobiThreads), 0, st, G, ldg, k, feat);
+  hipLaunchKernelGGL(features_kernel, dim3(1), dim3(kFeatThreads), 0, st, G, ldg, k, feat);
   return hipGetLastError();
 }
 
@@ -471,6 +524,12 @@ hipError_t launch_gather(const float* X, const int* y, int64_t N, int64_t a, int
 
 hipError_t launch_sum(const float* x, int64_t n, float scale, float* out, hipStream_t st) {
   hipLaunchKernelGGL(sum_kernel, dim3(1), dim3(256), 0, st, x, n, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_predict_class(const float* th, const float* feat, float* out, int* cls,
+                                hipStream_t st) {
+  hipLaunchKernelGGL(predict_class_kernel, dim3(1), dim3(kNH), 0, st, th, feat, out, cls);
   return hipGetLastError();
 }
 

@@ -879,8 +879,7 @@ hipError_t predict_q(Ctx& c, const FactorArgs& f, int k, const float* params, hi
   int* dcls = c.at<int>(c.lay.cls);
   HIP_TRY(feature_sketch(cp, f.A, f.m, f.n, f.lda, k, c.ws + c.lay.m1, c.ws + c.lay.y64,
                          c.at<double>(c.lay.g64), c.at<float>(c.lay.feat)));
-  HIP_TRY(mlp_forward_dev(params, c.at<float>(c.lay.feat), 1, mlp, mlp + kNH, mlp + 2 * kNH, st));
-  return launch_argmax(mlp + 2 * kNH, kNC, dcls, st);
+  return launch_predict_class(params, c.at<float>(c.lay.feat), mlp, dcls, st);
 }
 
 // Error judge after a run with q_hat rounds: sums = {||A||^2, ||L||^2,

@@ -284,6 +284,11 @@ hipError_t launch_gather(const float* X, const int* y, int64_t N, int64_t a, int
                          int64_t start, int B, int nin, float* Xb, int* yb, hipStream_t st);
 hipError_t launch_sum(const float* x, int64_t n, float scale, float* out, hipStream_t st);
 hipError_t launch_argmax(const float* Z, int C, int* out, hipStream_t st);
+// One feature vector -> MLP (parameters th, the layout of randqlp_mlp_forward)
+// -> predicted class in *cls; out (optional, 2 * hidden + classes floats)
+// receives the activations and logits.  One launch.
+hipError_t launch_predict_class(const float* th, const float* feat, float* out, int* cls,
+                                hipStream_t st);
 // ||X||_F^2 or ||X - Y||_F^2 (Y may be null) in fp64, deterministic order;
 // scratch holds sumsq_scratch_bytes().
 size_t sumsq_scratch_bytes();
