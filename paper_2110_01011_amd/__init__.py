@@ -9,6 +9,7 @@ any compute call needs the built library and a device.
 Matrices are column-major: a tensor of shape (rows, cols) with stride
 (1, ld), ld >= rows.  `colmajor()` makes such a copy of any 2-D tensor.
 """
+import contextlib
 import ctypes
 import os
 
@@ -231,6 +232,14 @@ def _ld(t):
     return max(1, t.stride(1)) if t.shape[1] > 1 else max(1, t.shape[0])
 
 
+def _on_device(dev):
+    """Context that makes `dev` current (a no-op when it already is)."""
+    torch = _torch()
+    if dev.index is None or dev.index == torch.cuda.current_device():
+        return contextlib.nullcontext()
+    return torch.cuda.device(dev)
+
+
 def _prepare(A, k, p, q, panel, precision):
     torch = _torch()
     if not A.is_cuda:
@@ -276,7 +285,7 @@ def factor(A, k, p, q, seed, panel="auto", precision=None, return_info=False):
     o.workspace_bytes = ws.numel()
     info = Info()
     o.info = ctypes.pointer(info)
-    with torch.cuda.device(A.device):
+    with _on_device(A.device):
         _check(lib().randqlp_factor(ctypes.c_void_p(A.data_ptr()), m, n, k, p, q, seed,
                                     ctypes.c_void_p(Q.data_ptr()), ctypes.c_void_p(L.data_ptr()),
                                     ctypes.c_void_p(P.data_ptr()), ctypes.byref(o)))
@@ -301,7 +310,7 @@ def factor_auto(A, k, p, seed, params, q_fallback=2, panel="auto", precision=Non
     info, ainfo = Info(), AutoInfo()
     o.info = ctypes.pointer(info)
     params = params.contiguous()
-    with torch.cuda.device(A.device):
+    with _on_device(A.device):
         _check(lib().randqlp_factor_auto(ctypes.c_void_p(A.data_ptr()), m, n, k, p, q_fallback,
                                          seed, ctypes.c_void_p(params.data_ptr()),
                                          ctypes.c_void_p(Q.data_ptr()),
