@@ -255,25 +255,44 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_grouped_kernel(
 }
 
 // C = sum_s P[s] in split order.  gram_bm > 0: element (i, j) in a lower
-// tile (i / gram_bm > j / gram_bm) is read from its mirror (j, i).
+// tile (i / gram_bm > j / gram_bm) is read from its mirror (j, i).  Grid:
+// (ceil(M / (2 * 256)), N); each thread sums rows i, i + 1 of column j, with
+// pair loads when M is even (and no mirroring).
 template <typename TP, typename TO>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(const TP* __restrict__ P, int64_t M,
                                                             int64_t N, int S,
                                                             TO* __restrict__ C, int64_t ldc,
                                                             int gram_bm) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= M * N) return;
-  const int64_t i = idx % M, j = idx / M;
-  int64_t si = i, sj = j;
-  if (gram_bm > 0 && (i / gram_bm) > (j / gram_bm)) {
-    si = j;
-    sj = i;
-  }
-  const int64_t off = si + sj * M, stride = M * N;
-  TP s = (TP)0;
+  typedef TP pair_t __attribute__((ext_vector_type(2)));
+  const int64_t j = blockIdx.y;
+  const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2;
+  if (i0 >= M) return;
+  const int64_t stride = M * N;
+  if (gram_bm == 0 && (M & 1) == 0) {
+    const TP* p = P + i0 + j * M;
+    pair_t s = {(TP)0, (TP)0};
 #pragma unroll 8
-  for (int t = 0; t < S; ++t) s += P[off + t * stride];
-  C[i + j * ldc] = (TO)s;
+    for (int t = 0; t < S; ++t) s += *(const pair_t*)(p + t * stride);
+    C[i0 + j * ldc] = (TO)s[0];
+    C[i0 + 1 + j * ldc] = (TO)s[1];
+    return;
+  }
+  for (int64_t i = i0; i < i0 + 2 && i < M; ++i) {
+    int64_t si = i, sj = j;
+    if (gram_bm > 0 && (i / gram_bm) > (j / gram_bm)) {
+      si = j;
+      sj = i;
+    }
+    const int64_t off = si + sj * M;
+    TP s = (TP)0;
+#pragma unroll 8
+    for (int t = 0; t < S; ++t) s += P[off + t * stride];
+    C[i + j * ldc] = (TO)s;
+  }
+}
+
+dim3 splitk_reduce_grid(int64_t M, int64_t N) {
+  return dim3((unsigned)((M + 511) / 512), (unsigned)N);
 }
 
 constexpr int kWavesM = 2, kWavesN = 2, kWM = 2, kBK = 16;
@@ -471,8 +490,7 @@ hipError_t gemm_typed(const GemmArgs& g, hipStream_t st) {
   if (g.ev_end) (void)hipEventRecord((hipEvent_t)g.ev_end, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || direct) return e;
-  const int64_t total = g.M * g.N;
-  hipLaunchKernelGGL((splitk_reduce_kernel<TO, TO>), dim3((unsigned)((total + 255) / 256)),
+  hipLaunchKernelGGL((splitk_reduce_kernel<TO, TO>), splitk_reduce_grid(g.M, g.N),
                      dim3(256), 0, st, (const TO*)g.partial, g.M, g.N, p.splits, (TO*)g.C,
                      g.ldc, g.gram ? kGramBM : 0);
   return hipGetLastError();
@@ -528,9 +546,9 @@ void choose_splits(int64_t tiles, int64_t K, int bk, int64_t max_s, int64_t slot
 
 hipError_t launch_splitk_reduce_f32(const float* P, int64_t M, int64_t N, int S, float* C,
                                     int64_t ldc, hipStream_t st) {
-  const int64_t total = M * N;
-  hipLaunchKernelGGL((splitk_reduce_kernel<float, float>), dim3((unsigned)((total + 255) / 256)),
-                     dim3(256), 0, st, P, M, N, S, C, ldc, 0);
+  if (M <= 0 || N <= 0) return hipSuccess;
+  hipLaunchKernelGGL((splitk_reduce_kernel<float, float>), splitk_reduce_grid(M, N), dim3(256), 0,
+                     st, P, M, N, S, C, ldc, 0);
   return hipGetLastError();
 }
 
