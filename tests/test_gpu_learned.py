@@ -208,3 +208,29 @@ def test_auto_f32(rq):
     e_o = rel_error(A, *randqlp(A, 20, 5, ai["q_used"], 2))
     log(f"  f32 auto {ai} e_g/e_o={e_g / e_o:.5f}")
     assert e_g <= 1.05 * e_o
+
+
+def test_auto_prediction_matches_oracle_mlp(rq):
+    """The class randqlp_factor_auto predicts (the MLP's three layers and the
+    argmax in one launch) is the argmax of the oracle's fp64 MLP applied to
+    the features the library computes for the same matrix and seed.  Random
+    parameters; an input whose two largest oracle logits are within 1e-4 is
+    too close to call in fp32 and is skipped."""
+    th = _params(11)
+    checked = 0
+    for i, (m, n, a) in enumerate([(600, 500, 0.5), (700, 400, 1.0), (500, 800, 2.0),
+                                   (900, 600, 3.0), (640, 640, 1.5)]):
+        A, U, s, V = W.poly_decay(m, n, a, seed=30 + i)
+        k, p, seed = 60, 10, 5 + i  # d = 70: the predictor reads Omega's first 64 columns
+        f = to_np(rq.features(to_dev(A), k, seed)).astype(np.float64)
+        Z, _ = mlp.forward(th, f[None, :])
+        top2 = np.sort(Z[0])[-2:]
+        Qg, Lg, Pg, info, ai = rq.factor_auto(to_dev(A), k, p, seed, _t(th), q_fallback=2,
+                                              return_info=True)
+        log(f"  {m}x{n} a={a}: oracle class {int(np.argmax(Z[0]))} margin "
+            f"{top2[1] - top2[0]:.2e}, predicted {ai['q_predicted']}")
+        if top2[1] - top2[0] < 1e-4:
+            continue
+        assert ai["q_predicted"] == int(np.argmax(Z[0]))
+        checked += 1
+    assert checked >= 3
