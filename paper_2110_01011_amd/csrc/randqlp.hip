@@ -679,13 +679,14 @@ rqlp_status acquire_ws(const rqlp_opts& o, size_t bytes, char** out,
 
 // Small read-backs (status words, sums, the predicted class): up to two
 // device ranges copied into a pinned buffer of the calling thread (256 bytes,
-// allocated on first use and kept), one stream synchronisation, then copied
-// out.  A copy straight to pageable memory measured about 10 us more.
+// allocated on first use, usable from every device, kept until the process
+// ends), one stream synchronisation, then copied out.  A copy straight to
+// pageable memory measured about 10 us more.
 hipError_t read_back(hipStream_t st, void* h0, const void* d0, size_t n0, void* h1 = nullptr,
                      const void* d1 = nullptr, size_t n1 = 0) {
   constexpr size_t kPin = 256;
   thread_local char* pin = nullptr;
-  if (!pin && hipHostMalloc((void**)&pin, kPin, hipHostMallocDefault) != hipSuccess) {
+  if (!pin && hipHostMalloc((void**)&pin, kPin, hipHostMallocPortable) != hipSuccess) {
     (void)hipGetLastError();
     pin = nullptr;
   }
