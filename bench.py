@@ -364,7 +364,7 @@ def main():
         traffic = read_traffic(f"profiles/gemm_kernel_rank200_8000_{args.precision}_traffic.txt")
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": "gemm_kernel (products with A)", "avg_ms": round(avg_ms, 4),
+                "kernel": "gemm_rem_kernel (fp64 products with A)", "avg_ms": round(avg_ms, 4),
                 "flops_per_launch": kflops / max(launches, 1),
                 "bytes_per_launch": kbytes / max(launches, 1)}
 

@@ -169,14 +169,16 @@ def test_prediction_at_or_above_fallback_runs_fixed_q(rq):
         _check_against_oracle(A, to_np(Qg), to_np(Lg), to_np(Pg), 15, 5, 2, 3)
 
 
-def test_judge_in_precision_form(rq):
-    """bf16 form, forced q = 0: on the slow decay the judge resumes, and the
-    error stays within 1.05x the fp64 oracle's at q_fallback = 2."""
+@pytest.mark.parametrize("precision", ["bf16", "bf16x3"])
+def test_judge_in_precision_form(rq, precision):
+    """bf16 forms (fp32 or split bf16 projection), forced q = 0: on the slow
+    decay the judge resumes, and the error stays within 1.05x the fp64
+    oracle's at q_fallback = 2."""
     import torch
     from oracle import rel_error
     A, U, s, V = W.poly_decay(1500, 1200, 0.6, seed=9)
     Qg, Lg, Pg, info, ai = rq.factor_auto(to_dev(A, torch.float32), 40, 10, 1, _forced(rq, 0),
-                                          precision="bf16", return_info=True)
+                                          precision=precision, return_info=True)
     log(f"  bf16 auto info {ai}")
     assert ai["resumed"] == 1 and ai["q_used"] == 2
     e_g = rel_error(A, to_np(Qg), to_np(Lg), to_np(Pg))

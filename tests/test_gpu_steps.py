@@ -207,3 +207,28 @@ def test_orth_robust_rank_deficient(rq, case):
         first = dep[0]
         assert np.abs(np.diag(Rg)[:first] - np.diag(Ro)[:first]).max(initial=0.0) <= 1e-12 * scale
         assert np.abs(np.diag(Rg)[dep]).max() <= 1e-12 * scale
+
+
+def test_orth_robust_rank_deficient_wide(rq):
+    """d = 300 > 224: the blocked Cholesky and the column-blocked TRSM on a
+    panel with a zero column and a duplicate, both beyond the first 224
+    columns (the duplicate of a column of the first block).  Same bar as the
+    narrow cases."""
+    log("orth robust wide d=300")
+    r = np.random.default_rng(4)
+    rows, d = 1200, 300
+    X = r.standard_normal((rows, d))
+    X[:, 230] = 0.0
+    X[:, 250] = X[:, 10]
+    dep = [230, 250]
+    X = np.asfortranarray(X)
+    for panel in ("auto", "robust"):
+        Qg, Rg = rq.orth(to_dev(X), panel=panel)
+        Qg, Rg = to_np(Qg), to_np(Rg)
+        assert np.abs(Qg.T @ Qg - np.eye(d)).max() < 1e-12
+        assert np.all(np.tril(Rg, -1) == 0) and np.all(np.diag(Rg) >= 0)
+        scale = max(np.abs(X).max(), 1.0)
+        assert np.abs(Qg @ Rg - X).max() <= 1e-12 * scale
+        Ro = qr_pos(X)[1]
+        assert np.abs(np.diag(Rg)[:dep[0]] - np.diag(Ro)[:dep[0]]).max() <= 1e-12 * scale
+        assert np.abs(np.diag(Rg)[dep]).max() <= 1e-12 * scale
