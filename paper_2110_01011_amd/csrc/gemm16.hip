@@ -67,8 +67,12 @@ __device__ __forceinline__ __bf16 to16(float x, __bf16*) {
 __device__ __forceinline__ _Float16 to16(float x, _Float16*) { return (_Float16)x; }
 
 constexpr int k16BK = 64;     // contraction depth of one tile (and the zero padding unit)
-constexpr int k16Waves = 4;   // waves per workgroup (32 rows each)
-constexpr int k16BM = 32 * k16Waves;
+// Waves per workgroup (32 rows each): 8 up to 14 column blocks, so that each
+// panel tile read from L2 serves 256 rows (one workgroup per CU, two waves
+// per SIMD either way); 4 for wider tiles, where 8 measured slower.
+constexpr int k16WideWN = 14;
+constexpr int waves16(int wn) { return wn <= k16WideWN ? 8 : 4; }
+constexpr int bm16(int wn) { return 32 * waves16(wn); }
 constexpr int k16MaxWN = 17;  // up to 272 columns per workgroup
 constexpr int kXcds = 8;
 
@@ -81,12 +85,12 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t L, int64_t T) {
 }
 
 template <typename T16, int WN>
-__global__ __launch_bounds__(64 * k16Waves, 2) void gemm16_kernel(
+__global__ __launch_bounds__(64 * waves16(WN), waves16(WN) == 8 ? 1 : 2) void gemm16_kernel(
     const T16* __restrict__ A, int64_t lda, const T16* __restrict__ B, int64_t ldb,
     float* __restrict__ C, int64_t ldc, int64_t strideS, int64_t M, int64_t N, int64_t Kp,
     int64_t kchunk, int tiles_m, int tiles_n, const T16* __restrict__ A2,
     const T16* __restrict__ B2, int seg_splits) {
-  constexpr int NT = 64 * k16Waves;
+  constexpr int NT = 64 * waves16(WN);
   constexpr int WM = 2, BK = k16BK, LK = BK + 8, CH = BK / 8;
   constexpr int BN = 16 * WN;
   constexpr int CB = BN * CH, NB = (CB + NT - 1) / NT;
@@ -101,7 +105,7 @@ __global__ __launch_bounds__(64 * k16Waves, 2) void gemm16_kernel(
   const int seg = split / seg_splits;  // 0: A B, 1: A B2, 2: A2 B
   if (seg == 2) A = A2;
   if (seg == 1) B = B2;
-  const int64_t i0 = (int64_t)tile_m * k16BM, j0 = (int64_t)tile_n * BN;
+  const int64_t i0 = (int64_t)tile_m * bm16(WN), j0 = (int64_t)tile_n * BN;
   const int64_t kbeg = (int64_t)(split - seg * seg_splits) * kchunk;
   const int64_t kend = (kbeg + kchunk < Kp) ? kbeg + kchunk : Kp;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -308,7 +312,7 @@ __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict_
 
 }  // namespace
 
-// Precision-form plan: k16BM-row tiles, N covered by as few tiles of at most
+// Precision-form plan: bm16(wn)-row tiles, N covered by as few tiles of at most
 // 16 k16MaxWN columns as possible (A is read once per N tile), split-K up to
 // ~1024 workgroups with at least four whole tiles per split.  Kp is the
 // padded contraction length (a multiple of k16BK).  nseg = 3 plans the split
@@ -324,7 +328,7 @@ int64_t pad16(int64_t K) { return (K + k16BK - 1) / k16BK * k16BK; }
 
 template <typename T16, int WN>
 int gemm16_occupancy() {
-  static const int nb = occupancy_of(gemm16_kernel<T16, WN>, 64 * k16Waves);
+  static const int nb = occupancy_of(gemm16_kernel<T16, WN>, 64 * waves16(WN));
   return nb;
 }
 
@@ -342,12 +346,12 @@ Plan16 make_plan16(int64_t M, int64_t N, int64_t K, bool f16, int nseg) {
   const int64_t nblk = (N + 15) / 16;
   p.tiles_n = (nblk + k16MaxWN - 1) / k16MaxWN;
   p.wn = (int)((nblk + p.tiles_n - 1) / p.tiles_n);
-  p.tiles_m = (M + k16BM - 1) / k16BM;
+  p.tiles_m = (M + bm16(p.wn) - 1) / bm16(p.wn);
   const int64_t tiles = p.tiles_m * p.tiles_n;
   const int64_t max_s = std::max<int64_t>(1, Kp / (4 * k16BK));
   const int occ = f16 ? gemm16_occupancy_wn<_Float16, k16MaxWN>(p.wn)
                       : gemm16_occupancy_wn<__bf16, k16MaxWN>(p.wn);
-  choose_splits(tiles * nseg, Kp, k16BK, max_s, (int64_t)occ * cu_count(), 2.0 * k16BM * 16 * p.wn,
+  choose_splits(tiles * nseg, Kp, k16BK, max_s, (int64_t)occ * cu_count(), 2.0 * bm16(p.wn) * 16 * p.wn,
                 900e12, 4.0 * (double)M * (double)N, &p.kchunk, &p.splits);
   return p;
 }
@@ -356,7 +360,7 @@ template <typename T16, int WN>
 static void run_gemm16(const Gemm16Args& g, const Plan16& p, int nseg, float* dst,
                        int64_t lddst, int64_t strideS, hipStream_t st) {
   const unsigned T = (unsigned)(p.tiles_m * p.tiles_n * p.splits * nseg);
-  hipLaunchKernelGGL((gemm16_kernel<T16, WN>), dim3(T), dim3(64 * k16Waves), 0, st,
+  hipLaunchKernelGGL((gemm16_kernel<T16, WN>), dim3(T), dim3(64 * waves16(WN)), 0, st,
                      (const T16*)g.A, g.lda, (const T16*)g.B, g.ldb, dst, lddst, strideS, g.M,
                      g.N, pad16(g.K), p.kchunk, (int)p.tiles_m, (int)p.tiles_n,
                      (const T16*)g.A2, (const T16*)g.B2, p.splits);
