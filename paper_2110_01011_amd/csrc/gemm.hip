@@ -263,18 +263,18 @@ __global__ __launch_bounds__(64 * WAVES_M * WAVES_N) void gemm_grouped_kernel(
 // C = sum_s P[s] in split order.  gram_bm > 0: element (i, j) in a lower
 // tile (i / gram_bm > j / gram_bm) is read from its mirror (j, i).  Grid:
 // (ceil(M / (2 * 256)), N); each thread sums rows i, i + 1 of column j, with
-// pair loads when M is even (and no mirroring).
+// pair loads when `pairs` (M even, P aligned to a pair, no mirroring).
 template <typename TP, typename TO>
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(const TP* __restrict__ P, int64_t M,
                                                             int64_t N, int S,
                                                             TO* __restrict__ C, int64_t ldc,
-                                                            int gram_bm) {
+                                                            int gram_bm, int pairs) {
   typedef TP pair_t __attribute__((ext_vector_type(2)));
   const int64_t j = blockIdx.y;
   const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * 2;
   if (i0 >= M) return;
   const int64_t stride = M * N;
-  if (gram_bm == 0 && (M & 1) == 0) {
+  if (pairs) {
     const TP* p = P + i0 + j * M;
     pair_t s = {(TP)0, (TP)0};
 #pragma unroll 8
@@ -299,6 +299,11 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const TP* __restrict
 
 dim3 splitk_reduce_grid(int64_t M, int64_t N) {
   return dim3((unsigned)((M + 511) / 512), (unsigned)N);
+}
+
+template <typename TP>
+int splitk_pairs(const TP* P, int64_t M, int gram_bm) {
+  return gram_bm == 0 && (M & 1) == 0 && ((uintptr_t)P % (2 * sizeof(TP))) == 0;
 }
 
 constexpr int kWavesM = 2, kWavesN = 2, kWM = 2, kBK = 16;
@@ -496,9 +501,10 @@ hipError_t gemm_typed(const GemmArgs& g, hipStream_t st) {
   if (g.ev_end) (void)hipEventRecord((hipEvent_t)g.ev_end, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || direct) return e;
+  const int gbm = g.gram ? kGramBM : 0;
   hipLaunchKernelGGL((splitk_reduce_kernel<TO, TO>), splitk_reduce_grid(g.M, g.N),
                      dim3(256), 0, st, (const TO*)g.partial, g.M, g.N, p.splits, (TO*)g.C,
-                     g.ldc, g.gram ? kGramBM : 0);
+                     g.ldc, gbm, splitk_pairs((const TO*)g.partial, g.M, gbm));
   return hipGetLastError();
 }
 
@@ -554,7 +560,7 @@ hipError_t launch_splitk_reduce_f32(const float* P, int64_t M, int64_t N, int S,
                                     int64_t ldc, hipStream_t st) {
   if (M <= 0 || N <= 0) return hipSuccess;
   hipLaunchKernelGGL((splitk_reduce_kernel<float, float>), splitk_reduce_grid(M, N), dim3(256), 0,
-                     st, P, M, N, S, C, ldc, 0);
+                     st, P, M, N, S, C, ldc, 0, splitk_pairs(P, M, 0));
   return hipGetLastError();
 }
 

@@ -435,7 +435,10 @@ hipError_t launch_convert16(const float* A, int64_t m, int64_t n, int64_t lda, v
                             int64_t ld16, void* At16, int64_t ldt16, bool f16, hipStream_t st,
                             double* rerr, void* A16lo, void* At16lo) {
   if (m <= 0 || n <= 0) return hipSuccess;
-  if (ld16 < pad16(m) || ldt16 < pad16(n)) return hipErrorInvalidValue;
+  // pair stores: even leading dimensions and 4-byte aligned copies
+  if (ld16 < pad16(m) || ldt16 < pad16(n) || (ld16 & 1) || (ldt16 & 1) ||
+      (((uintptr_t)A16 | (uintptr_t)At16 | (uintptr_t)A16lo | (uintptr_t)At16lo) & 3))
+    return hipErrorInvalidValue;
   dim3 grid((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64));
   if (f16)
     hipLaunchKernelGGL(convert16_kernel<_Float16>, grid, dim3(256), 0, st, A, m, n, lda,
