@@ -231,8 +231,12 @@ __global__ __launch_bounds__(64 * kRemWavesM) void gemm_rem_kernel(
     int64_t kchunk) {
   // 8-deep tiles for A X (row tiles of A strided in memory: keeps the
   // register count within two waves per SIMD) and for the widest tiles
-  // (keeps the LDS of one workgroup under the per-workgroup limit)
-  gemm_body<TI, TC, TO, TA, kRemWavesM, 1, rem_wm<TI>(), WN, (TA && WN <= 13) ? 16 : 8, kRemV>(
+  // (keeps the LDS of one workgroup under the per-workgroup limit); 32-deep
+  // tiles for narrow A^T X (up to 4 blocks, such as the predictor's 64-column
+  // sketch), whose streaming of A is bound by the bytes one workgroup keeps
+  // in flight
+  gemm_body<TI, TC, TO, TA, kRemWavesM, 1, rem_wm<TI>(), WN,
+            (TA && WN <= 4) ? 32 : ((TA && WN <= 13) ? 16 : 8), kRemV>(
       A, lda, B, ldb, C, ldc, strideS, M, N, K, kchunk, 0, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
