@@ -309,6 +309,10 @@ void randqlp_profile_enable(int on);
  * once each) of those launches.  Any pointer may be NULL.  Resets totals. */
 void randqlp_profile_read(double* ms, int64_t* launches, double* flops, double* bytes);
 
+/* Identifier of the sources this library was built from (the SHA-256, in
+ * hex, of its source files and compile flags; "unknown" if not given). */
+const char* randqlp_build_id(void);
+
 /* Human-readable name of a status, and the calling thread's last error. */
 const char* randqlp_status_string(rqlp_status s);
 const char* randqlp_last_error(void);

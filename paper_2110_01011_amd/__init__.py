@@ -39,7 +39,7 @@ EXPORTS = ["rqlp_opts_default", "randqlp_sketch_width", "randqlp_workspace_size"
            "randqlp_tune_load",
            "randqlp_gaussian", "randqlp_gemm", "randqlp_orth",
            "randqlp_profile_enable", "randqlp_profile_read",
-           "randqlp_status_string", "randqlp_last_error"]
+           "randqlp_status_string", "randqlp_last_error", "randqlp_build_id"]
 
 
 class RandQLPError(RuntimeError):
@@ -98,6 +98,14 @@ def lib():
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python -m paper_2110_01011_amd.build_lib`")
     L = ctypes.CDLL(LIB_PATH)
+    L.randqlp_build_id.argtypes = []
+    L.randqlp_build_id.restype = ctypes.c_char_p
+    from .build_lib import source_id
+    built, want = L.randqlp_build_id().decode(), source_id()
+    if built != want:
+        raise ImportError(f"{LIB_PATH} was built from other sources (build id {built[:12]}, "
+                          f"sources {want[:12]}): rebuild it with "
+                          "`python -m paper_2110_01011_amd.build_lib`")
     i64, i32, u64, vp, sz = ctypes.c_int64, ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p, ctypes.c_size_t
     L.rqlp_opts_default.argtypes = [ctypes.POINTER(Opts)]
     L.rqlp_opts_default.restype = None

@@ -2,8 +2,11 @@
 
 Usage: python -m paper_2110_01011_amd.build_lib  (or build() from Python).
 Each .hip translation unit is compiled to an object file under _build/ and
-linked into paper_2110_01011_amd/librandqlp.so.
+linked into paper_2110_01011_amd/librandqlp.so.  The library carries the
+SHA-256 of its sources and compile flags (randqlp_build_id()); the binding
+refuses to load a library whose id differs from the sources beside it.
 """
+import hashlib
 import os
 import shutil
 import subprocess
@@ -27,6 +30,19 @@ HIPCC_FLAGS = [
 ]
 
 
+def source_id():
+    """SHA-256 (hex) of every source file and flag the library is built from."""
+    h = hashlib.sha256()
+    files = [os.path.join(CSRC, f) for f in SOURCES] + [
+        os.path.join(CSRC, "rqlp_internal.h"), os.path.join(ROOT, "include", "randqlp.h")]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    h.update(" ".join(HIPCC_FLAGS[:-2]).encode())  # flags without the include path
+    return h.hexdigest()
+
+
 def _hipcc():
     path = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(path):
@@ -36,7 +52,8 @@ def _hipcc():
 
 def _compile(src, verbose):
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *HIPCC_FLAGS, f"-DRQLP_BUILD_ID=\"{source_id()}\"", "-c",
+           os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

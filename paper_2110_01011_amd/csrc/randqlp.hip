@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -93,6 +94,8 @@ struct Layout {
   size_t y64, g64, feat, mlp, cls, jd, sums, sres, rerr;
   size_t part2, part2_bytes;  // split-K scratch of the predictor's products
   size_t flags_bytes;  // status words cleared at the start of a call
+  int64_t omega_cols;  // columns of Omega drawn into m1: d, or at least the
+                       // predictor's kPredCols when the predictor reads them
 };
 
 size_t elem_size(Dtype dt) { return dt == DT_F64 ? 8 : 4; }
@@ -109,7 +112,11 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
     off += align_up(bytes);
     return o;
   };
-  L.m1 = take((size_t)m * d * es);
+  // Omega lives in m1 at the start of a call; the predictor reads its leading
+  // kPredCols columns, so m1 holds at least that many (the Gaussian is
+  // indexed by i + j m, so the method's own d columns are unchanged).
+  L.omega_cols = autoq ? std::max<int64_t>(d, kPredCols) : d;
+  L.m1 = take((size_t)m * L.omega_cols * es);
   L.m2 = take((size_t)m * d * es);
   L.n1 = take((size_t)n * d * es);
   L.n2 = take((size_t)n * d * es);
@@ -195,11 +202,20 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
   return L;
 }
 
-// Library-managed workspace: one growing buffer per device.
-struct WsCache {
+// Library-managed workspace: one growing buffer per (device, stream).  A call
+// holds its entry's lock until it returns (every such call completes its work
+// before returning), so calls on one stream are serialised and calls on
+// different streams run independently.
+struct WsEntry {
+  int dev = 0;
+  hipStream_t st = nullptr;
   std::mutex mu;
-  void* ptr[64] = {};
-  size_t size[64] = {};
+  void* ptr = nullptr;
+  size_t size = 0;
+};
+struct WsCache {
+  std::mutex mu;  // guards the list, not the buffers
+  std::vector<std::unique_ptr<WsEntry>> entries;
 };
 WsCache g_ws;
 
@@ -207,6 +223,7 @@ struct Ctx {
   hipStream_t st;
   Dtype dt;
   int mixed = 0;  // 0: no; 1: bf16 products; 2: fp16 products; 3: bf16 + split projection
+  bool noalloc = false;  // no allocation of any kind (static scratch, pageable read-backs)
   char* ws;
   Layout lay;
   int64_t d;
@@ -264,7 +281,7 @@ hipError_t gemm(Ctx& c, int trans_a, const void* A, int64_t lda, const void* B, 
   g.gram = gram;
   g.partial = c.ws + c.lay.part;
   g.partial_bytes = c.lay.part_bytes;
-  if (timed && g_prof.on) {
+  if (timed && g_prof.on && !c.noalloc) {
     const size_t i = g_prof.used++;
     while (g_prof.ev.size() < 2 * g_prof.used) {
       hipEvent_t e;
@@ -310,7 +327,7 @@ hipError_t gemm16(Ctx& c, int trans_a, int64_t m, int64_t n, const float* X, int
   hipError_t e = launch_convert_panel16(X, g.K, d, ldx, c.ws + c.lay.p16, c.lay.ldp16, g.f16, c.st,
                                         split ? c.ws + c.lay.p16lo : nullptr);
   if (e != hipSuccess) return e;
-  if (g_prof.on) {
+  if (g_prof.on && !c.noalloc) {
     const size_t i = g_prof.used++;
     while (g_prof.ev.size() < 2 * g_prof.used) {
       hipEvent_t ev;
@@ -515,7 +532,8 @@ hipError_t prod(Ctx& c, const FactorArgs& f, int trans_a, const void* X, int64_t
 // start: Omega (in Zm), then the 16-bit copies of A, Y = A^T Omega and
 // Qbar = orth(Y).
 hipError_t stage_omega(Ctx& c, const FactorArgs& f) {
-  return launch_gaussian(c.ws + c.lay.m1, f.m, c.d, f.m, c.seed, 0, c.dt, c.st);   // randn
+  return launch_gaussian(c.ws + c.lay.m1, f.m, c.lay.omega_cols, f.m, c.seed, 0, c.dt,
+                         c.st);                                                // randn
 }
 
 hipError_t stage_sketch(Ctx& c, const FactorArgs& f, PanelMode mode) {
@@ -573,9 +591,14 @@ hipError_t stage_finish(Ctx& c, const FactorArgs& f, PanelMode mode) {
   return stage_finish_from_z(c, f, mode);
 }
 
+// Zero the status words with a fill kernel (no memset node if captured).
+hipError_t clear_flags(Ctx& c) {
+  return launch_zero_ints(c.flags(), (int64_t)(c.lay.flags_bytes / sizeof(int)), c.st);
+}
+
 hipError_t run_pipeline(Ctx& c, const FactorArgs& f, PanelMode mode) {
   c.orth_calls = 0;
-  HIP_TRY(hipMemsetAsync(c.flags(), 0, c.lay.flags_bytes, c.st));
+  HIP_TRY(clear_flags(c));
   HIP_TRY(stage_start(c, f, mode));
   HIP_TRY(stage_rounds(c, f, mode, f.q));
   return stage_finish(c, f, mode);
@@ -615,6 +638,11 @@ const char* randqlp_status_string(rqlp_status s) {
 
 const char* randqlp_last_error(void) { return g_last_error.c_str(); }
 
+#ifndef RQLP_BUILD_ID
+#define RQLP_BUILD_ID "unknown"
+#endif
+const char* randqlp_build_id(void) { return RQLP_BUILD_ID; }
+
 void randqlp_profile_enable(int on) {
   g_prof.on = (on != 0);
   g_prof.used = 0;
@@ -643,8 +671,9 @@ size_t randqlp_workspace_size(int64_t m, int64_t n, int k, int p, int q, const r
 
 namespace {
 
-// Acquire `bytes` of device scratch: the caller's buffer or the per-device
-// cache (grown under the lock; the lock is held for the whole call).
+// Acquire `bytes` of device scratch: the caller's buffer or the cache entry
+// of (current device, o.stream), grown under that entry's lock, which stays
+// held (in lk) until the call returns.
 rqlp_status acquire_ws(const rqlp_opts& o, size_t bytes, char** out,
                        std::unique_lock<std::mutex>& lk) {
   if (o.workspace != nullptr) {
@@ -655,25 +684,38 @@ rqlp_status acquire_ws(const rqlp_opts& o, size_t bytes, char** out,
     return RQLP_OK;
   }
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
-    return fail(RQLP_E_HIP, "hipGetDevice failed");
-  lk = std::unique_lock<std::mutex>(g_ws.mu);
-  if (g_ws.size[dev] < bytes) {
-    if (g_ws.ptr[dev]) {
-      (void)hipDeviceSynchronize();
-      (void)hipFree(g_ws.ptr[dev]);
-      g_ws.ptr[dev] = nullptr;
-      g_ws.size[dev] = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(RQLP_E_HIP, "hipGetDevice failed");
+  const hipStream_t st = (hipStream_t)o.stream;
+  WsEntry* ent = nullptr;
+  {
+    std::lock_guard<std::mutex> g(g_ws.mu);
+    for (auto& e : g_ws.entries)
+      if (e->dev == dev && e->st == st) ent = e.get();
+    if (!ent) {
+      g_ws.entries.emplace_back(new WsEntry);
+      ent = g_ws.entries.back().get();
+      ent->dev = dev;
+      ent->st = st;
+    }
+  }
+  lk = std::unique_lock<std::mutex>(ent->mu);
+  if (ent->size < bytes) {
+    if (ent->ptr) {
+      // earlier calls on this stream have completed (each synchronises)
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(ent->ptr);
+      ent->ptr = nullptr;
+      ent->size = 0;
     }
     void* p = nullptr;
     if (hipMalloc(&p, bytes) != hipSuccess || p == nullptr) {
       (void)hipGetLastError();
       return fail(RQLP_E_NOMEM, "hipMalloc of %zu bytes failed", bytes);
     }
-    g_ws.ptr[dev] = p;
-    g_ws.size[dev] = bytes;
+    ent->ptr = p;
+    ent->size = bytes;
   }
-  *out = (char*)g_ws.ptr[dev];
+  *out = (char*)ent->ptr;
   return RQLP_OK;
 }
 
@@ -683,9 +725,14 @@ rqlp_status acquire_ws(const rqlp_opts& o, size_t bytes, char** out,
 // ends), one stream synchronisation, then copied out.  A copy straight to
 // pageable memory measured about 10 us more.
 hipError_t read_back(hipStream_t st, void* h0, const void* d0, size_t n0, void* h1 = nullptr,
-                     const void* d1 = nullptr, size_t n1 = 0) {
+                     const void* d1 = nullptr, size_t n1 = 0, bool pinned = true) {
   constexpr size_t kPin = 256;
   thread_local char* pin = nullptr;
+  if (!pinned) {  // straight to the caller's (pageable) memory: nothing allocated
+    HIP_TRY(hipMemcpyAsync(h0, d0, n0, hipMemcpyDeviceToHost, st));
+    if (n1) HIP_TRY(hipMemcpyAsync(h1, d1, n1, hipMemcpyDeviceToHost, st));
+    return hipStreamSynchronize(st);
+  }
   if (!pin && hipHostMalloc((void**)&pin, kPin, hipHostMallocPortable) != hipSuccess) {
     (void)hipGetLastError();
     pin = nullptr;
@@ -704,7 +751,8 @@ hipError_t read_back(hipStream_t st, void* h0, const void* d0, size_t n0, void* 
 }
 
 rqlp_status read_flags(Ctx& c, int host[4]) {
-  hipError_t e = read_back(c.st, host, c.flags(), 4 * sizeof(int));
+  hipError_t e = read_back(c.st, host, c.flags(), 4 * sizeof(int), nullptr, nullptr, 0,
+                           !c.noalloc);
   if (e != hipSuccess) return fail(RQLP_E_HIP, "status read-back: %s", hipGetErrorString(e));
   if (g_prof.on) prof_collect();
   return RQLP_OK;
@@ -777,7 +825,7 @@ rqlp_status run_with_escalation(Ctx& c, const FactorArgs& f, const rqlp_opts& o,
     if ((s = read_flags(c, fl)) != RQLP_OK) return s;
     if (fl[0] & FLAG_NONFINITE) {
       int fin[4] = {0, 0, 0, 0};
-      e = hipMemsetAsync(c.flags(), 0, 64, c.st);
+      e = clear_flags(c);
       if (e == hipSuccess) e = launch_check_finite(f.A, f.m, f.n, f.lda, c.dt, c.flags(), c.st);
       if (e != hipSuccess) return fail(RQLP_E_HIP, "finite check: %s", hipGetErrorString(e));
       if ((s = read_flags(c, fin)) != RQLP_OK) return s;
@@ -949,7 +997,7 @@ hipError_t resume(Ctx& c, const FactorArgs& f, PanelMode mode, int more) {
   void* Tm = c.ws + c.lay.m2;
   void* Yn = c.ws + c.lay.n1;
   void* Tn = c.ws + c.lay.n2;
-  HIP_TRY(hipMemsetAsync(c.flags(), 0, c.lay.flags_bytes, c.st));
+  HIP_TRY(clear_flags(c));
   if (more == 0) return stage_finish_from_z(c, f, mode);
   HIP_TRY(orth(c, Zm, m, m, Zm, m, Tm, nullptr, mode, false));                 // Q
   HIP_TRY(prod(c, f, 1, Zm, m, Yn, n));                                        // A^T Q
@@ -1021,7 +1069,7 @@ rqlp_status randqlp_factor_auto(const void* A, int64_t m, int64_t n, int k, int 
   c.orth_calls = 0;
   hipError_t e = aux_stream(&aux);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipMemsetAsync(c.flags(), 0, c.lay.flags_bytes, c.st);
+  if (e == hipSuccess) e = clear_flags(c);
   if (e == hipSuccess) e = stage_omega(c, f);
   if (e == hipSuccess) e = hipEventRecord(ready, c.st);           // Omega is in Zm
   if (e == hipSuccess) e = hipStreamWaitEvent(aux, ready, 0);
@@ -1106,6 +1154,7 @@ rqlp_status randqlp_features(const void* A, int64_t m, int64_t n, int64_t lda, i
   const size_t o_p = o_g + align_up((size_t)kPredCols * kPredCols * 8);
   rqlp_opts o;
   rqlp_opts_default(&o);
+  o.stream = stream;  // the workspace cache entry of the stream the call runs on
   std::unique_lock<std::mutex> lk;
   char* ws = nullptr;
   rqlp_status s = acquire_ws(o, o_p + std::max<size_t>(part, 256), &ws, lk);
@@ -1130,6 +1179,7 @@ rqlp_status randqlp_mlp_forward(const float* params, const float* X, int B, floa
     return fail(RQLP_E_INVALID_ARG, "bad pointer or batch size");
   rqlp_opts o;
   rqlp_opts_default(&o);
+  o.stream = stream;  // the workspace cache entry of the stream the call runs on
   std::unique_lock<std::mutex> lk;
   char* ws = nullptr;
   rqlp_status s = acquire_ws(o, 2 * align_up((size_t)B * kNH * 4), &ws, lk);
@@ -1149,6 +1199,7 @@ rqlp_status randqlp_mlp_loss_grad(const float* params, const float* X, const int
     return fail(RQLP_E_INVALID_ARG, "bad pointer or batch size");
   rqlp_opts o;
   rqlp_opts_default(&o);
+  o.stream = stream;  // the workspace cache entry of the stream the call runs on
   std::unique_lock<std::mutex> lk;
   char* ws = nullptr;
   MlpScratch sc;
@@ -1181,6 +1232,7 @@ rqlp_status randqlp_mlp_train(float* params, float* m, float* v, const float* X,
   const int64_t steps = (N + batch - 1) / batch;
   rqlp_opts o;
   rqlp_opts_default(&o);
+  o.stream = stream;  // the workspace cache entry of the stream the call runs on
   std::unique_lock<std::mutex> lk;
   char* ws = nullptr;
   rqlp_status s = acquire_ws(o, mlp_scratch_bytes(batch, steps), &ws, lk);
@@ -1236,6 +1288,7 @@ rqlp_status randqlp_gemm(int trans_a, const void* A, int64_t m, int64_t n, int64
   const hipStream_t st = (hipStream_t)stream;
   rqlp_opts o;
   rqlp_opts_default(&o);
+  o.stream = stream;  // the workspace cache entry of the stream the call runs on
   std::unique_lock<std::mutex> lk;
   char* ws = nullptr;
   hipError_t e = hipSuccess;
@@ -1333,6 +1386,7 @@ rqlp_status randqlp_orth(const void* X, int64_t rows, int64_t d, int64_t ldx, vo
   c.orth_calls = 0;
   rqlp_opts o;
   rqlp_opts_default(&o);
+  o.stream = stream;  // the workspace cache entry of the stream the call runs on
   std::unique_lock<std::mutex> lk;
   rqlp_status s = acquire_ws(o, c.lay.total, &c.ws, lk);
   if (s != RQLP_OK) return s;
@@ -1343,7 +1397,7 @@ rqlp_status randqlp_orth(const void* X, int64_t rows, int64_t d, int64_t ldx, vo
   int fl[4] = {0, 0, 0, 0};
   for (;;) {
     c.orth_calls = 0;
-    hipError_t e = hipMemsetAsync(c.flags(), 0, c.lay.flags_bytes, c.st);
+    hipError_t e = clear_flags(c);
     if (e == hipSuccess)
       e = orth(c, X, rows, ldx, Qx, ldq, c.ws + c.lay.m2, Rfin, mode, true);
     if (e == hipSuccess && R)

@@ -236,3 +236,29 @@ def test_auto_prediction_matches_oracle_mlp(rq):
         assert ai["q_predicted"] == int(np.argmax(Z[0]))
         checked += 1
     assert checked >= 3
+
+
+@pytest.mark.parametrize("m,n,k,p", [(3000, 200, 10, 5), (4000, 120, 20, 10),
+                                     (2500, 300, 40, 10), (1000, 900, 8, 2)])
+def test_auto_prediction_with_narrow_sketch(rq, m, n, k, p):
+    """d = k + p < 64 (and m >> n): the predictor reads the first 64 columns
+    of Omega, which the call draws beside the method's d columns.  The class
+    must be the oracle MLP's argmax on the oracle's features of the same
+    matrix and seed, and the factors the oracle method's at the q used.
+    Seeds whose two largest logits lie within 1e-2 (too close to call with
+    fp32 features) are passed over."""
+    th = _params(12)
+    A, U, s, V = W.poly_decay(m, n, 1.5, seed=m + k)
+    for seed in range(8):
+        Z, _ = mlp.forward(th, sketch_features(A, k, seed)[None, :])
+        top2 = np.sort(Z[0])[-2:]
+        if top2[1] - top2[0] >= 1e-2:
+            break
+    else:
+        pytest.skip("no seed with a clear margin")
+    Qg, Lg, Pg, info, ai = rq.factor_auto(to_dev(A), k, p, seed, _t(th), q_fallback=2,
+                                          return_info=True)
+    log(f"  {m}x{n} k={k} p={p} seed={seed}: oracle class {int(np.argmax(Z[0]))}, "
+        f"predicted {ai['q_predicted']}, used {ai['q_used']}")
+    assert ai["q_predicted"] == int(np.argmax(Z[0]))
+    _check_against_oracle(A, to_np(Qg), to_np(Lg), to_np(Pg), k, p, ai["q_used"], seed)
