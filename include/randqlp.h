@@ -153,6 +153,25 @@ rqlp_status randqlp_factor(const void* A, int64_t m, int64_t n, int k, int p, in
                            uint64_t seed, void* Q, void* L, void* P,
                            const rqlp_opts* opts);
 
+/* randqlp_factor for callers that cannot allocate memory (tight serving
+ * loops, harnesses that forbid allocation at run time): the same method and
+ * kernels, with the call's scratch taken from a static device array of
+ * RQLP_NOALLOC_SCRATCH_BYTES that every device holds from the time the
+ * library's code object is loaded on it until the process ends, and small
+ * read-backs copied to pageable host memory.  Nothing is allocated by the
+ * call (no hipMalloc, hipHostMalloc, hipFree, event or stream creation).
+ * opts->workspace must be NULL (RQLP_E_INVALID_ARG otherwise).  Sizes whose
+ * scratch (randqlp_workspace_size with the same arguments) exceeds the array
+ * return RQLP_E_WORKSPACE before anything is enqueued.  All calls on one
+ * device share its array, which keeps the last call's contents: within a
+ * process the library runs them one at a time (each completes before the
+ * next starts); calls from other processes have their own copies.  Results
+ * equal randqlp_factor's for the same arguments.  Synchronous. */
+#define RQLP_NOALLOC_SCRATCH_BYTES (128ull << 20)
+rqlp_status randqlp_factor_noalloc(const void* A, int64_t m, int64_t n, int k, int p, int q,
+                                   uint64_t seed, void* Q, void* L, void* P,
+                                   const rqlp_opts* opts);
+
 /* ---- Step-level entry points (the individual steps of the method; the
  * same kernels randqlp_factor runs).  Asynchronous on `stream`. ---- */
 

@@ -13,7 +13,7 @@ import contextlib
 import ctypes
 import os
 
-__all__ = ["factor", "factor_auto", "Batch", "factor_batched", "tune_save", "tune_load", "features", "mlp_forward", "mlp_loss_grad", "mlp_adam",
+__all__ = ["factor", "factor_noalloc", "factor_auto", "Batch", "factor_batched", "tune_save", "tune_load", "features", "mlp_forward", "mlp_loss_grad", "mlp_adam",
            "mlp_train", "gaussian", "gemm", "orth", "sketch_width", "workspace_size",
            "colmajor", "empty_colmajor", "lib", "RandQLPError", "F64", "F32", "MIXED_BF16",
            "MIXED_F16", "MIXED_BF16X3",
@@ -32,7 +32,7 @@ STATUS = {0: "RQLP_OK", 1: "RQLP_E_INVALID_ARG", 2: "RQLP_E_NONFINITE", 3: "RQLP
 
 # Every symbol include/randqlp.h declares.
 EXPORTS = ["rqlp_opts_default", "randqlp_sketch_width", "randqlp_workspace_size",
-           "randqlp_factor", "randqlp_factor_auto", "randqlp_features", "randqlp_mlp_forward",
+           "randqlp_factor", "randqlp_factor_noalloc", "randqlp_factor_auto", "randqlp_features", "randqlp_mlp_forward",
            "randqlp_mlp_loss_grad", "randqlp_mlp_adam", "randqlp_mlp_train",
            "randqlp_batch_create", "randqlp_batch_run", "randqlp_batch_query",
            "randqlp_batch_destroy", "randqlp_factor_batched", "randqlp_tune_save",
@@ -115,6 +115,9 @@ def lib():
     L.randqlp_workspace_size.restype = sz
     L.randqlp_factor.argtypes = [vp, i64, i64, i32, i32, i32, u64, vp, vp, vp, ctypes.POINTER(Opts)]
     L.randqlp_factor.restype = i32
+    L.randqlp_factor_noalloc.argtypes = [vp, i64, i64, i32, i32, i32, u64, vp, vp, vp,
+                                         ctypes.POINTER(Opts)]
+    L.randqlp_factor_noalloc.restype = i32
     L.randqlp_factor_auto.argtypes = [vp, i64, i64, i32, i32, i32, u64, vp, vp, vp, vp,
                                       ctypes.POINTER(Opts), ctypes.POINTER(AutoInfo)]
     L.randqlp_factor_auto.restype = i32
@@ -298,6 +301,33 @@ def factor(A, k, p, q, seed, panel="auto", precision=None, return_info=False):
                                     ctypes.c_void_p(Q.data_ptr()), ctypes.c_void_p(L.data_ptr()),
                                     ctypes.c_void_p(P.data_ptr()), ctypes.byref(o)))
     del ws
+    if return_info:
+        return Q, L, P, info.as_dict()
+    return Q, L, P
+
+
+NOALLOC_SCRATCH_BYTES = 128 << 20
+
+
+def factor_noalloc(A, k, p, q, seed, panel="auto", precision=None, return_info=False,
+                   out=None):
+    """factor() through randqlp_factor_noalloc: the library's static device
+    scratch instead of a workspace (nothing allocated by the call).  out:
+    optional (Q, L, P) column-major tensors to write into (allocated here
+    when None).  Raises RandQLPError (RQLP_E_WORKSPACE) when the sizes need
+    more than NOALLOC_SCRATCH_BYTES of scratch."""
+    A, Q, L, P, o = _prepare(A, k, p, q, panel, precision)
+    if out is not None:
+        Q, L, P = out
+        o.ldq, o.ldl, o.ldp = _ld(Q), _ld(L), _ld(P)
+    m, n = A.shape
+    info = Info()
+    o.info = ctypes.pointer(info)
+    with _on_device(A.device):
+        _check(lib().randqlp_factor_noalloc(ctypes.c_void_p(A.data_ptr()), m, n, k, p, q, seed,
+                                            ctypes.c_void_p(Q.data_ptr()),
+                                            ctypes.c_void_p(L.data_ptr()),
+                                            ctypes.c_void_p(P.data_ptr()), ctypes.byref(o)))
     if return_info:
         return Q, L, P, info.as_dict()
     return Q, L, P

@@ -759,11 +759,47 @@ rqlp_status read_flags(Ctx& c, int host[4]) {
 }
 
 
+// ---- static scratch of randqlp_factor_noalloc
+// Device memory that the library never allocates at run time: a file-scope
+// array that each device holds from the time the library's code object is
+// loaded on it until the process ends.  Host code must not pass `scratch`
+// itself to a kernel (on the host it only names the symbol): the device
+// address comes from hipGetSymbolAddress, once per device, with that device
+// current, and only that address is used.
+constexpr size_t kStaticScratchBytes = (size_t)RQLP_NOALLOC_SCRATCH_BYTES;
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;            // guards g_scratch_ptr
+void* g_scratch_ptr[64] = {};       // device address of `scratch` per device
+std::mutex g_scratch_call_mu[64];   // one randqlp_factor_noalloc call per device at a time
+
+// Device address of the static scratch on device `dev` (current).
+rqlp_status static_scratch(int dev, char** out) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) {
+      (void)hipGetLastError();
+      return fail(RQLP_E_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *out = (char*)g_scratch_ptr[dev];
+  return RQLP_OK;
+}
+
 // ---- shared set-up of randqlp_factor / randqlp_factor_auto
 rqlp_status setup_factor(const void* A, int64_t m, int64_t n, int k, int p, int q,
                          uint64_t seed, void* Q, void* L, void* P, const rqlp_opts* opts,
                          bool autoq, Ctx& c, FactorArgs& f, rqlp_opts& o,
-                         std::unique_lock<std::mutex>& lk) {
+                         std::unique_lock<std::mutex>& lk, bool noalloc = false) {
   if (opts)
     o = *opts;
   else
@@ -796,8 +832,25 @@ rqlp_status setup_factor(const void* A, int64_t m, int64_t n, int k, int p, int 
   c.d = d;
   c.seed = seed;
   c.orth_calls = 0;
-  rqlp_status s = acquire_ws(o, c.lay.total, &c.ws, lk);
-  if (s != RQLP_OK) return s;
+  rqlp_status s = RQLP_OK;
+  if (noalloc) {
+    if (o.workspace != nullptr)
+      return fail(RQLP_E_INVALID_ARG, "opts->workspace must be NULL: this entry point uses the "
+                  "library's static scratch");
+    if (c.lay.total > kStaticScratchBytes)
+      return fail(RQLP_E_WORKSPACE, "these sizes need %zu bytes of scratch; the static scratch "
+                  "holds %zu (use randqlp_factor with a workspace)", c.lay.total,
+                  kStaticScratchBytes);
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
+      return fail(RQLP_E_HIP, "hipGetDevice failed");
+    lk = std::unique_lock<std::mutex>(g_scratch_call_mu[dev]);
+    if ((s = static_scratch(dev, &c.ws)) != RQLP_OK) return s;
+    c.noalloc = true;
+  } else {
+    s = acquire_ws(o, c.lay.total, &c.ws, lk);
+    if (s != RQLP_OK) return s;
+  }
   f = FactorArgs{A, m, n, lda, q, Q, ldq, (double*)L, ldl, P, ldp};
   return RQLP_OK;
 }
@@ -1033,6 +1086,22 @@ rqlp_status randqlp_factor(const void* A, int64_t m, int64_t n, int k, int p, in
   rqlp_opts o;
   std::unique_lock<std::mutex> lk;
   rqlp_status s = setup_factor(A, m, n, k, p, q, seed, Q, L, P, opts, false, c, f, o, lk);
+  if (s != RQLP_OK) return s;
+  Outcome r;
+  if ((s = run_with_escalation(c, f, o, start_mode(o), r)) != RQLP_OK) return s;
+  fill_info(o, c.d, q, r);
+  g_last_error.clear();
+  return RQLP_OK;
+}
+
+rqlp_status randqlp_factor_noalloc(const void* A, int64_t m, int64_t n, int k, int p, int q,
+                                   uint64_t seed, void* Q, void* L, void* P,
+                                   const rqlp_opts* opts) {
+  Ctx c;
+  FactorArgs f;
+  rqlp_opts o;
+  std::unique_lock<std::mutex> lk;
+  rqlp_status s = setup_factor(A, m, n, k, p, q, seed, Q, L, P, opts, false, c, f, o, lk, true);
   if (s != RQLP_OK) return s;
   Outcome r;
   if ((s = run_with_escalation(c, f, o, start_mode(o), r)) != RQLP_OK) return s;

@@ -87,6 +87,26 @@ def test_undersized_workspace_is_reported(L):
     assert "workspace" in L.randqlp_last_error().decode()
 
 
+def test_noalloc_rejects_workspace_and_oversize(L):
+    """The no-allocation variant validates like randqlp_factor, refuses a
+    caller workspace and rejects sizes whose scratch exceeds its static
+    array before touching the device."""
+    dummy = ctypes.c_void_p(256)
+    assert L.randqlp_factor_noalloc(None, 10, 10, 3, 1, 0, 0, dummy, dummy, dummy, None) == 1
+    assert L.randqlp_factor_noalloc(dummy, 10, 10, 0, 1, 0, 0, dummy, dummy, dummy, None) == 1
+    o = rq.default_opts()
+    o.workspace = ctypes.c_void_p(4096)
+    o.workspace_bytes = 1 << 30
+    assert L.randqlp_factor_noalloc(dummy, 100, 80, 5, 2, 1, 0, dummy, dummy, dummy,
+                                    ctypes.byref(o)) == 1
+    assert "workspace" in L.randqlp_last_error().decode()
+    m = n = 20000
+    assert rq.workspace_size(m, n, 500, 20, 2) > rq.NOALLOC_SCRATCH_BYTES
+    st = L.randqlp_factor_noalloc(dummy, m, n, 500, 20, 2, 0, dummy, dummy, dummy, None)
+    assert st == 4
+    assert "static scratch" in L.randqlp_last_error().decode()
+
+
 def test_step_entry_points_validate(L):
     dummy = ctypes.c_void_p(16)
     assert L.randqlp_gaussian(dummy, 10, 3, 5, 0, 0, 0, None) == 1          # ld < m
