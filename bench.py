@@ -28,6 +28,13 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def _plain(o):
+    """JSON fallback for numpy scalars."""
+    if hasattr(o, "item"):
+        return o.item()
+    raise TypeError(f"not JSON serialisable: {type(o).__name__}")
+
+
 # Sources of the product kernel: a traffic measurement is only reported
 # while they are unchanged since the counters were taken.
 KERNEL_SOURCES = ["paper_2110_01011_amd/csrc/gemm.hip"]
@@ -75,9 +82,25 @@ def copy_calibration(mib):
     del src, dst
 
 
+def host_cpu():
+    """Host facts for the CPU baseline: logical CPUs, the ones this process
+    may run on, and the CPU model."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
 def cpu_baseline(A, k, p, q, flops, budget_s=15.0, max_reps=40):
-    """The fp64 oracle on the host cores, on whole factorisations of A."""
-    from threadpoolctl import threadpool_info
+    """The fp64 oracle on the host cores, on whole factorisations of A; then
+    one factorisation on a single BLAS thread."""
+    from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import randqlp, rel_error
     threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
     times, e = [], None
@@ -90,22 +113,16 @@ def cpu_baseline(A, k, p, q, flops, budget_s=15.0, max_reps=40):
             e = rel_error(A, Q, L, P)
         log(f"  oracle rep {len(times)}: {times[-1]:.2f} s")
     t = sorted(times)[len(times) // 2]
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        randqlp(A, k, p, q, seed=0)
+        t1 = time.perf_counter() - t0
+    log(f"  oracle on 1 thread: {t1:.2f} s")
     return {"value": flops / t / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(times)} whole fp64 factorisations of the same {A.shape[0]}x{A.shape[1]} "
-                      f"matrix (median {t:.2f} s each, Omega generation included)"}, e
-
-
-def gpu_svd_matrix(n, sigma, gen):
-    """A = U diag(sigma) V^T (n x n, fp64, column-major) with Haar U, V from
-    the QR of seeded Gaussian matrices, generated on the device."""
-    import torch
-    U, R = torch.linalg.qr(torch.randn(n, n, dtype=torch.float64, device="cuda", generator=gen))
-    U *= torch.sign(torch.diagonal(R))[None, :]
-    V, R = torch.linalg.qr(torch.randn(n, n, dtype=torch.float64, device="cuda", generator=gen))
-    V *= torch.sign(torch.diagonal(R))[None, :]
-    A = (U * sigma[None, :]) @ V.T
-    del U, V, R
-    return A.t().contiguous().t()
+                      f"matrix on {threads} BLAS threads (median {t:.2f} s each, Omega "
+                      f"generation included)",
+            "host": host_cpu(), "one_thread": {"s": round(t1, 3), "value": flops / t1 / 1e9}}, e
 
 
 def device_rel_error(A, Q, L, P):
@@ -122,6 +139,8 @@ def headline(rq, A_c2, k, p, steps, precision="bf16"):
     the bf16 form used: "bf16" or "bf16x3"."""
     import numpy as np
     import torch
+
+    import workloads as W
     wpath = os.path.join(ROOT, "paper_2110_01011_amd", "qpredictor.npy")
     if not os.path.exists(wpath):
         return None
@@ -132,8 +151,9 @@ def headline(rq, A_c2, k, p, steps, precision="bf16"):
     j = torch.arange(1, n + 1, dtype=torch.float64, device="cuda")
     cases = [("rank-200 + noise", A_c2)]
     log("generating the poly / exp evaluation matrices on the device")
-    cases.append(("poly sigma_j = j^-1", gpu_svd_matrix(n, j ** -1.0, gen)))
-    cases.append(("exp sigma_j = exp(-(j-1)/100)", gpu_svd_matrix(n, torch.exp(-(j - 1) / 100.0), gen)))
+    cases.append(("poly sigma_j = j^-1", rq.colmajor(W.device_svd_matrix(n, n, j ** -1.0, gen))))
+    cases.append(("exp sigma_j = exp(-(j-1)/100)",
+                  rq.colmajor(W.device_svd_matrix(n, n, torch.exp(-(j - 1) / 100.0), gen))))
     out = []
 
     def timed(fn):
@@ -146,7 +166,9 @@ def headline(rq, A_c2, k, p, steps, precision="bf16"):
         return (time.perf_counter() - t0) / steps, r
 
     for name, A in cases:
-        A32 = rq.colmajor(A.float().t().contiguous().t())
+        # the precision form takes A in fp32: the cast from the fp64 matrix is
+        # timed on its own and reported beside the speedup
+        tcast, A32 = timed(lambda: rq.colmajor(A.float().t().contiguous().t()))
         t64, (Q, L, P) = timed(lambda: rq.factor(A, k, p, 2, 0))
         e64 = device_rel_error(A, Q, L, P)
         ta, (Q, L, P, info, ai) = timed(lambda: rq.factor_auto(A32, k, p, 0, th, q_fallback=2,
@@ -155,53 +177,58 @@ def headline(rq, A_c2, k, p, steps, precision="bf16"):
         ea = device_rel_error(A, Q, L, P)
         out.append({"matrix": name, "fp64_q2_per_s": round(1.0 / t64, 2),
                     "bf16_learned_per_s": round(1.0 / ta, 2), "speedup": round(t64 / ta, 3),
+                    "cast_f64_to_f32_ms": round(tcast * 1e3, 4),
+                    "speedup_with_cast": round(t64 / (ta + tcast), 3),
                     "e_fp64_q2": e64, "e_bf16_learned": ea, "error_ratio": ea / e64,
                     "q_predicted": ai["q_predicted"], "q_used": ai["q_used"],
                     "resumed": ai["resumed"], "judge_ratio": ai["judge_ratio"]})
         log(f"  {out[-1]}")
         del A32
     sp = [c["speedup"] for c in out]
+    spc = [c["speedup_with_cast"] for c in out]
     return {"metric": "factorisations/s, bf16 precision form + learned q vs plain fp64 q = 2",
             "precision": precision, "workload": f"{n}x{n}, k={k} p={p}", "cases": out,
+            "input": "fp64 A for the fp64 method; fp32 A (cast from the fp64 A outside the "
+                     "timed call, cast time reported) for the precision form",
             "speedup_geomean": float(np.exp(np.mean(np.log(sp)))),
+            "speedup_with_cast_geomean": float(np.exp(np.mean(np.log(spc)))),
             "errors_within_1.05": all(c["error_ratio"] <= 1.05 for c in out)}
 
 
-def workload_c3(args):
+def c3_leg(steps, warmup, oracle=True):
     """Precision form: 20000 x 16000, sigma_i = exp(-i/100) (rank 4000, Haar
-    factors), k = 500, p = 20, q = 2 (d = 520); fp64, fp32, bf16, fp16 and
-    bf16x3 (bf16 with the split bf16 final projection) forms, each with its
-    error against the fp64 form's value for the same matrix."""
+    factors), k = 500, p = 20, q = 2 (d = 520).  Each form (bf16x3, bf16,
+    f16, fp32, fp64) is timed on the resident matrix and its error
+    ||A - Q L P^T||_F / ||A||_F is computed in fp64 against the fp64 A; the
+    fp64 oracle factors the same matrix on the host and every form's error
+    is divided by the oracle's."""
     import torch
 
     import paper_2110_01011_amd as rq
-    from paper_2110_01011_amd.metrics import PEAK_TFLOPS, randqlp_flops
+    import workloads as W
+    from paper_2110_01011_amd.metrics import randqlp_flops
     m, n, r, k, p, q = 20000, 16000, 4000, 500, 20, 2
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(3)
-    log("generating the 20000 x 16000 exp-decay matrix on the device")
-    U, _ = torch.linalg.qr(torch.randn(m, r, dtype=torch.float64, device="cuda", generator=gen))
-    V, _ = torch.linalg.qr(torch.randn(n, r, dtype=torch.float64, device="cuda", generator=gen))
-    sig = torch.exp(-torch.arange(1, r + 1, dtype=torch.float64, device="cuda") / 100.0)
-    A64 = rq.colmajor(((U * sig) @ V.T).t().contiguous().t())
-    del U, V
+    log("c3: generating the 20000 x 16000 exp-decay matrix on the device")
+    A64 = rq.colmajor(W.device_exp_decay(m, n, r, 100.0, seed=3))
     A32 = rq.colmajor(A64.float().t().contiguous().t())
+    torch.cuda.synchronize()
     d = rq.sketch_width(m, n, k, p)
     flops = randqlp_flops(m, n, d, q)
-    opt = float(torch.sqrt(torch.sum(sig[d:] ** 2)).item() / torch.linalg.norm(sig).item())
+    sig = torch.exp(-torch.arange(1, r + 1, dtype=torch.float64) / 100.0)
+    opt = float(torch.sqrt(torch.sum(sig[d:] ** 2)) / torch.linalg.norm(sig))
     forms = {}
-    for prec in ("f64", "f32", "bf16", "f16", "bf16x3"):
+    for prec in ("bf16x3", "bf16", "f16", "f32", "f64"):
         A = A64 if prec == "f64" else A32
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             rq.factor(A, k, p, q, 0, precision=prec)
         torch.cuda.synchronize()
         rq.profile_read()
         rq.profile_enable(True)
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             Q, L, P = rq.factor(A, k, p, q, 0, precision=prec)
         torch.cuda.synchronize()
-        t = (time.perf_counter() - t0) / args.steps
+        t = (time.perf_counter() - t0) / steps
         rq.profile_enable(False)
         kms, nl, kfl, kby = rq.profile_read()
         e = device_rel_error(A64, Q, L, P)
@@ -209,86 +236,131 @@ def workload_c3(args):
                        "products_avg_ms": round(kms / max(nl, 1), 4),
                        "products_tflops": round(kfl / max(kms, 1e-9) / 1e9, 2),
                        "e": e, "e_over_eckart_young_d": e / opt}
-        log(f"  {prec}: {forms[prec]}")
+        log(f"  c3 {prec}: {forms[prec]}")
         del Q, L, P
-    ref = forms["f64"]["e"]
-    for prec in forms:
-        forms[prec]["e_over_fp64"] = forms[prec]["e"] / ref
-    b = forms["bf16x3"]
-    print(json.dumps({
-        "metric": "Rand-QLP GFLOP/s, precision form (bf16 products, split bf16 projection) vs fp64",
-        "value": b["gflops"],
-        "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": b["ms_per_step"], "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16+f32+f64", "data": "synthetic",
-        "config": {"workload": f"exp-decay sigma_i = exp(-i/100), rank {r}, {m}x{n}, "
-                               f"k={k} p={p} q={q} (d={d}), precision form",
-                   "flops_per_step": flops},
-        "forms": forms}), flush=True)
+    out = {"workload": f"exp-decay sigma_i = exp(-i/100), rank {r}, {m}x{n}, "
+                       f"k={k} p={p} q={q} (d={d})",
+           "flops_per_step": flops, "steps": steps, "warmup": warmup, "forms": forms}
+    if oracle:
+        from oracle import randqlp, rel_error
+        from threadpoolctl import threadpool_info
+        log("c3: fp64 oracle on the host")
+        Ah = A64.cpu().numpy()          # column-major fp64 (a Fortran-ordered array)
+        t0 = time.perf_counter()
+        Qo, Lo, Po = randqlp(Ah, k, p, q, seed=0)
+        to = time.perf_counter() - t0
+        e_o = rel_error(Ah, Qo, Lo, Po)
+        del Ah, Qo, Lo, Po
+        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
+        out["oracle"] = {"e": e_o, "s": round(to, 2), "threads": threads}
+        for prec in forms:
+            forms[prec]["e_over_oracle"] = forms[prec]["e"] / e_o
+        out["errors_within_1.05_of_oracle"] = all(f["e_over_oracle"] <= 1.05
+                                                  for f in forms.values())
+        log(f"  c3 oracle: e={e_o:.6e} in {to:.1f} s; ratios "
+            f"{ {p_: round(f['e_over_oracle'], 5) for p_, f in forms.items()} }")
+    del A64, A32
+    torch.cuda.empty_cache()
+    return out
 
 
-def workload_batched(args):
-    """Batched form: 512 matrices, m, n uniform in 256..4096, sigma_j = j^-alpha
-    with alpha uniform in [0.5, 3] and Haar factors, k uniform in 8..128,
-    p = 10, q = 2, fp32; grouped launches replayed from a HIP graph, tuned
-    tile widths; against the same matrices factored one call at a time."""
+def c4_leg(steps, warmup, sample=16):
+    """Batched form: 512 matrices, m, n uniform in 256..4096, sigma_j =
+    j^-alpha with alpha uniform in [0.5, 3] and Haar factors, k uniform in
+    8..128, p = 10, q = 2, fp32; grouped launches replayed from a HIP graph,
+    tuned tile widths.  A seeded sample of the matrices is factored by the
+    fp64 oracle (on the same fp32 values) and each error is compared."""
     import numpy as np
     import torch
 
     import paper_2110_01011_amd as rq
+    import workloads as W
+    from oracle import randqlp, rel_error
     from paper_2110_01011_amd.metrics import PEAK_HBM_GBS, PEAK_TFLOPS, randqlp_flops
     count, p, q = 512, 10, 2
-    r = np.random.default_rng(0)
-    specs = [(int(r.integers(256, 4097)), int(r.integers(256, 4097)), int(r.integers(8, 129)),
-              float(r.uniform(0.5, 3.0))) for _ in range(count)]
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(0)
-    log("generating 512 matrices on the device")
-    As = []
-    for (m, n, k, a) in specs:
-        rr = min(m, n)
-        U, _ = torch.linalg.qr(torch.randn(m, rr, device="cuda", generator=gen))
-        V, _ = torch.linalg.qr(torch.randn(n, rr, device="cuda", generator=gen))
-        s = torch.arange(1, rr + 1, device="cuda", dtype=torch.float32) ** (-a)
-        As.append(rq.colmajor(((U * s) @ V.T).t().contiguous().t()))
-        del U, V
+    log("c4: generating 512 matrices on the device")
+    t0 = time.perf_counter()
+    As, specs = W.device_batch(count, seed=0)
     torch.cuda.synchronize()
-    ks = [sp[2] for sp in specs]
+    tgen = time.perf_counter() - t0
+    ks = [sp["k"] for sp in specs]
     seeds = list(range(count))
     F, roof = 0.0, 0.0
-    for (m, n, k, a) in specs:
-        d = min(k + p, m, n)
-        f = randqlp_flops(m, n, d, q)
+    for sp in specs:
+        m, n = sp["m"], sp["n"]
+        dd = min(sp["k"] + p, m, n)
+        f = randqlp_flops(m, n, dd, q)
         F += f
         roof += max(f / (PEAK_TFLOPS["f32"] * 1e12), (2 * q + 3) * m * n * 4 / (PEAK_HBM_GBS * 1e9))
     b = rq.Batch(As, ks, p, q, seeds, tune=True)
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         b.run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         b.run()
     torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / args.steps
+    t = (time.perf_counter() - t0) / steps
     info = b.info()
+    log(f"c4: {t * 1e3:.2f} ms per batch; oracle check on {sample} matrices")
+    pick = sorted(np.random.Generator(np.random.Philox(key=[2024, 4])).choice(count, sample,
+                                                                              replace=False))
+    checks = []
+    for i in pick:
+        i = int(i)
+        Ah = As[i].double().cpu().numpy()
+        Qg, Lg, Pg = (x.double().cpu().numpy() for x in (b.Q[i], b.L[i], b.P[i]))
+        e_g = rel_error(Ah, Qg, Lg, Pg)
+        e_o = rel_error(Ah, *randqlp(Ah, ks[i], p, q, seeds[i]))
+        checks.append({"i": i, "m": specs[i]["m"], "n": specs[i]["n"], "k": ks[i],
+                       "alpha": round(specs[i]["alpha"], 3), "e": e_g, "e_oracle": e_o,
+                       "ratio": e_g / e_o})
+    b.close()
     t0 = time.perf_counter()
     for A, k, sd in zip(As, ks, seeds):
         rq.factor(A, k, p, q, sd)
     torch.cuda.synchronize()
     tseq = time.perf_counter() - t0
-    b.close()
+    ratios = [c["ratio"] for c in checks]
+    log(f"  c4 error ratios vs oracle: max {max(ratios):.5f}")
+    del As
+    torch.cuda.empty_cache()
+    return {"workload": "512 matrices, m, n ~ U{256..4096}, sigma_j = j^-alpha, "
+                        "alpha ~ U[0.5, 3], k ~ U{8..128}, p=10, q=2, fp32",
+            "flops_per_step": F, "ms_per_step": round(t * 1e3, 3),
+            "gflops": round(F / t / 1e9, 1), "steps": steps, "warmup": warmup,
+            "roofline": {"bound": "sum over matrices of max(flops / fp32 peak, bytes / HBM peak)",
+                         "roof_ms": round(roof * 1e3, 3), "frac": round(roof / t, 4)},
+            "sequential_ms": round(tseq * 1e3, 2), "speedup_vs_sequential": round(tseq / t, 2),
+            "generation_s": round(tgen, 1), "plan": info,
+            "oracle_sample": {"count": sample, "max_ratio": max(ratios),
+                              "errors_within_1.05_of_oracle": max(ratios) <= 1.05,
+                              "cases": checks}}
+
+
+def workload_c3(args):
+    """`--workload c3`: the precision-form leg as its own JSON line."""
+    r = c3_leg(args.steps, args.warmup, oracle=not args.no_cpu_baseline)
+    b = r["forms"]["bf16x3"]
     print(json.dumps({
-        "metric": "Rand-QLP GFLOP/s, batched form", "value": round(F / t / 1e9, 1),
-        "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(t * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "metric": "Rand-QLP GFLOP/s, precision form (bf16 products, split bf16 projection) vs fp64",
+        "value": b["gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": b["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f32+f64", "data": "synthetic",
+        "config": {"workload": r["workload"] + ", precision form",
+                   "flops_per_step": r["flops_per_step"]}, "c3": r}), flush=True)
+
+
+def workload_batched(args):
+    """`--workload batched`: the batched leg as its own JSON line."""
+    r = c4_leg(args.steps, args.warmup)
+    print(json.dumps({
+        "metric": "Rand-QLP GFLOP/s, batched form", "value": r["gflops"], "unit": "GFLOP/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "512 matrices, m, n ~ U{256..4096}, sigma_j = j^-alpha, "
-                               "alpha ~ U[0.5, 3], k ~ U{8..128}, p=10, q=2, fp32",
-                   "flops_per_step": F},
-        "roofline": {"bound": "sum over matrices of max(flops / fp32 peak, bytes / HBM peak)",
-                     "roof_ms": round(roof * 1e3, 3), "frac": round(roof / t, 4)},
-        "sequential_ms": round(tseq * 1e3, 2), "speedup_vs_sequential": round(tseq / t, 2),
-        "plan": info}), flush=True)
+        "config": {"workload": r["workload"], "flops_per_step": r["flops_per_step"]},
+        "c4": r}, default=_plain), flush=True)
 
 
 def main():
@@ -300,6 +372,8 @@ def main():
     ap.add_argument("--size", type=int, default=8000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-headline", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 20000 x 16000 precision-form leg")
+    ap.add_argument("--no-c4", action="store_true", help="skip the 512-matrix batched leg")
     ap.add_argument("--workload", choices=["c2", "c3", "batched"], default="c2",
                     help="c2 (default): 8000 x 8000 rank-200 + noise; c3: the precision form "
                          "at 20000 x 16000; batched: 512 uneven matrices")
@@ -375,6 +449,11 @@ def main():
     if not args.no_headline and args.precision == "f64" and args.size == 8000:
         log("headline: bf16 + learned q vs fp64 q = 2")
         head = headline(rq, Ad, k, p, max(3, args.steps // 4), precision="bf16x3")
+    c3 = c4 = None
+    if not args.no_c3 and args.precision == "f64" and args.size == 8000:
+        c3 = c3_leg(3, 1, oracle=not args.no_cpu_baseline)
+    if not args.no_c4 and args.precision == "f64" and args.size == 8000:
+        c4 = c4_leg(5, 1)
     cpu = None
     e_orc = None
     if not args.no_cpu_baseline:
@@ -401,8 +480,10 @@ def main():
         "error": {"e_gpu": e_gpu, "e_oracle": e_orc,
                   "ratio": (e_gpu / e_orc) if e_orc else None},
         "headline": head,
+        "c3": c3,
+        "c4": c4,
     }
-    print(json.dumps(out), flush=True)
+    print(json.dumps(out, default=_plain), flush=True)
 
 
 if __name__ == "__main__":

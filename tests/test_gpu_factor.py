@@ -192,3 +192,33 @@ def test_c2_full_size_parity(rq):
     e32 = rel_error(A, Q32, L32, P32)
     log(f"  C2 f32 e={e32} oracle e={e_o}")
     assert e32 <= 1.05 * e_o
+
+
+@pytest.mark.slow
+def test_c3_full_size_precision_forms_vs_oracle(rq):
+    """20000 x 16000, sigma_i = exp(-i/100) (rank 4000), k = 500, p = 20,
+    q = 2 (d = 520): the fp64 form at the fp64 bar against the oracle on the
+    same matrix; the bf16x3, bf16, f16 and fp32 forms within 1.05x the
+    oracle's error (computed in fp64 against the fp64 A)."""
+    import torch
+    log("factor C3 20000x16000 k=500 p=20 q=2 (d=520): generating on the device")
+    A64 = rq.colmajor(W.device_exp_decay(20000, 16000, 4000, 100.0, seed=3))
+    Ah = A64.cpu().numpy()
+    log("  oracle")
+    Qo, Lo, Po = randqlp(Ah, 500, 20, 2, 0)
+    e_o = rel_error(Ah, Qo, Lo, Po)
+    Qg, Lg, Pg, info = rq.factor(A64, 500, 20, 2, 0, return_info=True)
+    Qg, Lg, Pg = to_np(Qg), to_np(Lg), to_np(Pg)
+    c = compare(Ah, Qg, Lg, Pg, Qo, Lo, Po, 500)
+    log(f"  fp64: {c} {info}")
+    assert c["de"] <= TOL and c["dsigma"] <= TOL
+    assert c["sinQk"] <= TOL and c["sinPk"] <= TOL and c["sinQ"] <= TOL and c["sinP"] <= TOL
+    del Qg, Lg, Pg
+    A32 = rq.colmajor(A64.float().t().contiguous().t())
+    nrm = torch.linalg.norm(A64)
+    for prec in ("bf16x3", "bf16", "f16", "f32"):
+        Q, L, P = rq.factor(A32, 500, 20, 2, 0, precision=prec)
+        e_g = float(torch.linalg.norm(A64 - Q.double() @ (L @ P.double().T)) / nrm)
+        log(f"  {prec}: e={e_g:.6e} oracle {e_o:.6e} ratio {e_g / e_o:.5f}")
+        assert e_g <= 1.05 * e_o
+        del Q, L, P

@@ -117,3 +117,56 @@ def batch_specs(count, seed, lo=256, hi=4096, alpha=(0.5, 3.0), kr=(8, 128)):
         out.append({"m": int(g.integers(lo, hi + 1)), "n": int(g.integers(lo, hi + 1)),
                     "alpha": float(g.uniform(*alpha)), "k": int(g.integers(kr[0], kr[1] + 1))})
     return out
+
+
+# ---- device-side generators (torch on the GPU) for the large workloads ----
+# Same families as above, drawn with torch's device generator so that the
+# 20000 x 16000 and batched workloads need no host-side QR.  They return
+# column-major device tensors (stride (1, rows)).
+
+def _device_haar(rows, cols, gen, dtype):
+    import torch
+    g = torch.randn(rows, cols, dtype=dtype, device="cuda", generator=gen)
+    q, r = torch.linalg.qr(g)
+    s = torch.sign(torch.diagonal(r))
+    s[s == 0] = 1.0
+    return q * s[None, :]
+
+
+def device_svd_matrix(m, n, sigma, gen, dtype=None):
+    """A = U diag(sigma) V^T on the device with Haar U (m x r), V (n x r)
+    from the sign-fixed QR of torch Gaussians drawn from `gen`."""
+    import torch
+    dtype = dtype or torch.float64
+    sigma = sigma.to(device="cuda", dtype=dtype)
+    r = sigma.numel()
+    U = _device_haar(m, r, gen, dtype)
+    V = _device_haar(n, r, gen, dtype)
+    A = (V * sigma[None, :]) @ U.T          # A^T (n x m), row-major = A column-major
+    del U, V
+    return A.t()
+
+
+def device_exp_decay(m, n, r, tau, seed):
+    """exp_decay on the device: sigma_i = exp(-i / tau), i = 1..r, fp64."""
+    import torch
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(int(seed))
+    sig = torch.exp(-torch.arange(1, r + 1, dtype=torch.float64) / float(tau))
+    return device_svd_matrix(m, n, sig, gen)
+
+
+def device_batch(count, seed, lo=256, hi=4096, alpha=(0.5, 3.0), kr=(8, 128)):
+    """The batched workload on the device, fp32: specs from batch_specs and,
+    per matrix, sigma_j = j^-alpha (j = 1..min(m, n)) with Haar factors.
+    Returns (list of column-major float32 device tensors, specs)."""
+    import torch
+    specs = batch_specs(count, seed, lo, hi, alpha, kr)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(int(seed))
+    As = []
+    for sp in specs:
+        r = min(sp["m"], sp["n"])
+        sig = torch.arange(1, r + 1, dtype=torch.float32) ** (-sp["alpha"])
+        As.append(device_svd_matrix(sp["m"], sp["n"], sig, gen, torch.float32))
+    return As, specs
