@@ -29,6 +29,17 @@ the plain fp64 definitions that its training data and tests rest on.
   e_k(q) <= 1.05 ||sigma_{>k}||_2 / ||sigma||_2 (1.05 x the Eckart-Young
   optimum; errors below the 4e-8 floor of the identity count as met), else
   qmax + 1 ("unreachable").
+* ``label_rank`` -- the rank half of the predictor: for a tolerance tol on
+  the relative Frobenius error of the rank-k approximation, the smallest k
+  of the classes 8, 16, ..., 256 whose Eckart-Young error
+  ||sigma_{>k}|| / ||sigma|| is at most tol / 1.05 (else the last class).
+  A rank-k QLP approximation run with the q that label_q asks for is within
+  1.05 x that optimum, so the pair (k, q) meets tol.  The rank network
+  reads the same 64 sketch features with rank_feature(tol) in place of
+  k / 256.
+* ``rank_errors`` -- e_k = ||A - Q L[:, :k] P[:, :k]^T||_F / ||A||_F for
+  k = 1..d, written out with the dense residual (the plain definition), and
+  ``smallest_rank`` -- the first k with e_k <= tol.
 """
 import numpy as np
 
@@ -37,6 +48,8 @@ from .randqlp import qr_pos, sketch_width
 
 NFEAT_SIGMA = 64
 FEAT_CLAMP = 6.0
+RANK_CLASSES = (8, 16, 32, 64, 128, 256)
+RANK_SLACK = 1.05
 ERR_FLOOR = 4e-8   # ~2 sqrt(u): resolution of 1 - ||A^T Q||^2 / ||A||^2
 
 
@@ -134,4 +147,42 @@ def label_q(errs, sigma, k, slack=1.05):
     for j, e in enumerate(errs):
         if e <= target:
             return j
+    return len(errs)
+
+
+def rank_feature(tol):
+    """The rank network's last input: -log10(tol) clamped to [0, 6], / 6."""
+    return float(np.clip(-np.log10(tol), 0.0, FEAT_CLAMP) / FEAT_CLAMP)
+
+
+def rank_features(feat, tol):
+    """Rank-network input from the predictor's features (the 64 spectrum
+    values, then rank_feature(tol))."""
+    feat = np.asarray(feat, dtype=np.float64)
+    return np.concatenate([feat[:NFEAT_SIGMA], [rank_feature(tol)]])
+
+
+def label_rank(sigma, tol, classes=RANK_CLASSES, slack=RANK_SLACK):
+    """Smallest class c with optimal_error(sigma, classes[c]) <= tol / slack;
+    the last class if none."""
+    for c, k in enumerate(classes):
+        if optimal_error(sigma, k) <= tol / slack:
+            return c
+    return len(classes) - 1
+
+
+def rank_errors(A, Q, L, P):
+    """e_k for k = 1..d from the dense residual of each truncation."""
+    A = np.asarray(A, dtype=np.float64)
+    nrm = np.linalg.norm(A)
+    d = L.shape[0]
+    return np.array([np.linalg.norm(A - Q @ (L[:, :k] @ P[:, :k].T)) / nrm
+                     for k in range(1, d + 1)])
+
+
+def smallest_rank(errs, tol):
+    """First k (1-based) with errs[k - 1] <= tol, or len(errs) if none."""
+    for i, e in enumerate(errs):
+        if e <= tol:
+            return i + 1
     return len(errs)

@@ -131,3 +131,50 @@ def test_mlp_learns_a_separable_rule():
         loss, g = mlp.loss_and_grad(theta, X, y)
         theta, m, v = mlp.adam_step(theta, g, m, v, t, 3e-3)
     assert np.mean(mlp.predict(theta, X) == y) > 0.97
+
+
+def test_label_rank_on_a_step_spectrum():
+    """sigma = 1 on the first r values, 0 after: the rank-k optimum is
+    sqrt((r - k) / r) for k < r (closed form), so for r = 40 and tol = 0.5
+    the first class with sqrt((40 - k) / 40) <= 0.5 / 1.05 is k = 32."""
+    from oracle.learned import RANK_CLASSES, label_rank
+    s = np.concatenate([np.ones(40), np.zeros(60)])
+    for k in (8, 16, 32, 39):
+        assert abs(optimal_error(s, k) - np.sqrt((40 - k) / 40)) < 1e-15
+    assert RANK_CLASSES[label_rank(s, 0.5)] == 32
+    assert RANK_CLASSES[label_rank(s, 0.9)] == 16     # sqrt(32/40) = 0.894 > 0.9 / 1.05
+    assert RANK_CLASSES[label_rank(s, 0.95)] == 8     # 0.894 <= 0.95 / 1.05 = 0.905
+    assert label_rank(s, 1e-9) == 3                   # k = 64 >= r: error 0
+    assert label_rank(np.arange(1, 2001) ** -0.3, 1e-3) == len(RANK_CLASSES) - 1
+
+
+def test_label_rank_matches_brute_force_truncation():
+    """On small matrices: the truncation error of the SVD (numpy's, an
+    independent routine) at each class k decides the label the same way."""
+    from oracle.learned import RANK_CLASSES, RANK_SLACK, label_rank
+    for alpha, tol in [(0.8, 0.2), (1.5, 0.05), (2.5, 0.01), (0.5, 0.3)]:
+        A, U, s, V = W.poly_decay(300, 280, alpha, seed=17)
+        u, sv, vt = np.linalg.svd(A)
+        errs = [np.linalg.norm(A - (u[:, :k] * sv[:k]) @ vt[:k]) / np.linalg.norm(A)
+                for k in RANK_CLASSES]
+        want = next((c for c, e in enumerate(errs) if e <= tol / RANK_SLACK),
+                    len(RANK_CLASSES) - 1)
+        assert label_rank(s, tol) == want
+
+
+def test_rank_errors_and_smallest_rank():
+    """Dense rank-k errors of the oracle's factors against the orthogonal
+    split e_k^2 = e^2 + ||L[k:, k:]||^2 / ||A||^2, and the first k under a
+    tolerance."""
+    from oracle.learned import rank_errors, smallest_rank
+    A, U, s, V = W.poly_decay(220, 160, 1.3, seed=5)
+    Q, L, P = randqlp(A, 20, 5, 1, 3)
+    ek = rank_errors(A, Q, L, P)
+    nrm2 = np.sum(A * A)
+    e2 = rel_error(A, Q, L, P) ** 2
+    for k in (1, 7, 25):
+        assert abs(ek[k - 1] - np.sqrt(e2 + np.sum(L[k:, k:] ** 2) / nrm2)) < 1e-12
+    assert np.all(np.diff(ek) <= 1e-15)
+    tol = float(ek[9])
+    assert smallest_rank(ek, tol) == 10
+    assert smallest_rank(ek, 0.0) == 25
