@@ -103,9 +103,14 @@ typedef struct {
   void* workspace;         /* device scratch; NULL = library-managed cache */
   size_t workspace_bytes;  /* size of workspace when given                 */
   rqlp_info* info;         /* optional host struct filled on return        */
+  /* randqlp_factor_auto with k <= 0 (the rank is predicted) only:          */
+  double tol;              /* target relative Frobenius error of the rank-k
+                              approximation Q L[:, :k] P[:, :k]^T, in (0, 1] */
+  int32_t k_max;           /* largest rank: Q, L, P hold min(k_max + p, m, n)
+                              columns                                       */
 } rqlp_opts;
 
-/* ---- Learned power-iteration predictor ----
+/* ---- Learned power-iteration and rank predictor ----
  * A small MLP (fp32) reads the spectrum of a cheap sketch and predicts how
  * many power rounds the method needs.  Input: 65 features, the singular
  * values of the 64-column sketch A^T Omega[:, :64] (the leading columns of
@@ -114,7 +119,13 @@ typedef struct {
  * Network: 65 -> 128 (ReLU) -> 128 (ReLU) -> 6 logits, class c = q for
  * c = 0..4 and c = 5 for "more than 4".  Parameters: one float vector
  * [W1 b1 W2 b2 W3 b3], each W (fan_in x fan_out) stored column by column.
- * Activations and feature rows are row-major (one sample contiguous). */
+ * Activations and feature rows are row-major (one sample contiguous).
+ * The rank network has the same shape and layout: the same 64 spectrum
+ * features, then clamp(-log10(tol), 0, 6) / 6 for the target error tol, and
+ * class c means rank k = 8 * 2^c (8 ... 256); it is trained to pick the
+ * smallest class whose optimal rank-k error (Eckart-Young, ||sigma_{>k}|| /
+ * ||sigma||) is at most tol / 1.05, so that the rank-k QLP approximation
+ * with enough power rounds (within 1.05x of that optimum) meets tol. */
 #define RQLP_MLP_INPUTS 65
 #define RQLP_MLP_HIDDEN 128
 #define RQLP_MLP_CLASSES 6
@@ -129,6 +140,15 @@ typedef struct {
   double judge_ratio;  /* the judge's statistic Delta / e^2 (0 if not run)    */
   double est_rel_err;  /* sqrt(1 - ||L||_F^2 / ||A||_F^2) for the q_predicted
                           factors, when judged                                */
+  int32_t k_predicted; /* k <= 0: the rank network's k_hat; else k            */
+  int32_t k_used;      /* k <= 0: smallest k whose rank-k approximation of the
+                          returned factors meets tol (d if none does); else k */
+  int32_t d;           /* columns of the returned Q, P (and order of L)       */
+  int32_t rank_fallback; /* k <= 0: 1 if no rank <= d met tol and the method
+                          was rerun with k_max and q_fallback                 */
+  double rank_err;     /* k <= 0: error of the rank-k_used approximation, from
+                          sqrt(1 - ||L[:, :k]||_F^2 / ||A||_F^2) (resolves
+                          errors down to about 1e-8)                          */
 } rqlp_auto_info;
 
 /* Fill *opts with defaults: F64, AUTO, tight leading dimensions, null
@@ -221,6 +241,20 @@ rqlp_status randqlp_factor_auto(const void* A, int64_t m, int64_t n, int k, int 
                                 int q_fallback, uint64_t seed, const float* params, void* Q,
                                 void* L, void* P, const rqlp_opts* opts,
                                 rqlp_auto_info* ainfo);
+/* ... and with k <= 0 the rank is predicted as well (Section 5.2's rank-k
+ * approximations Q L[:, :k] P[:, :k]^T; the tracking of the singular values
+ * by diag L is what makes a truncation of the factors rank-revealing).
+ * params then holds 2 * RQLP_MLP_PARAMS floats (the power-round network,
+ * then the rank network), opts must be given with tol and k_max, and Q, L,
+ * P must hold min(k_max + p, m, n) columns.  Steps: Omega, the 64-column
+ * feature sketch, the rank network -> k_hat = min(8 * 2^c, k_max), the
+ * power-round network with k_hat in its last input -> q_hat; then the
+ * method with d = min(k_hat + p, m, n) columns and q_hat judged as above.
+ * The returned factors are checked: k_used is the smallest k <= d whose
+ * rank-k error meets tol; if none does (and d or q was below k_max + p,
+ * q_fallback), the plain method reruns with k_max and q_fallback and is
+ * checked the same way.  ainfo->d gives the returned width (leading d
+ * columns of Q and P, leading d x d block of L); k_max + p <= 4096. */
 
 /* The predictor's 65 features of A (m x n, lda; precision RQLP_F64 or
  * RQLP_F32 = the type of A) into feat (device, 65 floats).  Synchronous. */

@@ -63,7 +63,10 @@ MLP_INPUTS, MLP_HIDDEN, MLP_CLASSES, MLP_PARAMS = 65, 128, 6, 25734
 class AutoInfo(ctypes.Structure):
     _fields_ = [("q_predicted", ctypes.c_int32), ("q_used", ctypes.c_int32),
                 ("judged", ctypes.c_int32), ("resumed", ctypes.c_int32),
-                ("judge_ratio", ctypes.c_double), ("est_rel_err", ctypes.c_double)]
+                ("judge_ratio", ctypes.c_double), ("est_rel_err", ctypes.c_double),
+                ("k_predicted", ctypes.c_int32), ("k_used", ctypes.c_int32),
+                ("d", ctypes.c_int32), ("rank_fallback", ctypes.c_int32),
+                ("rank_err", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -83,7 +86,8 @@ class Opts(ctypes.Structure):
                 ("lda", ctypes.c_int64), ("ldq", ctypes.c_int64), ("ldl", ctypes.c_int64),
                 ("ldp", ctypes.c_int64), ("stream", ctypes.c_void_p),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
-                ("info", ctypes.POINTER(Info))]
+                ("info", ctypes.POINTER(Info)), ("tol", ctypes.c_double),
+                ("k_max", ctypes.c_int32)]
 
 
 _lib = None
@@ -334,16 +338,28 @@ def factor_noalloc(A, k, p, q, seed, panel="auto", precision=None, return_info=F
 
 
 def factor_auto(A, k, p, seed, params, q_fallback=2, panel="auto", precision=None,
-                return_info=False):
+                return_info=False, tol=None, k_max=256):
     """Rand-QLP with the number of power rounds predicted from a first sketch
     (params: float32 device tensor of MLP_PARAMS), judged one round ahead and
-    resumed up to q_fallback when the prediction was too low.  Uses the
+    resumed up to q_fallback when the prediction was too low.  With k <= 0
+    the rank is predicted too: params then holds 2 * MLP_PARAMS values (the
+    power-round network, then the rank network), tol is the target relative
+    error of the rank-k approximation Q L[:, :k] P[:, :k]^T and k_max the
+    largest rank; the returned factors have auto_info["d"] columns and
+    auto_info["k_used"] is the smallest rank meeting tol.  Uses the
     library's workspace cache.  Returns (Q, L, P) or, with return_info,
     (Q, L, P, info, auto_info)."""
     torch = _torch()
-    if params.dtype != torch.float32 or params.numel() != MLP_PARAMS or not params.is_cuda:
-        raise ValueError("params must be a float32 device tensor of MLP_PARAMS values")
-    A, Q, L, P, o = _prepare(A, k, p, q_fallback, panel, precision)
+    rank = k <= 0
+    want = (2 if rank else 1) * MLP_PARAMS
+    if params.dtype != torch.float32 or params.numel() != want or not params.is_cuda:
+        raise ValueError(f"params must be a float32 device tensor of {want} values")
+    if rank and tol is None:
+        raise ValueError("k <= 0 (predict the rank) needs tol")
+    A, Q, L, P, o = _prepare(A, k_max if rank else k, p, q_fallback, panel, precision)
+    if rank:
+        o.tol = float(tol)
+        o.k_max = int(k_max)
     m, n = A.shape
     info, ainfo = Info(), AutoInfo()
     o.info = ctypes.pointer(info)
@@ -355,6 +371,8 @@ def factor_auto(A, k, p, seed, params, q_fallback=2, panel="auto", precision=Non
                                          ctypes.c_void_p(L.data_ptr()),
                                          ctypes.c_void_p(P.data_ptr()), ctypes.byref(o),
                                          ctypes.byref(ainfo)))
+    d = ainfo.d
+    Q, L, P = Q[:, :d], L[:d, :d], P[:, :d]
     if return_info:
         return Q, L, P, info.as_dict(), ainfo.as_dict()
     return Q, L, P

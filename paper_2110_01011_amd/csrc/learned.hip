@@ -362,16 +362,13 @@ __global__ __launch_bounds__(256) void sum_kernel(const float* __restrict__ x, i
 // activations h1, h2 and the logits.
 constexpr int kNI = RQLP_MLP_INPUTS, kNH = RQLP_MLP_HIDDEN, kNC = RQLP_MLP_CLASSES;
 static_assert(kNI <= kNH && kNC <= kNH, "one thread per hidden unit covers the inputs and logits");
-__global__ __launch_bounds__(kNH) void predict_class_kernel(const float* __restrict__ th,
-                                                            const float* __restrict__ x,
-                                                            float* __restrict__ out,
-                                                            int* __restrict__ cls) {
+// The three layers on xs (shared, kNI floats) into z (shared, kNC logits);
+// the whole workgroup of kNH threads takes part.  h1, h2: shared scratch.
+__device__ void mlp_logits(const float* __restrict__ th, const float* xs, float* h1, float* h2,
+                           float* z) {
   constexpr int oW1 = 0, oB1 = oW1 + kNI * kNH, oW2 = oB1 + kNH, oB2 = oW2 + kNH * kNH,
                 oW3 = oB2 + kNH, oB3 = oW3 + kNH * kNC;
-  __shared__ float xs[kNI], h1[kNH], h2[kNH], z[kNC];
   const int t = threadIdx.x;
-  if (t < kNI) xs[t] = x[t];
-  __syncthreads();
   {
     const float* w = th + oW1 + t * kNI;
     float s = th[oB1 + t];
@@ -393,17 +390,96 @@ __global__ __launch_bounds__(kNH) void predict_class_kernel(const float* __restr
     z[t] = s;
   }
   __syncthreads();
+}
+
+// argmax over the kNC logits (ties to the lower class).
+__device__ int argmax_logits(const float* z) {
+  int best = 0;
+  for (int c = 1; c < kNC; ++c)
+    if (z[c] > z[best]) best = c;
+  return best;
+}
+
+__global__ __launch_bounds__(kNH) void predict_class_kernel(const float* __restrict__ th,
+                                                            const float* __restrict__ x,
+                                                            float* __restrict__ out,
+                                                            int* __restrict__ cls) {
+  __shared__ float xs[kNI], h1[kNH], h2[kNH], z[kNC];
+  const int t = threadIdx.x;
+  if (t < kNI) xs[t] = x[t];
+  __syncthreads();
+  mlp_logits(th, xs, h1, h2, z);
   if (out) {
     out[t] = h1[t];
     out[kNH + t] = h2[t];
     if (t < kNC) out[2 * kNH + t] = z[t];
   }
+  if (t == 0) *cls = argmax_logits(z);
+}
+
+// Rank, then power rounds: the rank network (th_k) reads the 64 spectrum
+// features with rank_feat in the last input and picks class ck, the rank
+// k_hat = min(8 * 2^ck, k_max); the power-round network (th_q) then reads
+// the same spectrum with k_hat / 256 in the last input.  out[0] = q class,
+// out[1] = rank class, out[2] = k_hat.
+__global__ __launch_bounds__(kNH) void predict_rank_q_kernel(const float* __restrict__ th_q,
+                                                             const float* __restrict__ th_k,
+                                                             const float* __restrict__ x,
+                                                             float rank_feat, int k_max,
+                                                             int* __restrict__ out) {
+  __shared__ float xs[kNI], h1[kNH], h2[kNH], z[kNC];
+  __shared__ int khat;
+  const int t = threadIdx.x;
+  if (t < kNI) xs[t] = t < kNI - 1 ? x[t] : rank_feat;
+  __syncthreads();
+  mlp_logits(th_k, xs, h1, h2, z);
   if (t == 0) {
-    int best = 0;
-    for (int c = 1; c < kNC; ++c)
-      if (z[c] > z[best]) best = c;
-    *cls = best;
+    const int ck = argmax_logits(z);
+    khat = min(8 << ck, k_max);
+    out[1] = ck;
+    out[2] = khat;
+    xs[kNI - 1] = (float)khat / 256.0f;
   }
+  __syncthreads();
+  mlp_logits(th_q, xs, h1, h2, z);
+  if (t == 0) out[0] = argmax_logits(z);
+}
+
+// Rank-k errors of QLP factors from L alone: with nrm2 = ||A||_F^2 and the
+// squared column norms c_j of L (d x d lower-triangular, ldl),
+// e_k^2 = (nrm2 - c_1 - ... - c_k) / nrm2 (the residual of the rank-k
+// truncation is orthogonal to Q L[:, :k] P[:, :k]^T).  Writes res[0] = the
+// smallest k with e_k <= tol (d if none) and res[1] = that e_k.  One
+// workgroup; the sum runs in column order (deterministic).
+__global__ __launch_bounds__(256) void rank_scan_kernel(const double* __restrict__ L,
+                                                        int64_t ldl, int d,
+                                                        const double* __restrict__ nrm2,
+                                                        double tol, double* __restrict__ res) {
+  extern __shared__ double colsq[];
+  for (int j = threadIdx.x; j < d; j += blockDim.x) {
+    double s = 0.0;
+    for (int i = j; i < d; ++i) {
+      const double v = L[i + (int64_t)j * ldl];
+      s = fma(v, v, s);
+    }
+    colsq[j] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double a2 = *nrm2;
+  double acc = 0.0, e = a2 > 0.0 ? 1.0 : 0.0;
+  int k = d;
+  for (int j = 0; j < d; ++j) {
+    acc += colsq[j];
+    const double r = a2 > 0.0 ? fmax(0.0, (a2 - acc) / a2) : 0.0;
+    e = sqrt(r);
+    if (e <= tol) {
+      k = j + 1;
+      break;
+    }
+  }
+  res[0] = (double)k;
+  res[1] = e;
 }
 
 // argmax of the 6 logits -> predicted class (ties to the lower class).
@@ -530,6 +606,20 @@ hipError_t launch_sum(const float* x, int64_t n, float scale, float* out, hipStr
 hipError_t launch_predict_class(const float* th, const float* feat, float* out, int* cls,
                                 hipStream_t st) {
   hipLaunchKernelGGL(predict_class_kernel, dim3(1), dim3(kNH), 0, st, th, feat, out, cls);
+  return hipGetLastError();
+}
+
+hipError_t launch_predict_rank_q(const float* th_q, const float* th_k, const float* feat,
+                                 float rank_feat, int k_max, int* out, hipStream_t st) {
+  hipLaunchKernelGGL(predict_rank_q_kernel, dim3(1), dim3(kNH), 0, st, th_q, th_k, feat,
+                     rank_feat, k_max, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank_scan(const double* L, int64_t ldl, int64_t d, const double* nrm2,
+                            double tol, double* res, hipStream_t st) {
+  hipLaunchKernelGGL(rank_scan_kernel, dim3(1), dim3(256), (size_t)d * sizeof(double), st, L,
+                     ldl, (int)d, nrm2, tol, res);
   return hipGetLastError();
 }
 

@@ -76,6 +76,7 @@ constexpr double kTolDepRobust = 1e-12;
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int kPredCols = 64;  // sketch columns the predictor reads
+constexpr int kRankMaxD = 4096;  // widest sketch of the rank-predicting form (rank scan in LDS)
 // Offsets of the MLP parameters [W1 b1 W2 b2 W3 b3] (floats).
 constexpr int kNI = RQLP_MLP_INPUTS, kNH = RQLP_MLP_HIDDEN, kNC = RQLP_MLP_CLASSES;
 constexpr int64_t kOW1 = 0, kOB1 = kOW1 + kNI * kNH, kOW2 = kOB1 + kNH, kOB2 = kOW2 + kNH * kNH,
@@ -190,7 +191,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
     L.cls = take(16);
     L.jd = take((size_t)d * d * es);
     L.sums = take(sumsq_scratch_bytes());
-    L.sres = take(4 * 8);
+    L.sres = take(8 * 8);
     L.rerr = mixed ? take((size_t)convert16_blocks(m, n) * 2 * 8) : 0;
   } else {
     L.y64 = L.g64 = L.feat = L.mlp = L.cls = L.jd = L.sums = L.sres = L.rerr = 0;
@@ -795,11 +796,29 @@ rqlp_status static_scratch(int dev, char** out) {
   return RQLP_OK;
 }
 
+// Rank classes of the rank network: class c means k = 8 * 2^c, capped at
+// the caller's k_max.
+constexpr int kRankClasses = RQLP_MLP_CLASSES;
+int rank_of_class(int c, int k_max) { return std::min(8 << c, k_max); }
+
+// Workspace of the rank-predicting form: the largest layout among the sketch
+// widths the predicted rank can give (each class, and k_max).
+size_t rank_layout_bytes(int64_t m, int64_t n, int p, int k_max, Dtype dt, bool mixed,
+                         bool split) {
+  size_t b = make_layout(m, n, randqlp_sketch_width(m, n, k_max, p), dt, mixed, true, split).total;
+  for (int c = 0; c < kRankClasses; ++c)
+    b = std::max(b, make_layout(m, n, randqlp_sketch_width(m, n, rank_of_class(c, k_max), p), dt,
+                                mixed, true, split)
+                        .total);
+  return b;
+}
+
 // ---- shared set-up of randqlp_factor / randqlp_factor_auto
 rqlp_status setup_factor(const void* A, int64_t m, int64_t n, int k, int p, int q,
                          uint64_t seed, void* Q, void* L, void* P, const rqlp_opts* opts,
                          bool autoq, Ctx& c, FactorArgs& f, rqlp_opts& o,
-                         std::unique_lock<std::mutex>& lk, bool noalloc = false) {
+                         std::unique_lock<std::mutex>& lk, bool noalloc = false,
+                         int rank_kmax = 0) {
   if (opts)
     o = *opts;
   else
@@ -848,7 +867,12 @@ rqlp_status setup_factor(const void* A, int64_t m, int64_t n, int k, int p, int 
     if ((s = static_scratch(dev, &c.ws)) != RQLP_OK) return s;
     c.noalloc = true;
   } else {
-    s = acquire_ws(o, c.lay.total, &c.ws, lk);
+    // the rank-predicting form re-lays the workspace out for the predicted
+    // width: take enough for every width it can pick
+    const size_t bytes = rank_kmax > 0 ? rank_layout_bytes(m, n, p, rank_kmax, dt, mixed != 0,
+                                                           mixed == 3)
+                                       : c.lay.total;
+    s = acquire_ws(o, bytes, &c.ws, lk);
     if (s != RQLP_OK) return s;
   }
   f = FactorArgs{A, m, n, lda, q, Q, ldq, (double*)L, ldl, P, ldp};
@@ -1036,9 +1060,32 @@ hipError_t judge(Ctx& c, const FactorArgs& f, double sums[4], int flags_out[4]) 
   else
     HIP_TRY(launch_zero_block(res + 3, 1, 1, 1, c.st));
   // the four sums and the status words in one read-back
-  HIP_TRY(read_back(c.st, sums, res, 4 * sizeof(double), flags_out, c.flags(), 4 * sizeof(int)));
+  HIP_TRY(read_back(c.st, sums, res, 4 * sizeof(double), flags_out, c.flags(), 4 * sizeof(int),
+                    !c.noalloc));
   if (g_prof.on) prof_collect();
   sums[3] *= (double)d / (double)f.n;
+  return hipSuccess;
+}
+
+// Rank check of the returned factors (rank-predicting form): ||A||_F^2 into
+// sres[0] unless the judge left it there, then the smallest k whose rank-k
+// truncation Q L[:, :k] P[:, :k]^T meets tol, and its error, from the column
+// norms of L (rank_scan); out = {k, e_k}, plus the status words.
+hipError_t rank_check(Ctx& c, const FactorArgs& f, double tol, bool have_nrm, double out[2],
+                      int flags_out[4]) {
+  double* scr = c.at<double>(c.lay.sums);
+  double* res = c.at<double>(c.lay.sres);
+  if (!have_nrm) {
+    const int64_t nb16 = convert16_blocks(f.m, f.n);
+    if (c.mixed && c.lay.rerr)
+      HIP_TRY(launch_sum_f64(c.at<double>(c.lay.rerr) + nb16, nb16, res, c.st));
+    else
+      HIP_TRY(launch_sumsq(f.A, f.lda, nullptr, 0, f.m, f.n, c.dt, scr, res, c.st));
+  }
+  HIP_TRY(launch_rank_scan(f.L, f.ldl, c.d, res, tol, res + 4, c.st));
+  HIP_TRY(read_back(c.st, out, res + 4, 2 * sizeof(double), flags_out, c.flags(),
+                    4 * sizeof(int), !c.noalloc));
+  if (g_prof.on) prof_collect();
   return hipSuccess;
 }
 
@@ -1115,12 +1162,27 @@ rqlp_status randqlp_factor_auto(const void* A, int64_t m, int64_t n, int k, int 
                                 void* L, void* P, const rqlp_opts* opts,
                                 rqlp_auto_info* ainfo) {
   if (!params) return fail(RQLP_E_INVALID_ARG, "null predictor parameters");
+  const bool rank_mode = k <= 0;
+  double tol = 0.0;
+  int k_max = 0;
+  if (rank_mode) {
+    if (!opts)
+      return fail(RQLP_E_INVALID_ARG, "k <= 0 (predict the rank) needs opts->tol and opts->k_max");
+    tol = opts->tol;
+    k_max = opts->k_max;
+    if (!(tol > 0.0 && tol <= 1.0))
+      return fail(RQLP_E_INVALID_ARG, "tol = %g must lie in (0, 1]", tol);
+    if (k_max < 1) return fail(RQLP_E_INVALID_ARG, "k_max = %d must be >= 1", k_max);
+    if (p >= 0 && (int64_t)k_max + p > kRankMaxD)
+      return fail(RQLP_E_UNSUPPORTED, "k_max + p = %lld exceeds %d", (long long)k_max + p,
+                  kRankMaxD);
+  }
   Ctx c;
   FactorArgs f;
   rqlp_opts o;
   std::unique_lock<std::mutex> lk;
-  rqlp_status s =
-      setup_factor(A, m, n, k, p, q_fallback, seed, Q, L, P, opts, true, c, f, o, lk);
+  rqlp_status s = setup_factor(A, m, n, rank_mode ? k_max : k, p, q_fallback, seed, Q, L, P, opts,
+                               true, c, f, o, lk, false, rank_mode ? k_max : 0);
   if (s != RQLP_OK) return s;
   rqlp_auto_info ai;
   std::memset(&ai, 0, sizeof ai);
@@ -1129,25 +1191,62 @@ rqlp_status randqlp_factor_auto(const void* A, int64_t m, int64_t n, int k, int 
   int q_used = q_fallback;
   bool done = false;
   const PanelMode mode0 = start_mode(o);
-  // The first sketch and its orth() do not depend on q.  Omega comes first;
-  // the predictor (whose sketch uses Omega's leading columns) is enqueued on
-  // the second stream right after it, then the rest of the first sketch on
-  // the main stream, and the class is read back when the predictor is done.
-  hipStream_t aux = nullptr;
-  hipEvent_t ready = nullptr;
+  const int64_t d_max = c.d;
   c.orth_calls = 0;
-  hipError_t e = aux_stream(&aux);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
-  if (e == hipSuccess) e = clear_flags(c);
-  if (e == hipSuccess) e = stage_omega(c, f);
-  if (e == hipSuccess) e = hipEventRecord(ready, c.st);           // Omega is in Zm
-  if (e == hipSuccess) e = hipStreamWaitEvent(aux, ready, 0);
-  if (e == hipSuccess) e = predict_q(c, f, k, params, aux);
-  if (e == hipSuccess) e = stage_sketch(c, f, mode0);
-  // (the read-back waits for the predictor: enqueue it last)
-  if (e == hipSuccess) e = read_back(aux, &cls, c.at<int>(c.lay.cls), sizeof(int));
-  if (ready) (void)hipEventDestroy(ready);
-  if (e != hipSuccess) return fail(RQLP_E_HIP, "predictor: %s", hipGetErrorString(e));
+  hipError_t e = hipSuccess;
+  if (rank_mode) {
+    // Omega (at least 64 columns), the feature sketch and both networks on
+    // the call's stream; the sketch width follows from the predicted rank.
+    const float rank_feat =
+        (float)(std::min(std::max(-std::log10(tol), 0.0), 6.0) / 6.0);
+    int pc[4] = {0, 0, 0, 0};
+    int* dcls = c.at<int>(c.lay.cls);
+    e = clear_flags(c);
+    if (e == hipSuccess) e = stage_omega(c, f);
+    // the feature sketch has 64 columns (d may be fewer): the predictor's
+    // own split-K scratch
+    Ctx cp = c;
+    cp.lay.part = c.lay.part2;
+    cp.lay.part_bytes = c.lay.part2_bytes;
+    if (e == hipSuccess)
+      e = feature_sketch(cp, f.A, f.m, f.n, f.lda, 1, c.ws + c.lay.m1, c.ws + c.lay.y64,
+                         c.at<double>(c.lay.g64), c.at<float>(c.lay.feat));
+    if (e == hipSuccess)
+      e = launch_predict_rank_q(params, params + RQLP_MLP_PARAMS, c.at<float>(c.lay.feat),
+                                rank_feat, k_max, dcls, c.st);
+    if (e == hipSuccess)
+      e = read_back(c.st, pc, dcls, 3 * sizeof(int), nullptr, nullptr, 0, !c.noalloc);
+    if (e != hipSuccess) return fail(RQLP_E_HIP, "predictor: %s", hipGetErrorString(e));
+    cls = pc[0];
+    ai.k_predicted = pc[2];
+    // Omega stays where it is: m1 is the first region of every layout (ld m)
+    const int64_t d = randqlp_sketch_width(m, n, pc[2], p);
+    c.lay = make_layout(m, n, d, c.dt, c.mixed != 0, true, c.mixed == 3);
+    c.d = d;
+    e = stage_sketch(c, f, mode0);
+    if (e != hipSuccess) return fail(RQLP_E_HIP, "launch failed: %s", hipGetErrorString(e));
+  } else {
+    // The first sketch and its orth() do not depend on q.  Omega comes
+    // first; the predictor (whose sketch uses Omega's leading columns) is
+    // enqueued on the second stream right after it, then the rest of the
+    // first sketch on the main stream, and the class is read back when the
+    // predictor is done.
+    hipStream_t aux = nullptr;
+    hipEvent_t ready = nullptr;
+    e = aux_stream(&aux);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ready, hipEventDisableTiming);
+    if (e == hipSuccess) e = clear_flags(c);
+    if (e == hipSuccess) e = stage_omega(c, f);
+    if (e == hipSuccess) e = hipEventRecord(ready, c.st);           // Omega is in Zm
+    if (e == hipSuccess) e = hipStreamWaitEvent(aux, ready, 0);
+    if (e == hipSuccess) e = predict_q(c, f, k, params, aux);
+    if (e == hipSuccess) e = stage_sketch(c, f, mode0);
+    // (the read-back waits for the predictor: enqueue it last)
+    if (e == hipSuccess) e = read_back(aux, &cls, c.at<int>(c.lay.cls), sizeof(int));
+    if (ready) (void)hipEventDestroy(ready);
+    if (e != hipSuccess) return fail(RQLP_E_HIP, "predictor: %s", hipGetErrorString(e));
+    ai.k_predicted = k;
+  }
   ai.q_predicted = cls;
   if (cls < q_fallback) {
     // the method with q_hat, then the judge
@@ -1201,6 +1300,31 @@ rqlp_status randqlp_factor_auto(const void* A, int64_t m, int64_t n, int k, int 
     q_used = q_fallback;
     if ((s = run_with_escalation(c, f, o, mode0, r)) != RQLP_OK) return s;
   }
+  if (rank_mode) {
+    // does some rank k <= d of the returned factors meet tol?  If not, the
+    // predicted rank (or q) was too low: the plain method with k_max and
+    // q_fallback, and the same check on its factors.
+    double rk[2] = {0.0, 0.0};
+    int fl[4] = {0, 0, 0, 0};
+    e = rank_check(c, f, tol, ai.judged != 0 && done, rk, fl);
+    if (e != hipSuccess) return fail(RQLP_E_HIP, "rank check: %s", hipGetErrorString(e));
+    if (rk[1] > tol && (c.d < d_max || q_used < q_fallback)) {
+      ai.rank_fallback = 1;
+      c.lay = make_layout(m, n, d_max, c.dt, c.mixed != 0, true, c.mixed == 3);
+      c.d = d_max;
+      f.q = q_fallback;
+      q_used = q_fallback;
+      r = Outcome();
+      if ((s = run_with_escalation(c, f, o, mode0, r)) != RQLP_OK) return s;
+      e = rank_check(c, f, tol, false, rk, fl);
+      if (e != hipSuccess) return fail(RQLP_E_HIP, "rank check: %s", hipGetErrorString(e));
+    }
+    ai.k_used = (int32_t)rk[0];
+    ai.rank_err = rk[1];
+  } else {
+    ai.k_used = k;
+  }
+  ai.d = (int32_t)c.d;
   ai.q_used = q_used;
   fill_info(o, c.d, q_used, r);
   if (ainfo) *ainfo = ai;

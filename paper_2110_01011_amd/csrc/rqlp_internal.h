@@ -289,6 +289,15 @@ hipError_t launch_argmax(const float* Z, int C, int* out, hipStream_t st);
 // receives the activations and logits.  One launch.
 hipError_t launch_predict_class(const float* th, const float* feat, float* out, int* cls,
                                 hipStream_t st);
+// Rank network (th_k, last input rank_feat) -> rank class ck and
+// k_hat = min(8 * 2^ck, k_max); then the power-round network (th_q, last
+// input k_hat / 256).  out[0] = q class, out[1] = ck, out[2] = k_hat.
+hipError_t launch_predict_rank_q(const float* th_q, const float* th_k, const float* feat,
+                                 float rank_feat, int k_max, int* out, hipStream_t st);
+// res[0] = smallest k with sqrt((nrm2 - sum_{j<k} ||L[:, j]||^2) / nrm2) <= tol
+// (d if none), res[1] = that error; nrm2 is a device double.  d <= 8192.
+hipError_t launch_rank_scan(const double* L, int64_t ldl, int64_t d, const double* nrm2,
+                            double tol, double* res, hipStream_t st);
 // ||X||_F^2 or ||X - Y||_F^2 (Y may be null) in fp64, deterministic order;
 // scratch holds sumsq_scratch_bytes().
 size_t sumsq_scratch_bytes();

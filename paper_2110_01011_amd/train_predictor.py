@@ -1,13 +1,16 @@
-"""Train the power-iteration predictor on the GPU with the library's kernels.
+"""Train a predictor network on the GPU with the library's kernels.
 
-Usage: python -m paper_2110_01011_amd.train_predictor [data.npz] [out.npy]
+Usage: python -m paper_2110_01011_amd.train_predictor data.npz out.npy
 
-Reads a dataset of (65 features, label) pairs (by default the one written
-by tests/learned/make_qpred_data.py), holds out every tenth sample for
-validation, trains the MLP with randqlp_mlp_train (softmax cross-entropy,
-Adam, deterministic minibatch order) and writes the float32 parameter vector
-(RQLP_MLP_PARAMS values, the layout randqlp_factor_auto reads) to
-qpredictor.npy beside this file, with a JSON summary next to it.
+Reads a dataset of (65 inputs, label) pairs from data.npz (arrays X and y:
+the power-round labels written by make_qpred_data.py, or the rank labels
+written by make_kpred_data.py, both under tests/learned), holds out every
+tenth sample for validation, trains the MLP with randqlp_mlp_train (softmax
+cross-entropy, Adam, deterministic minibatch order) and writes the float32
+parameter vector (RQLP_MLP_PARAMS values, the layout randqlp_factor_auto
+reads) to out.npy, with a JSON summary next to it.  The package ships the
+two trained vectors as qpredictor.npy (power rounds) and kpredictor.npy
+(rank).
 """
 import json
 import os
@@ -16,9 +19,6 @@ import sys
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-ROOT = os.path.dirname(HERE)
-DEFAULT_DATA = os.path.join(ROOT, "tests", "learned", "qpred_data.npz")
-DEFAULT_OUT = os.path.join(HERE, "qpredictor.npy")
 SIZES = (65, 128, 128, 6)
 
 
@@ -39,7 +39,7 @@ def split(n):
     return idx[~val], idx[val]
 
 
-def train(data_path=DEFAULT_DATA, epochs=(60, 30), lrs=(2e-3, 4e-4), batch=256, seed=1):
+def train(data_path, epochs=(60, 30), lrs=(2e-3, 4e-4), batch=256, seed=1):
     """Returns (params as float32 numpy, summary dict)."""
     import torch
 
@@ -83,8 +83,9 @@ def train(data_path=DEFAULT_DATA, epochs=(60, 30), lrs=(2e-3, 4e-4), batch=256, 
 
 
 def main():
-    data = sys.argv[1] if len(sys.argv) > 1 else DEFAULT_DATA
-    out = sys.argv[2] if len(sys.argv) > 2 else DEFAULT_OUT
+    if len(sys.argv) != 3:
+        sys.exit("usage: python -m paper_2110_01011_amd.train_predictor data.npz out.npy")
+    data, out = sys.argv[1], sys.argv[2]
     params, summary = train(data)
     np.save(out, params.astype(np.float32))
     with open(os.path.splitext(out)[0] + ".json", "w") as f:

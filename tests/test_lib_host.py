@@ -170,3 +170,21 @@ def test_batched_entry_points_validate(L):
     assert L.randqlp_batch_run(None, 1, None) == 1
     assert L.randqlp_tune_save(None) == 1
     assert L.randqlp_tune_load(b"/nonexistent/dir/tune.txt") == 1
+
+
+def test_auto_rank_mode_validates(L):
+    """k <= 0 asks for the rank to be predicted: opts with tol in (0, 1] and
+    k_max >= 1 (k_max + p <= 4096) are required; checked before any work."""
+    dummy = ctypes.c_void_p(256)
+    args = (dummy, 500, 400, 0, 10, 2, 0, dummy, dummy, dummy, dummy)
+    assert L.randqlp_factor_auto(*args, None, None) == 1
+    assert "tol" in L.randqlp_last_error().decode()
+    o = rq.default_opts()
+    o.tol, o.k_max = 0.0, 64
+    assert L.randqlp_factor_auto(*args, ctypes.byref(o), None) == 1
+    o.tol, o.k_max = 1.5, 64
+    assert L.randqlp_factor_auto(*args, ctypes.byref(o), None) == 1
+    o.tol, o.k_max = 0.1, 0
+    assert L.randqlp_factor_auto(*args, ctypes.byref(o), None) == 1
+    o.tol, o.k_max = 0.1, 5000
+    assert L.randqlp_factor_auto(*args, ctypes.byref(o), None) == 6
