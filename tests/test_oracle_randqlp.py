@@ -264,3 +264,38 @@ def test_planted_mistakes_are_caught(kind):
     assert not (np.any(np.triu(L, 1) != 0) or np.any(np.diag(L) < 0)
                 or not np.allclose(L, Q.T @ A @ P, atol=1e-12)
                 or subspace_sine(Qy, Q) > 1e-8)
+
+
+@pytest.mark.parametrize("q", [0, 1, 2, 3])
+def test_bound_exponents_are_attained_in_two_dimensions(q):
+    """A = diag(s1, s2), k = 1, p = 0: the sketch direction after q power
+    rounds is (AA^T)^(q+1) Omega = (s1^e w1, s2^e w2) with e = 2(q+1), so
+    tan theta_Q = psi^(2(q+1)) |M| with M = w2 / w1 exactly, and the
+    projection gives tan theta_P = psi^(2q+3) |M|.  Theorem 2's bounds t
+    (for R13's exponents) are then attained as sin theta = t / sqrt(1 + t^2):
+    a looser exponent gives a larger t and fails the equality as surely as
+    a tighter one fails the bound.  Theorem 1's lower bound s1 / sqrt(1 +
+    psi^(4(q+1)) |M|^2) = s1 cos theta_Q is attained to O(psi^2 t^2), and
+    Theorem 3's bounds are the tail plus ||A|| times Theorem 2's."""
+    s = np.array([1.0, 0.5])
+    A = np.diag(s)
+    for seed in range(3):
+        Q, L, P, st = randqlp(A, 1, 0, q, seed=seed, return_steps=True)
+        t = B.theorem_quantities(np.eye(2), s, st["omega"], 1, q)
+        w = st["omega"][:, 0]
+        assert t["M"] == pytest.approx(abs(w[1] / w[0]), rel=1e-14)
+        b2 = B.theorem2_bounds(t)
+        tq, tp = b2["theta_Q"], b2["theta_P"]
+        assert tq == pytest.approx(0.5 ** (2 * (q + 1)) * t["M"], rel=1e-14)
+        assert tp == pytest.approx(0.5 ** (2 * q + 3) * t["M"], rel=1e-14)
+        sin_q, sin_p = abs(Q[1, 0]), abs(P[1, 0])
+        assert sin_q == pytest.approx(tq / np.sqrt(1 + tq * tq), rel=1e-10)
+        assert sin_p == pytest.approx(tp / np.sqrt(1 + tp * tp), rel=1e-10)
+        lo, up, l22 = B.theorem1_bounds(t)
+        assert lo[0] == pytest.approx(s[0] / np.sqrt(1 + tq * tq), rel=1e-14)
+        assert lo[0] <= L[0, 0] <= lo[0] * (1 + 0.25 * tq * tq + 1e-14)
+        for rho in ("fro", 2):
+            bq, bp = B.theorem3_bounds(t, A, rho)
+            a = np.linalg.norm(A, rho)
+            assert bq == pytest.approx(s[1] + a * tq, rel=1e-14)
+            assert bp == pytest.approx(s[1] + a * tp, rel=1e-14)
