@@ -346,11 +346,14 @@ hipError_t gemm16(Ctx& c, int trans_a, int64_t m, int64_t n, const float* X, int
 }
 
 // Cholesky of G + shift I for any d <= RQLP_MAX_D into R (ldr) and the
-// diagonal-block inverses.  Blocked right-looking: the leading CHOL_MAX_D
-// columns on the one-workgroup kernel; R12 = R11^{-T} G12, computed as the
-// TRSM of G21 = G12^T; the Schur complement G22 - R12^T R12 through the Gram
-// product; then the same on the complement.  Pivot tolerances stay relative
-// to the original diagonal.  scratch holds 4 d^2 doubles.
+// diagonal-block inverses.  Right-looking, in blocks of CHOL_MAX_D columns:
+// the diagonal block on the one-workgroup kernel; R12 = R11^{-T} G12,
+// computed as the TRSM of G21 = G12^T; the Schur complement
+// G22 - R12^T R12 through the Gram product; then the same on the complement.
+// The complements alternate between two tight buffers, so the scratch stays
+// at 3 d^2 + CHOL_MAX_D d doubles for any d.  Pivot tolerances stay relative
+// to the original diagonal (odiag_src when given, else G's own).  The shift
+// applies to the original diagonal only.
 hipError_t chol_any(Ctx& c, const double* G, int64_t d, int64_t ldg, double shift,
                     const double* shift_dev, double tol_dep, double tol_warn, double* R,
                     int64_t ldr, double* dinv, int* col_flags, const double* odiag_src,
@@ -358,23 +361,37 @@ hipError_t chol_any(Ctx& c, const double* G, int64_t d, int64_t ldg, double shif
   if (d <= CHOL_MAX_D)
     return launch_cholesky_tile(G, d, ldg, shift, shift_dev, tol_dep, tol_warn, R, ldr, dinv,
                                 col_flags, c.flags(), odiag_src, odiag_stride, c.st);
-  const int64_t d1 = CHOL_MAX_D, d2 = d - d1;
-  HIP_TRY(launch_cholesky_tile(G, d1, ldg, shift, shift_dev, tol_dep, tol_warn, R, ldr, dinv,
-                               col_flags, c.flags(), odiag_src, odiag_stride, c.st));
-  double* Xs = scratch;          // G21 R11^{-1} = R12^T, d2 x d1
-  double* C = Xs + d2 * d1;      // R12^T R12, d2 x d2
-  double* S = C + d2 * d2;       // Schur complement, d2 x d2
-  HIP_TRY(launch_trsm(G + d1, d2, d1, ldg, R, ldr, dinv, Xs, d2, DT_F64, c.st));
-  double* R12 = R + d1 * ldr;
-  HIP_TRY(launch_transpose(Xs, d2, d1, d2, R12, ldr, c.st));
-  HIP_TRY(launch_zero_block(R + d1, d2, d1, ldr, c.st));
-  HIP_TRY(gemm(c, 1, R12, ldr, R12, ldr, C, d2, d2, d2, d1, DT_F64, DT_F64, true));
-  HIP_TRY(launch_schur(G + d1 + d1 * ldg, ldg, C, d2, shift, shift_dev, S, c.st));
-  const double* od = odiag_src ? odiag_src + d1 * odiag_stride : G + d1 + d1 * ldg;
-  const int64_t ods = odiag_src ? odiag_stride : ldg + 1;
-  return chol_any(c, S, d2, d2, 0.0, nullptr, tol_dep, tol_warn, R + d1 + d1 * ldr, ldr,
-                  dinv + (d1 / 16) * 256, col_flags ? col_flags + d1 : nullptr, od, ods,
-                  S + d2 * d2);
+  double* Wbuf[2] = {scratch, scratch + d * d};  // trailing complements, tight
+  double* C = scratch + 2 * d * d;                // R12^T R12
+  double* Xs = C + d * d;                         // G21 R11^{-1} = R12^T
+  const double* src = G;                          // current trailing block
+  int64_t lds = ldg;
+  for (int64_t j0 = 0, lvl = 0; j0 < d; j0 += CHOL_MAX_D, ++lvl) {
+    const int64_t b = std::min<int64_t>(CHOL_MAX_D, d - j0), d2 = d - j0 - b;
+    const bool top = (j0 == 0);
+    // original diagonal of this block (for the pivot tolerances)
+    const double* od = top ? odiag_src
+                           : (odiag_src ? odiag_src + j0 * odiag_stride : G + j0 + j0 * ldg);
+    const int64_t ods = top ? odiag_stride : (odiag_src ? odiag_stride : ldg + 1);
+    double* Rjj = R + j0 + j0 * ldr;
+    HIP_TRY(launch_cholesky_tile(src, b, lds, top ? shift : 0.0, top ? shift_dev : nullptr,
+                                 tol_dep, tol_warn, Rjj, ldr, dinv + (j0 / 16) * 256,
+                                 col_flags ? col_flags + j0 : nullptr, c.flags(), od, ods,
+                                 c.st));
+    if (d2 == 0) break;
+    HIP_TRY(launch_trsm(src + b, d2, b, lds, Rjj, ldr, dinv + (j0 / 16) * 256, Xs, d2, DT_F64,
+                        c.st));
+    double* R12 = R + j0 + (j0 + b) * ldr;
+    HIP_TRY(launch_transpose(Xs, d2, b, d2, R12, ldr, c.st));
+    HIP_TRY(launch_zero_block(R + (j0 + b) + j0 * ldr, d2, b, ldr, c.st));
+    HIP_TRY(gemm(c, 1, R12, ldr, R12, ldr, C, d2, d2, d2, b, DT_F64, DT_F64, true));
+    double* S = Wbuf[lvl & 1];
+    HIP_TRY(launch_schur(src + b + b * lds, lds, C, d2, top ? shift : 0.0,
+                         top ? shift_dev : nullptr, S, c.st));
+    src = S;
+    lds = d2;
+  }
+  return hipSuccess;
 }
 
 // Qx = X R^+ (rows x d; Qx may be X with the same ld).  Up to CHOL_MAX_D

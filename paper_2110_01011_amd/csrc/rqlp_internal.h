@@ -37,7 +37,7 @@ enum Dtype : int { DT_F64 = 0, DT_F32 = 1 };
 
 constexpr int CHOL_MAX_D = 224;   // single-workgroup Cholesky tile limit (14 x 14 tiles of 16)
 constexpr int TRSM_MAX_D = 1024;  // TRSM keeps a 16 x d panel per wave in LDS
-constexpr int RQLP_MAX_D = 1024;  // largest sketch width (blocked Cholesky above CHOL_MAX_D)
+constexpr int RQLP_MAX_D = 8192;  // largest sketch width (blocked Cholesky above CHOL_MAX_D)
 
 // ---- philox.hip ----
 hipError_t launch_gaussian(void* out, int64_t m, int64_t d, int64_t ld, uint64_t seed,
