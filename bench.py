@@ -9,7 +9,13 @@ L = R^T).  Throughput = the Section 4.2 flop model / measured time.
 
 Prints one JSON line with the roofline of the dominant kernel (the product
 kernel that streams A, timed with HIP events on its stream) and the fp64 CPU
-oracle timed on a bounded sample of the same workload.
+oracle timed on a bounded sample of the same workload.  Extra keys:
+headline (bf16 precision form + learned q against fp64 q = 2), c3 (the
+precision form at 20000 x 16000), c4 (512 uneven matrices, batched),
+fullrank (Algorithm 1 at d = n at the paper's orders), accuracy (diag(L)
+and rank-k errors on the Section 5.2 families).  Every oracle run -- the
+CPU baseline and the error checks of c3, c4 and fullrank -- happens in the
+cpu_baseline leg.
 """
 import argparse
 import hashlib
@@ -97,9 +103,13 @@ def host_cpu():
     return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
 
 
-def cpu_baseline(A, k, p, q, flops, budget_s=15.0, max_reps=40):
-    """The fp64 oracle on the host cores, on whole factorisations of A; then
-    one factorisation on a single BLAS thread."""
+def cpu_baseline(A, k, p, q, flops, checks=None, budget_s=15.0, max_reps=40):
+    """The fp64 oracle on the host cores: whole factorisations of the default
+    workload's A (then one on a single BLAS thread), and the oracle runs that
+    the other legs' errors are checked against (`checks`: the precision-form
+    matrix, the batched sample, the smallest full-rank matrix).  Returns
+    (baseline, oracle error of A, oracle results of the checks)."""
+    import numpy as np
     from threadpoolctl import threadpool_info, threadpool_limits
     from oracle import randqlp, rel_error
     threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
@@ -118,11 +128,40 @@ def cpu_baseline(A, k, p, q, flops, budget_s=15.0, max_reps=40):
         randqlp(A, k, p, q, seed=0)
         t1 = time.perf_counter() - t0
     log(f"  oracle on 1 thread: {t1:.2f} s")
-    return {"value": flops / t / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
+    base = {"value": flops / t / 1e9, "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(times)} whole fp64 factorisations of the same {A.shape[0]}x{A.shape[1]} "
                       f"matrix on {threads} BLAS threads (median {t:.2f} s each, Omega "
                       f"generation included)",
-            "host": host_cpu(), "one_thread": {"s": round(t1, 3), "value": flops / t1 / 1e9}}, e
+            "host": host_cpu(), "one_thread": {"s": round(t1, 3), "value": flops / t1 / 1e9}}
+    res = {}
+    checks = checks or {}
+    if checks.get("c3") is not None:
+        Ah, a = checks["c3"]
+        log("  oracle on the 20000 x 16000 precision-form matrix")
+        t0 = time.perf_counter()
+        Qo, Lo, Po = randqlp(Ah, a["k"], a["p"], a["q"], seed=a["seed"])
+        to = time.perf_counter() - t0
+        res["c3"] = {"e": rel_error(Ah, Qo, Lo, Po), "s": round(to, 2), "threads": threads}
+        del Qo, Lo, Po
+    if checks.get("c4"):
+        out = []
+        for smp in checks["c4"]:
+            Ah = smp["A"]
+            e_o = rel_error(Ah, *randqlp(Ah, smp["k"], smp["p"], smp["q"], smp["seed"]))
+            out.append({key: smp[key] for key in ("i", "m", "n", "k", "alpha")} |
+                       {"e": smp["e"], "e_oracle": e_o, "ratio": smp["e"] / e_o})
+        res["c4"] = out
+    if checks.get("fullrank") is not None:
+        c = checks["fullrank"]
+        Ah, n = c["A"], c["n"]
+        t0 = time.perf_counter()
+        Qo, Lo, Po = randqlp(Ah, n, 0, 0, seed=0)
+        to = time.perf_counter() - t0
+        res["fullrank"] = {"n": n, "e_oracle": rel_error(Ah, Qo, Lo, Po), "e": c["e"],
+                           "max_diagL_diff_over_L11": float(np.abs(np.diag(Lo) - c["diagL"]).max()
+                                                            / Lo[0, 0]),
+                           "oracle_s": round(to, 3)}
+    return base, e, res
 
 
 def device_rel_error(A, Q, L, P):
@@ -195,13 +234,12 @@ def headline(rq, A_c2, k, p, steps, precision="bf16"):
             "errors_within_1.05": all(c["error_ratio"] <= 1.05 for c in out)}
 
 
-def c3_leg(steps, warmup, oracle=True):
+def c3_leg(steps, warmup, keep_host=True):
     """Precision form: 20000 x 16000, sigma_i = exp(-i/100) (rank 4000, Haar
     factors), k = 500, p = 20, q = 2 (d = 520).  Each form (bf16x3, bf16,
     f16, fp32, fp64) is timed on the resident matrix and its error
-    ||A - Q L P^T||_F / ||A||_F is computed in fp64 against the fp64 A; the
-    fp64 oracle factors the same matrix on the host and every form's error
-    is divided by the oracle's."""
+    ||A - Q L P^T||_F / ||A||_F is computed in fp64 against the fp64 A.
+    Returns (result, host copy of A for the oracle check or None)."""
     import torch
 
     import paper_2110_01011_amd as rq
@@ -240,42 +278,25 @@ def c3_leg(steps, warmup, oracle=True):
         del Q, L, P
     out = {"workload": f"exp-decay sigma_i = exp(-i/100), rank {r}, {m}x{n}, "
                        f"k={k} p={p} q={q} (d={d})",
-           "flops_per_step": flops, "steps": steps, "warmup": warmup, "forms": forms}
-    if oracle:
-        from oracle import randqlp, rel_error
-        from threadpoolctl import threadpool_info
-        log("c3: fp64 oracle on the host")
-        Ah = A64.cpu().numpy()          # column-major fp64 (a Fortran-ordered array)
-        t0 = time.perf_counter()
-        Qo, Lo, Po = randqlp(Ah, k, p, q, seed=0)
-        to = time.perf_counter() - t0
-        e_o = rel_error(Ah, Qo, Lo, Po)
-        del Ah, Qo, Lo, Po
-        threads = max([t.get("num_threads", 1) for t in threadpool_info()] or [1])
-        out["oracle"] = {"e": e_o, "s": round(to, 2), "threads": threads}
-        for prec in forms:
-            forms[prec]["e_over_oracle"] = forms[prec]["e"] / e_o
-        out["errors_within_1.05_of_oracle"] = all(f["e_over_oracle"] <= 1.05
-                                                  for f in forms.values())
-        log(f"  c3 oracle: e={e_o:.6e} in {to:.1f} s; ratios "
-            f"{ {p_: round(f['e_over_oracle'], 5) for p_, f in forms.items()} }")
+           "flops_per_step": flops, "steps": steps, "warmup": warmup, "forms": forms,
+           "oracle_args": {"k": k, "p": p, "q": q, "seed": 0}}
+    Ah = A64.cpu().numpy() if keep_host else None   # column-major fp64 (Fortran order)
     del A64, A32
     torch.cuda.empty_cache()
-    return out
+    return out, Ah
 
 
 def c4_leg(steps, warmup, sample=16):
     """Batched form: 512 matrices, m, n uniform in 256..4096, sigma_j =
     j^-alpha with alpha uniform in [0.5, 3] and Haar factors, k uniform in
     8..128, p = 10, q = 2, fp32; grouped launches replayed from a HIP graph,
-    tuned tile widths.  A seeded sample of the matrices is factored by the
-    fp64 oracle (on the same fp32 values) and each error is compared."""
+    tuned tile widths.  Returns (result, a seeded sample of matrices with
+    their GPU factors' errors, for the oracle check)."""
     import numpy as np
     import torch
 
     import paper_2110_01011_amd as rq
     import workloads as W
-    from oracle import randqlp, rel_error
     from paper_2110_01011_amd.metrics import PEAK_HBM_GBS, PEAK_TFLOPS, randqlp_flops
     count, p, q = 512, 10, 2
     log("c4: generating 512 matrices on the device")
@@ -302,27 +323,24 @@ def c4_leg(steps, warmup, sample=16):
     torch.cuda.synchronize()
     t = (time.perf_counter() - t0) / steps
     info = b.info()
-    log(f"c4: {t * 1e3:.2f} ms per batch; oracle check on {sample} matrices")
+    log(f"c4: {t * 1e3:.2f} ms per batch")
     pick = sorted(np.random.Generator(np.random.Philox(key=[2024, 4])).choice(count, sample,
                                                                               replace=False))
-    checks = []
+    samples = []
     for i in pick:
         i = int(i)
         Ah = As[i].double().cpu().numpy()
         Qg, Lg, Pg = (x.double().cpu().numpy() for x in (b.Q[i], b.L[i], b.P[i]))
-        e_g = rel_error(Ah, Qg, Lg, Pg)
-        e_o = rel_error(Ah, *randqlp(Ah, ks[i], p, q, seeds[i]))
-        checks.append({"i": i, "m": specs[i]["m"], "n": specs[i]["n"], "k": ks[i],
-                       "alpha": round(specs[i]["alpha"], 3), "e": e_g, "e_oracle": e_o,
-                       "ratio": e_g / e_o})
+        e_g = float(np.linalg.norm(Ah - Qg @ (Lg @ Pg.T)) / np.linalg.norm(Ah))
+        samples.append({"i": i, "A": Ah, "k": ks[i], "p": p, "q": q, "seed": seeds[i],
+                        "m": specs[i]["m"], "n": specs[i]["n"],
+                        "alpha": round(specs[i]["alpha"], 3), "e": e_g})
     b.close()
     t0 = time.perf_counter()
     for A, k, sd in zip(As, ks, seeds):
         rq.factor(A, k, p, q, sd)
     torch.cuda.synchronize()
     tseq = time.perf_counter() - t0
-    ratios = [c["ratio"] for c in checks]
-    log(f"  c4 error ratios vs oracle: max {max(ratios):.5f}")
     del As
     torch.cuda.empty_cache()
     return {"workload": "512 matrices, m, n ~ U{256..4096}, sigma_j = j^-alpha, "
@@ -332,15 +350,100 @@ def c4_leg(steps, warmup, sample=16):
             "roofline": {"bound": "sum over matrices of max(flops / fp32 peak, bytes / HBM peak)",
                          "roof_ms": round(roof * 1e3, 3), "frac": round(roof / t, 4)},
             "sequential_ms": round(tseq * 1e3, 2), "speedup_vs_sequential": round(tseq / t, 2),
-            "generation_s": round(tgen, 1), "plan": info,
-            "oracle_sample": {"count": sample, "max_ratio": max(ratios),
-                              "errors_within_1.05_of_oracle": max(ratios) <= 1.05,
-                              "cases": checks}}
+            "generation_s": round(tgen, 1), "plan": info}, samples
+
+
+# Section 5.1's timings of Rand-QLP (Fig. 2) on SuiteSparse matrices of
+# these orders, in seconds on the paper's CPU and CPU + RTX 2080Ti ("hybrid")
+# setups; context only: other matrices (Rand-QLP's cost depends only on the
+# order) on other hardware.
+PAPER_FIG2_S = {1856: (0.57, 0.48), 2904: (1.38, 0.61), 4929: (4.93, 1.73),
+                6747: (10.11, 3.62), 7320: (11.88, 4.41)}
+
+
+def fullrank_leg(reps=3, sizes=(1856, 2904, 4929, 6747, 7320)):
+    """Algorithm 1 itself (Section 3.1): d = n, q = 0 on dense uniform(0,1)
+    n x n fp64 matrices (Section 5.1's random test matrices), at the orders
+    of the paper's Fig. 2; GFLOP/s on the paper's count 8n^3 + 3n^3 - 2n^2
+    (Section 4.2, m = n).  Returns (result, host copy of the smallest
+    matrix and its GPU factors for the oracle check)."""
+    import numpy as np
+    import torch
+
+    import paper_2110_01011_amd as rq
+    rows, check = [], None
+    for n in sizes:
+        g = torch.Generator(device="cuda")
+        g.manual_seed(n)
+        A = rq.colmajor(torch.rand(n, n, dtype=torch.float64, device="cuda", generator=g).t())
+        Q, L, P, info = rq.factor(A, n, 0, 0, 0, return_info=True)
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            Q, L, P, info = rq.factor(A, n, 0, 0, 0, return_info=True)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t = float(np.median(ts))
+        fl = 8.0 * n ** 3 + 3.0 * n ** 3 - 2.0 * n ** 2
+        e = device_rel_error(A, Q, L, P)
+        cpu_s, hyb_s = PAPER_FIG2_S.get(n, (None, None))
+        rows.append({"n": n, "ms": round(t * 1e3, 2), "gflops": round(fl / t / 1e9, 1),
+                     "e": e, "robust_rerun": info["robust_rerun"],
+                     "paper_fig2_cpu_s": cpu_s, "paper_fig2_hybrid_s": hyb_s})
+        log(f"  full rank n={n}: {rows[-1]}")
+        if check is None:
+            check = {"A": A.cpu().numpy(), "e": e,
+                     "diagL": np.diag(L.cpu().numpy()).copy(), "n": n}
+        del A, Q, L, P
+        torch.cuda.empty_cache()
+    return {"workload": "Algorithm 1 (d = n, q = 0), dense uniform(0,1) n x n, fp64",
+            "flop_count": "8n^3 + 3n^3 - 2n^2 (Section 4.2, m = n)", "cases": rows}, check
+
+
+def accuracy_leg():
+    """Section 5.2's four n = 1000 families (LowRankPlusNoise, FastDecay,
+    S-shaped, SlowDecay) through Algorithm 1 (d = n, q = 0): how closely
+    diag(L) tracks the singular values (from LAPACK's SVD of A), and the
+    rank-k errors of Q L[:, :k] P[:, :k]^T in the Frobenius norm against the
+    truncated SVD's (the optimum)."""
+    import numpy as np
+    import torch
+
+    import paper_2110_01011_amd as rq
+    import workloads as W
+    n = 1000
+    mats = {"LowRankPlusNoise": W.paper_low_rank_plus_noise(n, 5),
+            "FastDecay": W.fast_decay(n, n, 5)[0], "S-shaped": W.s_shaped(n, 5)[0],
+            "SlowDecay": W.slow_decay(n, 5)[0]}
+    out = {}
+    for name, A in mats.items():
+        s = np.linalg.svd(A, compute_uv=False)
+        Ad = rq.colmajor(torch.from_numpy(np.ascontiguousarray(A.T)).cuda().t())
+        Q, L, P = rq.factor(Ad, n, 0, 0, 11)
+        sh = np.abs(np.diag(L.cpu().numpy()))
+        nrm = float(np.linalg.norm(A))
+        ek = {}
+        for k in (10, 20, 50, 100, 200):
+            Ak = Q[:, :].double() @ (L[:, :k] @ P[:, :k].double().T)
+            e = float(torch.linalg.norm(Ad - Ak)) / nrm
+            opt = float(np.sqrt(np.sum(s[k:] ** 2))) / nrm
+            ek[k] = {"e": e, "optimal": opt, "ratio": e / opt if opt > 0 else None}
+        lead = int(np.sum(s > 1e-8 * s[0]))
+        r = sh[:min(lead, 200)] / s[:min(lead, 200)]
+        out[name] = {"diagL_over_sigma_leading": [round(float(r.min()), 4), round(float(r.max()), 4)],
+                     "leading_count": int(min(lead, 200)),
+                     "diagL_over_sigma_geomean": round(float(np.exp(np.mean(np.log(r)))), 4),
+                     "rank_k_frobenius": ek}
+        log(f"  accuracy {name}: {out[name]}")
+        del Ad, Q, L, P
+    return {"workload": "Section 5.2 families, n = 1000, Algorithm 1 (d = n, q = 0), fp64",
+            "families": out}
 
 
 def workload_c3(args):
     """`--workload c3`: the precision-form leg as its own JSON line."""
-    r = c3_leg(args.steps, args.warmup, oracle=not args.no_cpu_baseline)
+    r, _ = c3_leg(args.steps, args.warmup, keep_host=False)
     b = r["forms"]["bf16x3"]
     print(json.dumps({
         "metric": "Rand-QLP GFLOP/s, precision form (bf16 products, split bf16 projection) vs fp64",
@@ -353,7 +456,7 @@ def workload_c3(args):
 
 def workload_batched(args):
     """`--workload batched`: the batched leg as its own JSON line."""
-    r = c4_leg(args.steps, args.warmup)
+    r, _ = c4_leg(args.steps, args.warmup)
     print(json.dumps({
         "metric": "Rand-QLP GFLOP/s, batched form", "value": r["gflops"], "unit": "GFLOP/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -374,6 +477,10 @@ def main():
     ap.add_argument("--no-headline", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the 20000 x 16000 precision-form leg")
     ap.add_argument("--no-c4", action="store_true", help="skip the 512-matrix batched leg")
+    ap.add_argument("--no-fullrank", action="store_true",
+                    help="skip the full-rank (d = n, q = 0) leg at the paper's orders")
+    ap.add_argument("--no-accuracy", action="store_true",
+                    help="skip the rank-revealing accuracy leg on the n = 1000 families")
     ap.add_argument("--workload", choices=["c2", "c3", "batched"], default="c2",
                     help="c2 (default): 8000 x 8000 rank-200 + noise; c3: the precision form "
                          "at 20000 x 16000; batched: 512 uneven matrices")
@@ -449,16 +556,39 @@ def main():
     if not args.no_headline and args.precision == "f64" and args.size == 8000:
         log("headline: bf16 + learned q vs fp64 q = 2")
         head = headline(rq, Ad, k, p, max(3, args.steps // 4), precision="bf16x3")
-    c3 = c4 = None
-    if not args.no_c3 and args.precision == "f64" and args.size == 8000:
-        c3 = c3_leg(3, 1, oracle=not args.no_cpu_baseline)
-    if not args.no_c4 and args.precision == "f64" and args.size == 8000:
-        c4 = c4_leg(5, 1)
+    c3 = c4 = fr = acc = None
+    checks = {}
+    big = args.precision == "f64" and args.size == 8000
+    if not args.no_c3 and big:
+        c3, Ah = c3_leg(3, 1, keep_host=not args.no_cpu_baseline)
+        checks["c3"] = (Ah, c3.pop("oracle_args"))
+    if not args.no_c4 and big:
+        c4, checks["c4"] = c4_leg(5, 1)
+    if not args.no_fullrank and big:
+        log("full-rank Algorithm 1 (d = n, q = 0)")
+        fr, checks["fullrank"] = fullrank_leg()
+    if not args.no_accuracy and big:
+        log("rank-revealing accuracy on the Section 5.2 families")
+        acc = accuracy_leg()
     cpu = None
     e_orc = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu, e_orc = cpu_baseline(A64, k, p, q, flops)
+        cpu, e_orc, oc = cpu_baseline(A64, k, p, q, flops, checks)
+        if "c3" in oc:
+            c3["oracle"] = oc["c3"]
+            for f_ in c3["forms"].values():
+                f_["e_over_oracle"] = f_["e"] / oc["c3"]["e"]
+            c3["errors_within_1.05_of_oracle"] = bool(all(
+                f_["e_over_oracle"] <= 1.05 for f_ in c3["forms"].values()))
+        if "c4" in oc:
+            mr = max(x["ratio"] for x in oc["c4"])
+            c4["oracle_sample"] = {"count": len(oc["c4"]), "max_ratio": mr,
+                                   "errors_within_1.05_of_oracle": bool(mr <= 1.05),
+                                   "cases": oc["c4"]}
+        if "fullrank" in oc:
+            fr["oracle_check"] = oc["fullrank"]
+    del checks
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
@@ -482,6 +612,8 @@ def main():
         "headline": head,
         "c3": c3,
         "c4": c4,
+        "fullrank": fr,
+        "accuracy": acc,
     }
     print(json.dumps(out, default=_plain), flush=True)
 
