@@ -173,6 +173,22 @@ rqlp_status randqlp_factor(const void* A, int64_t m, int64_t n, int k, int p, in
                            uint64_t seed, void* Q, void* L, void* P,
                            const rqlp_opts* opts);
 
+/* randqlp_factor for a sparse A (Section 5.1 factors sparse matrices), given
+ * in CSR form on the device: row i's entries are colind[t], vals[t] for t
+ * in [rowptr[i], rowptr[i + 1]) (rowptr: m + 1 int64, rowptr[0] = 0,
+ * rowptr[m] = nnz; colind: nnz int32 in [0, n), any order within a row,
+ * repeated positions add up; vals: nnz values of opts->precision, RQLP_F64
+ * or RQLP_F32).  The products with A and A^T run as sparse products (A^T
+ * is built in the workspace from the CSR arrays); everything else is
+ * randqlp_factor's, and the outputs are those of randqlp_factor on the
+ * dense A, up to the order of the sums.  The arrays are checked on the
+ * device first: an invalid structure returns RQLP_E_INVALID_ARG before any
+ * product reads them.  m, n < 2^21.  opts->lda is ignored; the workspace is
+ * the library's (opts->workspace is not used).  Synchronous. */
+rqlp_status randqlp_factor_csr(const int64_t* rowptr, const int32_t* colind, const void* vals,
+                               int64_t m, int64_t n, int64_t nnz, int k, int p, int q,
+                               uint64_t seed, void* Q, void* L, void* P, const rqlp_opts* opts);
+
 /* randqlp_factor for callers that cannot allocate memory (tight serving
  * loops, harnesses that forbid allocation at run time): the same method and
  * kernels, with the call's scratch taken from a static device array of

@@ -13,7 +13,7 @@ import contextlib
 import ctypes
 import os
 
-__all__ = ["factor", "factor_noalloc", "factor_auto", "Batch", "factor_batched", "tune_save", "tune_load", "features", "mlp_forward", "mlp_loss_grad", "mlp_adam",
+__all__ = ["factor", "factor_noalloc", "factor_csr", "factor_auto", "Batch", "factor_batched", "tune_save", "tune_load", "features", "mlp_forward", "mlp_loss_grad", "mlp_adam",
            "mlp_train", "gaussian", "gemm", "orth", "sketch_width", "workspace_size",
            "colmajor", "empty_colmajor", "lib", "RandQLPError", "F64", "F32", "MIXED_BF16",
            "MIXED_F16", "MIXED_BF16X3",
@@ -32,7 +32,8 @@ STATUS = {0: "RQLP_OK", 1: "RQLP_E_INVALID_ARG", 2: "RQLP_E_NONFINITE", 3: "RQLP
 
 # Every symbol include/randqlp.h declares.
 EXPORTS = ["rqlp_opts_default", "randqlp_sketch_width", "randqlp_workspace_size",
-           "randqlp_factor", "randqlp_factor_noalloc", "randqlp_factor_auto", "randqlp_features", "randqlp_mlp_forward",
+           "randqlp_factor", "randqlp_factor_noalloc", "randqlp_factor_csr",
+           "randqlp_factor_auto", "randqlp_features", "randqlp_mlp_forward",
            "randqlp_mlp_loss_grad", "randqlp_mlp_adam", "randqlp_mlp_train",
            "randqlp_batch_create", "randqlp_batch_run", "randqlp_batch_query",
            "randqlp_batch_destroy", "randqlp_factor_batched", "randqlp_tune_save",
@@ -121,6 +122,9 @@ def lib():
     L.randqlp_factor.restype = i32
     L.randqlp_factor_noalloc.argtypes = [vp, i64, i64, i32, i32, i32, u64, vp, vp, vp,
                                          ctypes.POINTER(Opts)]
+    L.randqlp_factor_csr.argtypes = [vp, vp, vp, i64, i64, i64, i32, i32, i32, u64, vp, vp, vp,
+                                     ctypes.POINTER(Opts)]
+    L.randqlp_factor_csr.restype = i32
     L.randqlp_factor_noalloc.restype = i32
     L.randqlp_factor_auto.argtypes = [vp, i64, i64, i32, i32, i32, u64, vp, vp, vp, vp,
                                       ctypes.POINTER(Opts), ctypes.POINTER(AutoInfo)]
@@ -305,6 +309,46 @@ def factor(A, k, p, q, seed, panel="auto", precision=None, return_info=False):
                                     ctypes.c_void_p(Q.data_ptr()), ctypes.c_void_p(L.data_ptr()),
                                     ctypes.c_void_p(P.data_ptr()), ctypes.byref(o)))
     del ws
+    if return_info:
+        return Q, L, P, info.as_dict()
+    return Q, L, P
+
+
+def factor_csr(rowptr, colind, vals, shape, k, p, q, seed, panel="auto", return_info=False):
+    """Rand-QLP of a sparse device matrix in CSR form: rowptr (m + 1, int64),
+    colind (nnz, int32), vals (nnz, float64 or float32), shape = (m, n).
+    Returns (Q, L, P) as factor() does for the dense matrix."""
+    torch = _torch()
+    m, n = int(shape[0]), int(shape[1])
+    if not (rowptr.is_cuda and colind.is_cuda and vals.is_cuda):
+        raise ValueError("CSR arrays must be device tensors")
+    if rowptr.dtype != torch.int64 or colind.dtype != torch.int32:
+        raise TypeError("rowptr must be int64 and colind int32")
+    if rowptr.numel() != m + 1 or colind.numel() != vals.numel():
+        raise ValueError("rowptr needs m + 1 entries and colind / vals nnz each")
+    rowptr, colind, vals = rowptr.contiguous(), colind.contiguous(), vals.contiguous()
+    nnz = vals.numel()
+    d = sketch_width(m, n, k, p)
+    if d < 1:
+        _check(lib().randqlp_factor(None, m, n, k, p, q, 0, None, None, None, None))
+    dev = vals.device
+    Q = empty_colmajor(m, d, vals.dtype, dev)
+    P = empty_colmajor(n, d, vals.dtype, dev)
+    L = empty_colmajor(d, d, torch.float64, dev)
+    o = default_opts()
+    o.precision = _precision(vals.dtype)
+    o.panel_qr = _PANELS[panel] if isinstance(panel, str) else int(panel)
+    o.ldq, o.ldl, o.ldp = _ld(Q), _ld(L), _ld(P)
+    o.stream = _stream_ptr(dev)
+    info = Info()
+    o.info = ctypes.pointer(info)
+    with _on_device(dev):
+        _check(lib().randqlp_factor_csr(ctypes.c_void_p(rowptr.data_ptr()),
+                                        ctypes.c_void_p(colind.data_ptr()),
+                                        ctypes.c_void_p(vals.data_ptr()), m, n, nnz, k, p, q,
+                                        seed, ctypes.c_void_p(Q.data_ptr()),
+                                        ctypes.c_void_p(L.data_ptr()),
+                                        ctypes.c_void_p(P.data_ptr()), ctypes.byref(o)))
     if return_info:
         return Q, L, P, info.as_dict()
     return Q, L, P

@@ -77,6 +77,7 @@ size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
 constexpr int kPredCols = 64;  // sketch columns the predictor reads
 constexpr int kRankMaxD = 4096;  // widest sketch of the rank-predicting form (rank scan in LDS)
+constexpr int64_t kSparseMaxRows = (int64_t)1 << 21;  // sparse products: rows per grid dimension
 // Offsets of the MLP parameters [W1 b1 W2 b2 W3 b3] (floats).
 constexpr int kNI = RQLP_MLP_INPUTS, kNH = RQLP_MLP_HIDDEN, kNC = RQLP_MLP_CLASSES;
 constexpr int64_t kOW1 = 0, kOB1 = kOW1 + kNI * kNH, kOW2 = kOB1 + kNH, kOB2 = kOW2 + kNH * kNH,
@@ -225,6 +226,12 @@ struct Ctx {
   Dtype dt;
   int mixed = 0;  // 0: no; 1: bf16 products; 2: fp16 products; 3: bf16 + split projection
   bool noalloc = false;  // no allocation of any kind (static scratch, pageable read-backs)
+  // sparse input: A and A^T in CSR form, and the panel scratch of the sparse
+  // products (offsets into ws); null for a dense A
+  const CsrView* sp = nullptr;
+  const CsrView* spt = nullptr;
+  size_t sp_xr = 0, sp_cr = 0;
+  size_t extra_off = 0;  // start of the caller-specific region after the layout
   char* ws;
   Layout lay;
   int64_t d;
@@ -537,6 +544,9 @@ struct FactorArgs {
 // asks for fp32 accuracy: the fp32 product, or the split bf16 product.
 hipError_t prod(Ctx& c, const FactorArgs& f, int trans_a, const void* X, int64_t ldx, void* C,
                 int64_t ldc, bool full = false) {
+  if (c.sp)  // sparse A: A^T X uses the CSR form of A^T
+    return launch_spmm(trans_a ? *c.spt : *c.sp, X, ldx, c.d, C, ldc, c.dt, c.ws + c.sp_xr,
+                       c.ws + c.sp_cr, c.st);
   const int64_t rows = trans_a ? f.n : f.m, K = trans_a ? f.m : f.n;
   if (c.mixed && !full)
     return gemm16(c, trans_a, f.m, f.n, (const float*)X, ldx, (float*)C, ldc, c.d);
@@ -835,7 +845,7 @@ rqlp_status setup_factor(const void* A, int64_t m, int64_t n, int k, int p, int 
                          uint64_t seed, void* Q, void* L, void* P, const rqlp_opts* opts,
                          bool autoq, Ctx& c, FactorArgs& f, rqlp_opts& o,
                          std::unique_lock<std::mutex>& lk, bool noalloc = false,
-                         int rank_kmax = 0) {
+                         int rank_kmax = 0, size_t extra = 0) {
   if (opts)
     o = *opts;
   else
@@ -873,9 +883,10 @@ rqlp_status setup_factor(const void* A, int64_t m, int64_t n, int k, int p, int 
     if (o.workspace != nullptr)
       return fail(RQLP_E_INVALID_ARG, "opts->workspace must be NULL: this entry point uses the "
                   "library's static scratch");
-    if (c.lay.total > kStaticScratchBytes)
+    c.extra_off = align_up(c.lay.total);
+    if (c.extra_off + extra > kStaticScratchBytes)
       return fail(RQLP_E_WORKSPACE, "these sizes need %zu bytes of scratch; the static scratch "
-                  "holds %zu (use randqlp_factor with a workspace)", c.lay.total,
+                  "holds %zu (use randqlp_factor with a workspace)", c.extra_off + extra,
                   kStaticScratchBytes);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64)
@@ -889,7 +900,8 @@ rqlp_status setup_factor(const void* A, int64_t m, int64_t n, int k, int p, int 
     const size_t bytes = rank_kmax > 0 ? rank_layout_bytes(m, n, p, rank_kmax, dt, mixed != 0,
                                                            mixed == 3)
                                        : c.lay.total;
-    s = acquire_ws(o, bytes, &c.ws, lk);
+    c.extra_off = align_up(bytes);
+    s = acquire_ws(o, c.extra_off + extra, &c.ws, lk);
     if (s != RQLP_OK) return s;
   }
   f = FactorArgs{A, m, n, lda, q, Q, ldq, (double*)L, ldl, P, ldp};
@@ -920,7 +932,14 @@ rqlp_status run_with_escalation(Ctx& c, const FactorArgs& f, const rqlp_opts& o,
     if (fl[0] & FLAG_NONFINITE) {
       int fin[4] = {0, 0, 0, 0};
       e = clear_flags(c);
-      if (e == hipSuccess) e = launch_check_finite(f.A, f.m, f.n, f.lda, c.dt, c.flags(), c.st);
+      if (e == hipSuccess) {
+        if (c.sp)  // the stored entries of a sparse A, as one row
+          e = c.sp->nnz > 0 ? launch_check_finite(c.sp->vals, 1, c.sp->nnz, 1, c.dt, c.flags(),
+                                                  c.st)
+                            : hipSuccess;
+        else
+          e = launch_check_finite(f.A, f.m, f.n, f.lda, c.dt, c.flags(), c.st);
+      }
       if (e != hipSuccess) return fail(RQLP_E_HIP, "finite check: %s", hipGetErrorString(e));
       if ((s = read_flags(c, fin)) != RQLP_OK) return s;
       if (fin[0] & FLAG_NONFINITE) return fail(RQLP_E_NONFINITE, "A holds NaN or Inf");
@@ -1151,6 +1170,63 @@ rqlp_status randqlp_factor(const void* A, int64_t m, int64_t n, int k, int p, in
   std::unique_lock<std::mutex> lk;
   rqlp_status s = setup_factor(A, m, n, k, p, q, seed, Q, L, P, opts, false, c, f, o, lk);
   if (s != RQLP_OK) return s;
+  Outcome r;
+  if ((s = run_with_escalation(c, f, o, start_mode(o), r)) != RQLP_OK) return s;
+  fill_info(o, c.d, q, r);
+  g_last_error.clear();
+  return RQLP_OK;
+}
+
+rqlp_status randqlp_factor_csr(const int64_t* rowptr, const int32_t* colind, const void* vals,
+                               int64_t m, int64_t n, int64_t nnz, int k, int p, int q,
+                               uint64_t seed, void* Q, void* L, void* P, const rqlp_opts* opts) {
+  if (nnz < 0) return fail(RQLP_E_INVALID_ARG, "nnz = %lld must be >= 0", (long long)nnz);
+  if (!rowptr || (nnz > 0 && (!colind || !vals)))
+    return fail(RQLP_E_INVALID_ARG, "null CSR array");
+  rqlp_opts o0;
+  if (opts)
+    o0 = *opts;
+  else
+    rqlp_opts_default(&o0);
+  o0.lda = 0;  // no dense A
+  o0.workspace = nullptr;  // the layout has sparse regions: the library's cache
+  o0.workspace_bytes = 0;
+  if (o0.precision != RQLP_F64 && o0.precision != RQLP_F32)
+    return fail(RQLP_E_UNSUPPORTED, "sparse input takes precision RQLP_F64 or RQLP_F32");
+  if (m >= kSparseMaxRows || n >= kSparseMaxRows)
+    return fail(RQLP_E_UNSUPPORTED, "sparse input needs m, n < %lld", (long long)kSparseMaxRows);
+  const Dtype dt = o0.precision == RQLP_F64 ? DT_F64 : DT_F32;
+  const int64_t d = randqlp_sketch_width(m, n, k, p);
+  const size_t es = elem_size(dt);
+  const size_t panel = d > 0 ? align_up((size_t)std::max(m, n) * d * es) : 0;
+  const size_t tb = align_up(csr_transpose_bytes(n, nnz, dt));
+  Ctx c;
+  FactorArgs f;
+  rqlp_opts o;
+  std::unique_lock<std::mutex> lk;
+  rqlp_status s = setup_factor(rowptr, m, n, k, p, q, seed, Q, L, P, &o0, false, c, f, o, lk,
+                               false, 0, tb + 2 * panel + 256);
+  if (s != RQLP_OK) return s;
+  char* tws = c.ws + c.extra_off;
+  c.sp_xr = c.extra_off + tb;
+  c.sp_cr = c.sp_xr + panel;
+  int* bad = (int*)(c.ws + c.sp_cr + panel);
+  // structure check before any kernel indexes with the arrays
+  int hbad = 0;
+  hipError_t e = launch_zero_ints(bad, 1, c.st);
+  if (e == hipSuccess) e = launch_csr_check(rowptr, colind, m, n, nnz, bad, c.st);
+  if (e == hipSuccess)
+    e = read_back(c.st, &hbad, bad, sizeof(int), nullptr, nullptr, 0, !c.noalloc);
+  if (e != hipSuccess) return fail(RQLP_E_HIP, "CSR check: %s", hipGetErrorString(e));
+  if (hbad)
+    return fail(RQLP_E_INVALID_ARG, "CSR arrays invalid (%s)",
+                (hbad & 1) ? "rowptr must rise from 0 to nnz" : "column index outside [0, n)");
+  const CsrView A{rowptr, colind, vals, m, n, nnz};
+  CsrView At;
+  e = launch_csr_transpose(rowptr, colind, vals, m, n, nnz, dt, tws, &At, c.st);
+  if (e != hipSuccess) return fail(RQLP_E_HIP, "CSR transpose: %s", hipGetErrorString(e));
+  c.sp = &A;
+  c.spt = &At;
   Outcome r;
   if ((s = run_with_escalation(c, f, o, start_mode(o), r)) != RQLP_OK) return s;
   fill_info(o, c.d, q, r);

@@ -164,6 +164,31 @@ hipError_t launch_count_flags(const int* col_flags, int64_t d, int* count, hipSt
 hipError_t launch_check_finite(const void* A, int64_t m, int64_t n, int64_t lda, Dtype dt,
                                int* flags, hipStream_t st);
 
+// ---- sparse.hip ----
+// A CSR matrix on the device: rows x cols, row i's entries at
+// [rowptr[i], rowptr[i + 1]) of colind / vals (vals of the panel type).
+struct CsrView {
+  const int64_t* rowptr;
+  const int32_t* colind;
+  const void* vals;
+  int64_t rows, cols, nnz;
+};
+// Raise *bad (a device int) unless rowptr[0] = 0, rowptr is non-decreasing,
+// rowptr[rows] = nnz and every column index lies in [0, cols).
+hipError_t launch_csr_check(const int64_t* rowptr, const int32_t* colind, int64_t rows,
+                            int64_t cols, int64_t nnz, int* bad, hipStream_t st);
+// Device bytes of the transpose of an m x n CSR matrix with nnz entries.
+size_t csr_transpose_bytes(int64_t n, int64_t nnz, Dtype dt);
+// A^T of a (checked) m x n CSR matrix in CSR form, built in ws
+// (csr_transpose_bytes); entries of each row of A^T in ascending column order.
+hipError_t launch_csr_transpose(const int64_t* rowptr, const int32_t* colind, const void* vals,
+                                int64_t m, int64_t n, int64_t nnz, Dtype dt, void* ws,
+                                CsrView* out, hipStream_t st);
+// C (A.rows x d, ldc) = A X (X: A.cols x d, ldx), both column-major; xr and
+// cr hold A.cols x d and A.rows x d elements of scratch.  rows < 2^21.
+hipError_t launch_spmm(const CsrView& A, const void* X, int64_t ldx, int64_t d, void* C,
+                       int64_t ldc, Dtype dt, void* xr, void* cr, hipStream_t st);
+
 // ---- launch planning shared by the product kernels (gemm.hip) ----
 int cu_count();
 void choose_splits(int64_t tiles, int64_t K, int bk, int64_t max_s, int64_t slots,

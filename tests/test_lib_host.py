@@ -188,3 +188,18 @@ def test_auto_rank_mode_validates(L):
     assert L.randqlp_factor_auto(*args, ctypes.byref(o), None) == 1
     o.tol, o.k_max = 0.1, 5000
     assert L.randqlp_factor_auto(*args, ctypes.byref(o), None) == 6
+
+
+def test_csr_entry_validates_on_the_host(L):
+    dummy = ctypes.c_void_p(256)
+    # nnz < 0, null arrays, 16-bit precision, too many rows
+    assert L.randqlp_factor_csr(dummy, dummy, dummy, 10, 10, -1, 3, 1, 0, 0, dummy, dummy,
+                                dummy, None) == 1
+    assert L.randqlp_factor_csr(dummy, None, dummy, 10, 10, 5, 3, 1, 0, 0, dummy, dummy,
+                                dummy, None) == 1
+    o = rq.default_opts()
+    o.precision = rq.MIXED_BF16
+    assert L.randqlp_factor_csr(dummy, dummy, dummy, 10, 10, 5, 3, 1, 0, 0, dummy, dummy,
+                                dummy, ctypes.byref(o)) == 6
+    assert L.randqlp_factor_csr(dummy, dummy, dummy, 1 << 21, 10, 5, 3, 1, 0, 0, dummy, dummy,
+                                dummy, None) == 6

@@ -170,3 +170,34 @@ def device_batch(count, seed, lo=256, hi=4096, alpha=(0.5, 3.0), kr=(8, 128)):
         sig = torch.arange(1, r + 1, dtype=torch.float32) ** (-sp["alpha"])
         As.append(device_svd_matrix(sp["m"], sp["n"], sig, gen, torch.float32))
     return As, specs
+
+
+def sparse_standin(m, n, per_row, seed, band=2):
+    """A sparse m x n stand-in for the sparse, square, non-symmetric test
+    matrices of Section 5.1 (their entries are not reproduced): in each row
+    the diagonal entry (when i < n), the entries within `band` of it, and
+    `per_row` further columns drawn uniformly; values N(0, 1); duplicate
+    positions merged.  Returns CSR arrays (rowptr int64, colind int32,
+    vals float64), columns ascending within a row."""
+    g = rng(seed, STREAM_NOISE)
+    rowptr = np.zeros(m + 1, dtype=np.int64)
+    cols, vals = [], []
+    for i in range(m):
+        c = list(range(max(0, i - band), min(n, i + band + 1))) if i < n + band else []
+        c.extend(int(x) for x in g.integers(0, n, per_row))
+        c = np.unique(np.asarray(c, dtype=np.int64))
+        cols.append(c.astype(np.int32))
+        vals.append(g.standard_normal(c.size))
+        rowptr[i + 1] = rowptr[i] + c.size
+    colind = np.concatenate(cols) if cols else np.zeros(0, np.int32)
+    v = np.concatenate(vals) if vals else np.zeros(0)
+    return rowptr, colind, v
+
+
+def csr_to_dense(rowptr, colind, vals, m, n):
+    """Dense column-major copy of a CSR matrix (for the dense checks)."""
+    A = np.zeros((m, n), order="F")
+    for i in range(m):
+        a, b = rowptr[i], rowptr[i + 1]
+        np.add.at(A, (i, colind[a:b]), vals[a:b])     # repeated positions add up
+    return A
