@@ -12,9 +12,10 @@ kernel that streams A, timed with HIP events on its stream) and the fp64 CPU
 oracle timed on a bounded sample of the same workload.  Extra keys:
 headline (bf16 precision form + learned q against fp64 q = 2), c3 (the
 precision form at 20000 x 16000), c4 (512 uneven matrices, batched),
-fullrank (Algorithm 1 at d = n at the paper's orders), accuracy (diag(L)
+fullrank (Algorithm 1 at d = n at the paper's orders), sparse (the CSR
+input on sparse stand-ins at the same orders), accuracy (diag(L)
 and rank-k errors on the Section 5.2 families).  Every oracle run -- the
-CPU baseline and the error checks of c3, c4 and fullrank -- happens in the
+CPU baseline and the error checks of c3, c4, fullrank and sparse -- happens in the
 cpu_baseline leg.
 """
 import argparse
@@ -151,6 +152,17 @@ def cpu_baseline(A, k, p, q, flops, checks=None, budget_s=15.0, max_reps=40):
             out.append({key: smp[key] for key in ("i", "m", "n", "k", "alpha")} |
                        {"e": smp["e"], "e_oracle": e_o, "ratio": smp["e"] / e_o})
         res["c4"] = out
+    if checks.get("sparse") is not None:
+        c = checks["sparse"]
+        rp, ci, va = c["csr"]
+        n = c["n"]
+        Ah = np.zeros((n, n), order="F")
+        for i in range(n):
+            np.add.at(Ah, (i, ci[rp[i]:rp[i + 1]]), va[rp[i]:rp[i + 1]])
+        Qo, Lo, Po = randqlp(Ah, n, 0, 0, seed=0)
+        res["sparse"] = {"n": n, "e_oracle": rel_error(Ah, Qo, Lo, Po), "e": c["e"],
+                         "max_diagL_diff_over_L11": float(np.abs(np.diag(Lo) - c["diagL"]).max()
+                                                          / Lo[0, 0])}
     if checks.get("fullrank") is not None:
         c = checks["fullrank"]
         Ah, n = c["A"], c["n"]
@@ -401,6 +413,54 @@ def fullrank_leg(reps=3, sizes=(1856, 2904, 4929, 6747, 7320)):
             "flop_count": "8n^3 + 3n^3 - 2n^2 (Section 4.2, m = n)", "cases": rows}, check
 
 
+def sparse_leg(reps=3, sizes=(1856, 2904, 4929, 6747, 7320), per_row=8):
+    """Sparse input (randqlp_factor_csr) on stand-ins for Section 5.1's sparse
+    test matrices at the orders of its Table 1: the diagonal, a +-2 band and
+    `per_row` random columns per row, N(0,1) values.  Full rank (d = n,
+    q = 0, as the paper runs it; its count 8n^3 + 3n^3 - 2n^2) and the
+    truncated form (k = 100, p = 10, q = 2).  Returns (result, the smallest
+    matrix's CSR arrays and GPU factors' error for the oracle check)."""
+    import numpy as np
+    import torch
+
+    import paper_2110_01011_amd as rq
+    import workloads as W
+    rows, check = [], None
+    for n in sizes:
+        rp, ci, va = W.sparse_standin(n, n, per_row, seed=n)
+        dev = (torch.from_numpy(rp).cuda(), torch.from_numpy(ci).cuda(),
+               torch.from_numpy(va).cuda())
+        row = {"n": n, "nnz": int(rp[-1])}
+        for tag, (k, p, q) in (("full_rank", (n, 0, 0)), ("k100_q2", (100, 10, 2))):
+            rq.factor_csr(*dev, (n, n), k, p, q, 0)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                Q, L, P = rq.factor_csr(*dev, (n, n), k, p, q, 0)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            row[tag + "_ms"] = round(float(np.median(ts)) * 1e3, 2)
+            if tag == "full_rank":
+                fl = 8.0 * n ** 3 + 3.0 * n ** 3 - 2.0 * n ** 2
+                row["full_rank_gflops_paper_count"] = round(fl / float(np.median(ts)) / 1e9, 1)
+                if check is None:
+                    Ad = rq.colmajor(torch.from_numpy(np.ascontiguousarray(
+                        W.csr_to_dense(rp, ci, va, n, n).T)).cuda().t())
+                    check = {"csr": (rp, ci, va), "n": n, "e": device_rel_error(Ad, Q, L, P),
+                             "diagL": np.diag(L.cpu().numpy()).copy()}
+                    del Ad
+            del Q, L, P
+        cpu_s, hyb_s = PAPER_FIG2_S.get(n, (None, None))
+        row["paper_fig2_cpu_s"], row["paper_fig2_hybrid_s"] = cpu_s, hyb_s
+        rows.append(row)
+        log(f"  sparse n={n}: {row}")
+        del dev
+        torch.cuda.empty_cache()
+    return {"workload": f"sparse stand-ins (diagonal, +-2 band, {per_row} random columns per row, "
+                        "N(0,1)), n x n, fp64, randqlp_factor_csr", "cases": rows}, check
+
+
 def accuracy_leg():
     """Section 5.2's four n = 1000 families (LowRankPlusNoise, FastDecay,
     S-shaped, SlowDecay) through Algorithm 1 (d = n, q = 0): how closely
@@ -479,6 +539,8 @@ def main():
     ap.add_argument("--no-c4", action="store_true", help="skip the 512-matrix batched leg")
     ap.add_argument("--no-fullrank", action="store_true",
                     help="skip the full-rank (d = n, q = 0) leg at the paper's orders")
+    ap.add_argument("--no-sparse", action="store_true",
+                    help="skip the sparse-input leg at the paper's orders")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the rank-revealing accuracy leg on the n = 1000 families")
     ap.add_argument("--workload", choices=["c2", "c3", "batched"], default="c2",
@@ -567,6 +629,10 @@ def main():
     if not args.no_fullrank and big:
         log("full-rank Algorithm 1 (d = n, q = 0)")
         fr, checks["fullrank"] = fullrank_leg()
+    sp = None
+    if not args.no_sparse and big:
+        log("sparse input (CSR) at the paper's orders")
+        sp, checks["sparse"] = sparse_leg()
     if not args.no_accuracy and big:
         log("rank-revealing accuracy on the Section 5.2 families")
         acc = accuracy_leg()
@@ -588,6 +654,8 @@ def main():
                                    "cases": oc["c4"]}
         if "fullrank" in oc:
             fr["oracle_check"] = oc["fullrank"]
+        if "sparse" in oc:
+            sp["oracle_check"] = oc["sparse"]
     del checks
 
     out = {
@@ -613,6 +681,7 @@ def main():
         "c3": c3,
         "c4": c4,
         "fullrank": fr,
+        "sparse": sp,
         "accuracy": acc,
     }
     print(json.dumps(out, default=_plain), flush=True)

@@ -237,6 +237,54 @@ __global__ __launch_bounds__(256) void convert_panel16_kernel(const float* __res
 // tile's sum of squares a^2 to rerr[nblocks + its linear index].  A16lo /
 // At16lo, if given, receive the rounded residual a - a16 (exact in fp32) in
 // the layout of A16 / At16.
+// Power-of-two exponent s with max|a| 2^s in [2^13, 2^14): the fp16 copy's
+// scale (finite values up to 65504, normal ones from 2^-14), so that the
+// largest entry sits well inside the range whatever ||A|| is.  0 for a zero
+// or non-finite maximum.
+__device__ __forceinline__ int f16_scale_exponent(unsigned amax_bits) {
+  const float mx = __uint_as_float(amax_bits);
+  if (!(mx > 0.0f) || !(mx <= 3.0e38f)) return 0;
+  int e = 0;
+  (void)frexpf(mx, &e);  // mx = f 2^e, f in [0.5, 1)
+  return min(max(14 - e, -100), 100);
+}
+
+// amax_bits = bit pattern of max |a| over A (m x n, lda); non-negative floats
+// order like their bit patterns, so an unsigned atomic max does.  *amax_bits
+// must start at zero.
+__global__ __launch_bounds__(256) void absmax_kernel(const float* __restrict__ A, int64_t m,
+                                                     int64_t n, int64_t lda,
+                                                     unsigned* __restrict__ amax_bits) {
+  __shared__ unsigned red[256];
+  unsigned mx = 0u;
+  const int64_t total = m * n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx % m, j = idx / m;
+    mx = max(mx, __float_as_uint(A[i + j * lda]) & 0x7fffffffu);
+  }
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(amax_bits, red[0]);
+}
+
+// C (rows x d, ldc) *= 2^-s with s = *scale_exp (undoes the fp16 copy's scale).
+__global__ __launch_bounds__(256) void unscale_kernel(float* __restrict__ C, int64_t rows,
+                                                      int64_t d, int64_t ldc,
+                                                      const int* __restrict__ scale_exp) {
+  const float f = ldexpf(1.0f, -*scale_exp);
+  const int64_t total = rows * d;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx % rows, j = idx / rows;
+    C[i + j * ldc] *= f;
+  }
+}
+
 template <typename T16>
 __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict__ A, int64_t m,
                                                         int64_t n, int64_t lda,
@@ -244,7 +292,9 @@ __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict_
                                                         T16* __restrict__ At16, int64_t ldt16,
                                                         double* __restrict__ rerr,
                                                         T16* __restrict__ A16lo,
-                                                        T16* __restrict__ At16lo) {
+                                                        T16* __restrict__ At16lo,
+                                                        const unsigned* __restrict__ amax_bits,
+                                                        int* __restrict__ scale_out) {
   typedef T16 pair_t __attribute__((ext_vector_type(2)));
   __shared__ T16 tile[64][66];
   __shared__ T16 tlo[64][66];
@@ -252,6 +302,10 @@ __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict_
   const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   const bool pairs = ((((uintptr_t)A) & 7) == 0) && ((lda & 1) == 0);
+  // the copy holds 2^s a (exact: a power of two); errors are taken unscaled
+  const int sexp = amax_bits ? f16_scale_exponent(*amax_bits) : 0;
+  const float sc = ldexpf(1.0f, sexp), inv = ldexpf(1.0f, -sexp);
+  if (scale_out && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *scale_out = sexp;
   double err = 0.0, nrm = 0.0;
   for (int jj = ty; jj < 64; jj += 8) {
     const int64_t i = i0 + 2 * tx, j = j0 + jj;
@@ -270,9 +324,10 @@ __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict_
     T16 v[2], vl[2];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
-      v[u] = to16(a[u], (T16*)nullptr);
-      vl[u] = to16(a[u] - (float)v[u], (T16*)nullptr);
-      const double e = (double)a[u] - (double)(float)v[u];
+      const float as = a[u] * sc;
+      v[u] = to16(as, (T16*)nullptr);
+      vl[u] = to16(as - (float)v[u], (T16*)nullptr);
+      const double e = (double)a[u] - (double)((float)v[u] * inv);
       err += e * e;
       nrm += (double)a[u] * (double)a[u];
     }
@@ -433,8 +488,19 @@ int64_t convert16_blocks(int64_t m, int64_t n) { return ((m + 63) / 64) * ((n + 
 
 hipError_t launch_convert16(const float* A, int64_t m, int64_t n, int64_t lda, void* A16,
                             int64_t ld16, void* At16, int64_t ldt16, bool f16, hipStream_t st,
-                            double* rerr, void* A16lo, void* At16lo) {
+                            double* rerr, void* A16lo, void* At16lo, unsigned* amax,
+                            int* scale_out) {
   if (m <= 0 || n <= 0) return hipSuccess;
+  if (f16 && amax) {  // the fp16 copy is scaled by a power of two from max |a|
+    hipError_t e = launch_zero_ints((int*)amax, 1, st);
+    if (e != hipSuccess) return e;
+    const int64_t tot = m * n;
+    const unsigned nb = (unsigned)std::min<int64_t>(2048, std::max<int64_t>(1, (tot + 255) / 256));
+    hipLaunchKernelGGL(absmax_kernel, dim3(nb), dim3(256), 0, st, A, m, n, lda, amax);
+  } else {
+    amax = nullptr;
+    scale_out = nullptr;
+  }
   // pair stores: even leading dimensions and 4-byte aligned copies
   if (ld16 < pad16(m) || ldt16 < pad16(n) || (ld16 & 1) || (ldt16 & 1) ||
       (((uintptr_t)A16 | (uintptr_t)At16 | (uintptr_t)A16lo | (uintptr_t)At16lo) & 3))
@@ -443,11 +509,19 @@ hipError_t launch_convert16(const float* A, int64_t m, int64_t n, int64_t lda, v
   if (f16)
     hipLaunchKernelGGL(convert16_kernel<_Float16>, grid, dim3(256), 0, st, A, m, n, lda,
                        (_Float16*)A16, ld16, (_Float16*)At16, ldt16, rerr, (_Float16*)A16lo,
-                       (_Float16*)At16lo);
+                       (_Float16*)At16lo, (const unsigned*)amax, scale_out);
   else
     hipLaunchKernelGGL(convert16_kernel<__bf16>, grid, dim3(256), 0, st, A, m, n, lda,
                        (__bf16*)A16, ld16, (__bf16*)At16, ldt16, rerr, (__bf16*)A16lo,
-                       (__bf16*)At16lo);
+                       (__bf16*)At16lo, (const unsigned*)nullptr, (int*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_unscale(float* C, int64_t rows, int64_t d, int64_t ldc, const int* scale_exp,
+                          hipStream_t st) {
+  if (rows <= 0 || d <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)std::min<int64_t>(2048, (rows * d + 255) / 256);
+  hipLaunchKernelGGL(unscale_kernel, dim3(nb), dim3(256), 0, st, C, rows, d, ldc, scale_exp);
   return hipGetLastError();
 }
 

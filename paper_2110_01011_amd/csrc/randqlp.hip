@@ -89,7 +89,7 @@ constexpr double kJudgeSlack = 0.0404;
 
 struct Layout {
   size_t m1, m2, n1, n2, part, part_bytes, G, R[4], Racc[2], Rfin, dinv, colf, scal, flags,
-      chs, tsub, tsr, a16, at16, p16, a16lo, p16lo, total;
+      chs, tsub, tsr, a16, at16, p16, a16lo, p16lo, amax, total;
   int64_t ld16, ldt16;  // leading dimensions of the 16-bit copies of A and A^T
   int64_t ldp16;        // leading dimension of the 16-bit copy of a panel
   // predictor and error judge (randqlp_factor_auto only)
@@ -174,9 +174,10 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
     L.at16 = take((size_t)L.ldt16 * m * 2);
     L.ldp16 = gemm16_ld(std::max(m, n));
     L.p16 = take((size_t)L.ldp16 * d * 2);
+    L.amax = take(16);  // max |a| of the fp16 form's scale
   } else {
     L.ld16 = L.ldt16 = L.ldp16 = 0;
-    L.a16 = L.at16 = L.p16 = 0;
+    L.a16 = L.at16 = L.p16 = L.amax = 0;
   }
   if (mixed && split) {
     L.a16lo = take((size_t)L.ld16 * n * 2);
@@ -458,8 +459,13 @@ hipError_t chol_pass(Ctx& c, const void* X, int64_t rows, int64_t ldx, void* Qx,
 //  ROBUST   shifted pass, completion of dependent columns, two more passes.
 enum PanelMode { PM_FAST = 0, PM_CHOLQR2 = 1, PM_ROBUST = 2 };
 
-// max |E| for which the first-order second pass is accurate to the
-// precision's rounding level (the neglected terms are O(|E|^2)).
+// max |E| for which the first-order second pass is used; the neglected terms
+// are O(|E|^2), so the final Q and P keep an orthogonality error of about
+// |E|^2: at most 1e-16 for fp64 panels (the rounding level), and at most
+// 1e-6 (about 17 fp32 units) for fp32 panels, whose factors are held to the
+// error bar of the reduced-precision forms (1.05x the fp64 error) rather than
+// to fp32 rounding; a larger |E| raises FLAG_SECOND_PASS and the call reruns
+// with two full passes.
 double first_order_tol(Dtype dt) { return dt == DT_F64 ? 1e-8 : 1e-3; }
 
 // orth(): X (rows x d, ldx) -> out (rows x d, ldo), using tmp (rows x d,
@@ -569,11 +575,12 @@ hipError_t stage_sketch(Ctx& c, const FactorArgs& f, PanelMode mode) {
   void* Zm = c.ws + c.lay.m1;
   void* Yn = c.ws + c.lay.n1;
   void* Tn = c.ws + c.lay.n2;
-  if (c.mixed)
+  if (c.mixed)  // (fp16: the copies carry a power-of-two scale, exponent in flags[3])
     HIP_TRY(launch_convert16((const float*)f.A, m, n, f.lda, c.ws + c.lay.a16, c.lay.ld16,
                              c.ws + c.lay.at16, c.lay.ldt16, c.mixed == 2, c.st,
                              c.lay.rerr ? c.at<double>(c.lay.rerr) : nullptr,
-                             c.lay.a16lo ? c.ws + c.lay.a16lo : nullptr));
+                             c.lay.a16lo ? c.ws + c.lay.a16lo : nullptr, nullptr,
+                             c.at<unsigned>(c.lay.amax), c.flags() + 3));
   HIP_TRY(prod(c, f, 1, Zm, m, Yn, n));                                        // A^T Omega
   return orth(c, Yn, n, n, Yn, n, Tn, nullptr, mode, false);                   // Qbar
 }
@@ -1100,6 +1107,7 @@ hipError_t judge(Ctx& c, const FactorArgs& f, double sums[4], int flags_out[4]) 
                     !c.noalloc));
   if (g_prof.on) prof_collect();
   sums[3] *= (double)d / (double)f.n;
+  if (c.mixed == 2) sums[2] = std::ldexp(sums[2], -2 * flags_out[3]);  // Z carries 2^s
   return hipSuccess;
 }
 
@@ -1593,11 +1601,14 @@ rqlp_status randqlp_gemm(int trans_a, const void* A, int64_t m, int64_t n, int64
     const size_t off_alo = off_x + align_up((size_t)ldx16 * d * 2);
     const size_t off_xlo = off_alo + (split ? align_up(bytes_op) : 0);
     const size_t off_p = off_xlo + (split ? align_up((size_t)ldx16 * d * 2) : 0);
-    rqlp_status s = acquire_ws(o, off_p + std::max<size_t>(part, 256), &ws, lk);
+    const size_t off_s = off_p + align_up(std::max<size_t>(part, 256));  // fp16 scale words
+    rqlp_status s = acquire_ws(o, off_s + 256, &ws, lk);
     if (s != RQLP_OK) return s;
+    unsigned* amax = (unsigned*)(ws + off_s);
+    int* sexp = (int*)(ws + off_s + 16);
     e = launch_convert16((const float*)A, m, n, lda, ws + off_a, ld16, ws + off_at, ldt16, f16, st,
                          nullptr, (split && trans_a) ? ws + off_alo : nullptr,
-                         (split && !trans_a) ? ws + off_alo : nullptr);
+                         (split && !trans_a) ? ws + off_alo : nullptr, amax, sexp);
     if (e == hipSuccess)
       e = launch_convert_panel16((const float*)X, K, d, ldx, ws + off_x, ldx16, f16, st,
                                  split ? ws + off_xlo : nullptr);
@@ -1620,6 +1631,8 @@ rqlp_status randqlp_gemm(int trans_a, const void* A, int64_t m, int64_t n, int64
         g.B2 = ws + off_xlo;
       }
       e = launch_gemm16(g, st);
+      if (e == hipSuccess && f16)  // the fp16 copy of A carried 2^s
+        e = launch_unscale((float*)C, rows, d, ldc, sexp, st);
     }
   } else {
     const Dtype dt = precision == RQLP_F64 ? DT_F64 : DT_F32;

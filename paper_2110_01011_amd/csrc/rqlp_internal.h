@@ -105,10 +105,19 @@ hipError_t launch_convert_panel16(const float* X, int64_t rows, int64_t d, int64
 // double for each of the nb = convert16_blocks(m, n) workgroups, followed by
 // the nb per-workgroup sums of squares of A (2 nb doubles in all).  A16lo /
 // At16lo (optional): the rounded residuals a - a16 in the layouts of A16 / At16.
+// f16 (amax, scale_out given): the copies hold 2^s a with s chosen from
+// max |a| (amax: one device unsigned of scratch) so that the largest entry
+// lies in [2^13, 2^14); *scale_out (device int) receives s.  rerr stays in
+// A's own units.  Products with the copies then carry the factor 2^s, which
+// orth() removes (exactly: a power of two) and launch_unscale undoes.
 hipError_t launch_convert16(const float* A, int64_t m, int64_t n, int64_t lda, void* A16,
                             int64_t ld16, void* At16, int64_t ldt16, bool f16, hipStream_t st,
                             double* rerr = nullptr, void* A16lo = nullptr,
-                            void* At16lo = nullptr);
+                            void* At16lo = nullptr, unsigned* amax = nullptr,
+                            int* scale_out = nullptr);
+// C (rows x d fp32, ldc) *= 2^-(*scale_exp).
+hipError_t launch_unscale(float* C, int64_t rows, int64_t d, int64_t ldc, const int* scale_exp,
+                          hipStream_t st);
 int64_t convert16_blocks(int64_t m, int64_t n);
 
 // ---- panel.hip ----

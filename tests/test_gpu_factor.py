@@ -222,3 +222,37 @@ def test_c3_full_size_precision_forms_vs_oracle(rq):
         log(f"  {prec}: e={e_g:.6e} oracle {e_o:.6e} ratio {e_g / e_o:.5f}")
         assert e_g <= 1.05 * e_o
         del Q, L, P
+
+
+@pytest.mark.parametrize("scale", [1e6, 1e-6, 3e-30])
+def test_f16_form_does_not_depend_on_the_scale_of_A(rq, scale):
+    """The fp16 copy of A is scaled by a power of two chosen from max |a|, so
+    c A factors with the relative error of A: no overflow to Inf for large
+    entries, no underflow for small ones.  The error is against the fp64
+    oracle on the unscaled A (the method's relative error does not depend on
+    c for the same Omega)."""
+    import torch
+    A, U, s, V = W.poly_decay(2000, 1500, 1.0, seed=61)
+    e_o = rel_error(A, *randqlp(A, 40, 10, 2, 3))
+    res = {}
+    for c in (1.0, scale):
+        Ac = c * A
+        Qg, Lg, Pg, info = _run(rq, Ac, 40, 10, 2, 3, dtype=torch.float32, precision="f16")
+        res[c] = rel_error(Ac, Qg, Lg, Pg)
+        log(f"  f16 scale {c:g}: e={res[c]:.6e} (oracle {e_o:.6e}) {info}")
+    assert res[scale] <= 1.05 * e_o
+    assert abs(res[scale] / res[1.0] - 1.0) < 1e-3
+
+
+def test_f16_step_product_with_large_entries(rq):
+    """randqlp_gemm in fp16 on entries near 1e6 (beyond fp16's 65504): the
+    product comes back in A's units within fp16 rounding."""
+    import torch
+    r = np.random.default_rng(3)
+    A = 1e6 * r.standard_normal((700, 500))
+    X = r.standard_normal((700, 30))
+    C = to_np(rq.gemm(to_dev(A, torch.float32), to_dev(X, torch.float32), True, precision="f16"))
+    ref = A.T @ X
+    err = np.abs(C - ref).max() / np.abs(ref).max()
+    log(f"  f16 A^T X with |a| ~ 1e6: max rel err {err:.2e}")
+    assert np.isfinite(C).all() and err < 5e-3
