@@ -526,6 +526,32 @@ def workload_batched(args):
         "c4": r}, default=_plain), flush=True)
 
 
+def workload_fullrank(args):
+    """`--workload fullrank`: Algorithm 1 at d = n at the paper's orders."""
+    r, _ = fullrank_leg(reps=args.steps)
+    c = r["cases"][-1]
+    print(json.dumps({
+        "metric": "Rand-QLP GFLOP/s, Algorithm 1 (d = n, q = 0), paper's flop count",
+        "value": c["gflops"], "unit": "GFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": c["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": r["workload"] + f", n = {c['n']}"}, "fullrank": r},
+        default=_plain), flush=True)
+
+
+def workload_sparse(args):
+    """`--workload sparse`: the CSR input on sparse stand-ins."""
+    r, _ = sparse_leg(reps=args.steps)
+    c = r["cases"][-1]
+    print(json.dumps({
+        "metric": "Rand-QLP time, sparse input (CSR), n x n stand-ins",
+        "value": c["full_rank_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": c["full_rank_ms"], "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": r["workload"] + f", n = {c['n']}"}, "sparse": r},
+        default=_plain), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -543,9 +569,11 @@ def main():
                     help="skip the sparse-input leg at the paper's orders")
     ap.add_argument("--no-accuracy", action="store_true",
                     help="skip the rank-revealing accuracy leg on the n = 1000 families")
-    ap.add_argument("--workload", choices=["c2", "c3", "batched"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c3", "batched", "fullrank", "sparse"],
+                    default="c2",
                     help="c2 (default): 8000 x 8000 rank-200 + noise; c3: the precision form "
-                         "at 20000 x 16000; batched: 512 uneven matrices")
+                         "at 20000 x 16000; batched: 512 uneven matrices; fullrank: Algorithm "
+                         "1 at d = n; sparse: the CSR input")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run a plain copy of this size first (for counter scaling)")
     args = ap.parse_args()
@@ -558,6 +586,10 @@ def main():
         return workload_c3(args)
     if args.workload == "batched":
         return workload_batched(args)
+    if args.workload == "fullrank":
+        return workload_fullrank(args)
+    if args.workload == "sparse":
+        return workload_sparse(args)
 
     import numpy as np
     import torch
