@@ -246,20 +246,27 @@ def headline(rq, A_c2, k, p, steps, precision="bf16"):
             "errors_within_1.05": all(c["error_ratio"] <= 1.05 for c in out)}
 
 
-def c3_leg(steps, warmup, keep_host=True):
+def c3_leg(steps, warmup, keep_host=True, gen="device"):
     """Precision form: 20000 x 16000, sigma_i = exp(-i/100) (rank 4000, Haar
     factors), k = 500, p = 20, q = 2 (d = 520).  Each form (bf16x3, bf16,
     f16, fp32, fp64) is timed on the resident matrix and its error
     ||A - Q L P^T||_F / ||A||_F is computed in fp64 against the fp64 A.
     Returns (result, host copy of A for the oracle check or None)."""
+    import numpy as np
     import torch
 
     import paper_2110_01011_amd as rq
     import workloads as W
     from paper_2110_01011_amd.metrics import randqlp_flops
     m, n, r, k, p, q = 20000, 16000, 4000, 500, 20, 2
-    log("c3: generating the 20000 x 16000 exp-decay matrix on the device")
-    A64 = rq.colmajor(W.device_exp_decay(m, n, r, 100.0, seed=3))
+    if gen == "host":  # (numpy: a different draw of the same family)
+        log("c3: generating the 20000 x 16000 exp-decay matrix on the host")
+        Ah0 = W.exp_decay(m, n, r, 100.0, seed=3)[0]
+        A64 = rq.colmajor(torch.from_numpy(np.ascontiguousarray(Ah0.T)).cuda().t())
+        del Ah0
+    else:
+        log("c3: generating the 20000 x 16000 exp-decay matrix on the device")
+        A64 = rq.colmajor(W.device_exp_decay(m, n, r, 100.0, seed=3))
     A32 = rq.colmajor(A64.float().t().contiguous().t())
     torch.cuda.synchronize()
     d = rq.sketch_width(m, n, k, p)
@@ -503,7 +510,7 @@ def accuracy_leg():
 
 def workload_c3(args):
     """`--workload c3`: the precision-form leg as its own JSON line."""
-    r, _ = c3_leg(args.steps, args.warmup, keep_host=False)
+    r, _ = c3_leg(args.steps, args.warmup, keep_host=False, gen=args.gen)
     b = r["forms"]["bf16x3"]
     print(json.dumps({
         "metric": "Rand-QLP GFLOP/s, precision form (bf16 products, split bf16 projection) vs fp64",
@@ -557,7 +564,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--precision", choices=["f64", "f32", "bf16x3"], default="f64",
+                    help="precision of the default workload's factorisation (bf16x3: the "
+                         "precision form with the split bf16 projection, on the fp32 A)")
+    ap.add_argument("--gen", choices=["device", "host"], default="device",
+                    help="c3: generate the matrix on the device (torch) or on the host (numpy)")
     ap.add_argument("--size", type=int, default=8000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-headline", action="store_true")
@@ -604,6 +615,7 @@ def main():
     log(f"generating {m}x{n} rank-{r} + noise matrix")
     A64, s = W.rank_plus_noise(m, n, r, 1e-3, seed=0)
     tdt = torch.float64 if args.precision == "f64" else torch.float32
+    fprec = None if args.precision in ("f64", "f32") else args.precision
     Ad = rq.colmajor(torch.from_numpy(np.ascontiguousarray(A64.T)).to(tdt).cuda().t())
     torch.cuda.synchronize()
     flops = randqlp_flops(m, n, d, q)
@@ -612,7 +624,7 @@ def main():
 
     log("warmup")
     for i in range(args.warmup):
-        rq.factor(Ad, k, p, q, seed=i)
+        rq.factor(Ad, k, p, q, seed=i, precision=fprec)
     torch.cuda.synchronize()
     rq.profile_read()
     rq.profile_enable(True)
@@ -621,7 +633,7 @@ def main():
     t0 = time.perf_counter()
     marks = [t0]
     for i in range(args.steps):
-        Q, L, P = rq.factor(Ad, k, p, q, seed=0)  # returns after the call's stream is done
+        Q, L, P = rq.factor(Ad, k, p, q, seed=0, precision=fprec)  # returns when done
         marks.append(time.perf_counter())
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -633,13 +645,15 @@ def main():
 
     avg_ms = kms / max(launches, 1)
     achieved = (kflops / max(launches, 1)) / (avg_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[args.precision]
+    peak = PEAK_TFLOPS["bf16" if fprec else args.precision]
     traffic = None
     if args.size == 8000:
         traffic = read_traffic(f"profiles/gemm_kernel_rank200_8000_{args.precision}_traffic.txt")
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
-                "kernel": "gemm_rem_kernel (fp64 products with A)", "avg_ms": round(avg_ms, 4),
+                "kernel": ("gemm16_kernel (16-bit products with A)" if fprec else
+                           f"gemm_rem_kernel ({args.precision} products with A)"),
+                "avg_ms": round(avg_ms, 4),
                 "flops_per_launch": kflops / max(launches, 1),
                 "bytes_per_launch": kbytes / max(launches, 1)}
 

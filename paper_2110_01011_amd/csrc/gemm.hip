@@ -301,6 +301,44 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const TP* __restrict
   }
 }
 
+// Small outputs with many splits (the d x d Gram matrices): four threads per
+// output element, thread q summing the splits q, q + 4, ... in order, then
+// the four quarters added in a fixed order -- deterministic, and four times
+// the loads in flight of one thread per element.  Element e = i + j M of the
+// tight M x N partials; gram_bm as in splitk_reduce_kernel.
+template <typename TP, typename TO>
+__global__ __launch_bounds__(256) void splitk_reduce4_kernel(const TP* __restrict__ P, int64_t M,
+                                                             int64_t N, int S,
+                                                             TO* __restrict__ C, int64_t ldc,
+                                                             int gram_bm) {
+  __shared__ TP part[4][64];
+  const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t total = M * N;
+  const int64_t e = (int64_t)blockIdx.x * 64 + l;
+  int64_t i = 0, j = 0;
+  TP s = (TP)0;
+  if (e < total) {
+    i = e % M;
+    j = e / M;
+    int64_t si = i, sj = j;
+    if (gram_bm > 0 && (i / gram_bm) > (j / gram_bm)) {
+      si = j;
+      sj = i;
+    }
+    const TP* p = P + si + sj * M;
+#pragma unroll 4
+    for (int t = q; t < S; t += 4) s += p[(int64_t)t * total];
+  }
+  part[q][l] = s;
+  __syncthreads();
+  if (q == 0 && e < total) C[i + j * ldc] = (TO)((part[0][l] + part[1][l]) + (part[2][l] + part[3][l]));
+}
+
+// The one-thread-per-element reduction is bound by the latency of its S
+// dependent loads when the output is small; above this many elements it has
+// enough threads.
+constexpr int64_t kReduce4MaxElems = (int64_t)1 << 20;
+
 dim3 splitk_reduce_grid(int64_t M, int64_t N) {
   return dim3((unsigned)((M + 511) / 512), (unsigned)N);
 }
@@ -506,9 +544,14 @@ hipError_t gemm_typed(const GemmArgs& g, hipStream_t st) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || direct) return e;
   const int gbm = g.gram ? kGramBM : 0;
-  hipLaunchKernelGGL((splitk_reduce_kernel<TO, TO>), splitk_reduce_grid(g.M, g.N),
-                     dim3(256), 0, st, (const TO*)g.partial, g.M, g.N, p.splits, (TO*)g.C,
-                     g.ldc, gbm, splitk_pairs((const TO*)g.partial, g.M, gbm));
+  if (g.M * g.N <= kReduce4MaxElems && p.splits >= 4)
+    hipLaunchKernelGGL((splitk_reduce4_kernel<TO, TO>),
+                       dim3((unsigned)((g.M * g.N + 63) / 64)), dim3(256), 0, st,
+                       (const TO*)g.partial, g.M, g.N, p.splits, (TO*)g.C, g.ldc, gbm);
+  else
+    hipLaunchKernelGGL((splitk_reduce_kernel<TO, TO>), splitk_reduce_grid(g.M, g.N),
+                       dim3(256), 0, st, (const TO*)g.partial, g.M, g.N, p.splits, (TO*)g.C,
+                       g.ldc, gbm, splitk_pairs((const TO*)g.partial, g.M, gbm));
   return hipGetLastError();
 }
 

@@ -28,8 +28,9 @@ namespace {
 //
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2); the linear workgroup id is remapped so that each XCD works through a
-// contiguous range of (row tile, column tile, split) items with the row tile
-// fastest: the panel chunk of one (column tile, split) then stays in one L2.
+// contiguous range of (column tile, row tile, split) items with the column
+// tile fastest: the workgroups of one row tile then read its rows of A
+// together from one L2, and the panel chunk of one split stays in that L2.
 //
 // Split bf16 product (A2, B2 given): with A = A16 + A2 and X = B16 + B2 split
 // into a rounded part and its rounding residual (both bf16), the splits
@@ -99,8 +100,11 @@ __global__ __launch_bounds__(64 * waves16(WN), waves16(WN) == 8 ? 1 : 2) void ge
 
   const int64_t T = (int64_t)gridDim.x;
   const int64_t w = xcd_remap(blockIdx.x, T);
-  const int tile_m = (int)(w % tiles_m);
-  const int tile_n = (int)((w / tiles_m) % tiles_n);
+  // column tile fastest: the tiles_n workgroups that read the same rows of A
+  // run side by side on one XCD, so A comes from HBM about once and the
+  // other column tiles find it in that XCD's L2
+  const int tile_n = (int)(w % tiles_n);
+  const int tile_m = (int)((w / tiles_n) % tiles_m);
   const int split = (int)(w / ((int64_t)tiles_m * tiles_n));
   const int seg = split / seg_splits;  // 0: A B, 1: A B2, 2: A2 B
   if (seg == 2) A = A2;
