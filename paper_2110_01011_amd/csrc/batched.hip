@@ -106,6 +106,11 @@ struct rqlp_batch {
   // candidate product sets per width (0 = per class)
   std::map<int, ProdSet> tn_alt, nn_alt, tnf_alt;
   hipStream_t cap = nullptr;
+  // side streams and events: the width classes of one product run side by
+  // side (forked from the calling stream and joined back, also in the graph)
+  static constexpr int kSide = 4;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork_ev = nullptr, join_ev[kSide] = {};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   // host staging of the tables
@@ -206,15 +211,37 @@ hipError_t run_gemm(const rqlp_batch* b, const Launch& l, Dtype in_t, Dtype out_
                              at<int4>(b, l.map), l.nblocks, st);
 }
 
+hipError_t run_part(const rqlp_batch* b, const ProdSet& ps, size_t i, int trans,
+                    hipStream_t st) {
+  const auto& pl = ps.parts[i];
+  return ps.rem ? launch_gemm_rem_grouped(b->dt, trans, pl.first,
+                                          at<GroupGemm>(b, pl.second.desc),
+                                          at<int4>(b, pl.second.map), pl.second.nblocks, st)
+                : run_gemm(b, pl.second, b->dt, b->dt, trans, false, pl.first, st);
+}
+
+// One product over all matrices: one launch per width class.  Classes after
+// the first go to the side streams (each waits for the calling stream's work
+// so far and the calling stream waits for them at the end), so the classes
+// overlap and one class's tail does not idle the device.
 hipError_t run_prod(const rqlp_batch* b, const ProdSet& ps, int trans, hipStream_t st) {
-  for (const auto& pl : ps.parts) {
-    hipError_t e =
-        ps.rem ? launch_gemm_rem_grouped(b->dt, trans, pl.first, at<GroupGemm>(b, pl.second.desc),
-                                         at<int4>(b, pl.second.map), pl.second.nblocks, st)
-               : run_gemm(b, pl.second, b->dt, b->dt, trans, false, pl.first, st);
-    if (e != hipSuccess) return e;
+  const size_t np = ps.parts.size();
+  if (np == 0) return hipSuccess;
+  const size_t nside = std::min<size_t>(np - 1, rqlp_batch::kSide);
+  if (nside == 0 || !b->fork_ev) return run_part(b, ps, 0, trans, st);
+  hipError_t e = hipEventRecord(b->fork_ev, st);
+  for (size_t i = 1; e == hipSuccess && i < np; ++i) {
+    const size_t sd = (i - 1) % nside;
+    hipStream_t ss = b->side[sd];
+    if (i <= nside) e = hipStreamWaitEvent(ss, b->fork_ev, 0);
+    if (e == hipSuccess) e = run_part(b, ps, i, trans, ss);
   }
-  return hipSuccess;
+  if (e == hipSuccess) e = run_part(b, ps, 0, trans, st);
+  for (size_t sd = 0; e == hipSuccess && sd < nside; ++sd) {
+    e = hipEventRecord(b->join_ev[sd], b->side[sd]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(st, b->join_ev[sd], 0);
+  }
+  return e;
 }
 
 hipError_t run_trsm(const rqlp_batch* b, const Launch& l, hipStream_t st) {
@@ -306,6 +333,11 @@ void free_batch(rqlp_batch* b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (int i = 0; i < rqlp_batch::kSide; ++i) {
+    if (b->side[i]) (void)hipStreamDestroy(b->side[i]);
+    if (b->join_ev[i]) (void)hipEventDestroy(b->join_ev[i]);
+  }
+  if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
   if (b->ws) (void)hipFree(b->ws);
   if (b->tab) (void)hipFree(b->tab);
   if (b->flags) (void)hipFree(b->flags);
@@ -485,6 +517,11 @@ rqlp_status randqlp_batch_create(int count, const void* const* A, const int64_t*
     }
   }
   e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  for (int i = 0; e == hipSuccess && i < rqlp_batch::kSide; ++i) {
+    e = hipStreamCreateWithFlags(&b->side[i], hipStreamNonBlocking);  // default priority
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->join_ev[i], hipEventDisableTiming);
+  }
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming);
   if (e != hipSuccess) {
     free_batch(b);
     return rqlp_fail(RQLP_E_HIP, "stream: %s", hipGetErrorString(e));
