@@ -173,6 +173,24 @@ rqlp_status randqlp_factor(const void* A, int64_t m, int64_t n, int k, int p, in
                            uint64_t seed, void* Q, void* L, void* P,
                            const rqlp_opts* opts);
 
+/* randqlp_factor without host synchronisation, so that the call can be
+ * captured into a HIP graph (or overlap host work): every step is enqueued on
+ * opts->stream and the call returns at once.  opts must be given with a
+ * workspace of randqlp_workspace_size bytes (nothing is allocated).  The
+ * panel QR is opts->panel_qr's, except that AUTO means the fast path with no
+ * automatic rerun (the rerun needs the host).  When the work completes,
+ * status (device, 4 ints) holds the call's status words: status[0] is 0 for
+ * trusted factors, else a mask of 1 (a pivot at or below the dependence
+ * tolerance: rank-deficient panel), 2 (a non-finite value met) and 4 (the
+ * second pass was not accurate enough); status[2] counts completed columns
+ * (ROBUST).  A non-zero status[0] means: call randqlp_factor, which reruns
+ * with the stronger panels and reports non-finite input.  opts->info, if
+ * given, receives d and q_used only.  Status words are cleared by a kernel
+ * (no memset node).  Returns after enqueueing. */
+rqlp_status randqlp_factor_async(const void* A, int64_t m, int64_t n, int k, int p, int q,
+                                 uint64_t seed, void* Q, void* L, void* P,
+                                 const rqlp_opts* opts, int* status);
+
 /* randqlp_factor for a sparse A (Section 5.1 factors sparse matrices), given
  * in CSR form on the device: row i's entries are colind[t], vals[t] for t
  * in [rowptr[i], rowptr[i + 1]) (rowptr: m + 1 int64, rowptr[0] = 0,

@@ -13,7 +13,7 @@ import contextlib
 import ctypes
 import os
 
-__all__ = ["factor", "factor_noalloc", "factor_csr", "factor_auto", "Batch", "factor_batched", "tune_save", "tune_load", "features", "mlp_forward", "mlp_loss_grad", "mlp_adam",
+__all__ = ["factor", "factor_async", "factor_noalloc", "factor_csr", "factor_auto", "Batch", "factor_batched", "tune_save", "tune_load", "features", "mlp_forward", "mlp_loss_grad", "mlp_adam",
            "mlp_train", "gaussian", "gemm", "orth", "sketch_width", "workspace_size",
            "colmajor", "empty_colmajor", "lib", "RandQLPError", "F64", "F32", "MIXED_BF16",
            "MIXED_F16", "MIXED_BF16X3",
@@ -32,7 +32,8 @@ STATUS = {0: "RQLP_OK", 1: "RQLP_E_INVALID_ARG", 2: "RQLP_E_NONFINITE", 3: "RQLP
 
 # Every symbol include/randqlp.h declares.
 EXPORTS = ["rqlp_opts_default", "randqlp_sketch_width", "randqlp_workspace_size",
-           "randqlp_factor", "randqlp_factor_noalloc", "randqlp_factor_csr",
+           "randqlp_factor", "randqlp_factor_async", "randqlp_factor_noalloc",
+           "randqlp_factor_csr",
            "randqlp_factor_auto", "randqlp_features", "randqlp_mlp_forward",
            "randqlp_mlp_loss_grad", "randqlp_mlp_adam", "randqlp_mlp_train",
            "randqlp_batch_create", "randqlp_batch_run", "randqlp_batch_query",
@@ -125,6 +126,9 @@ def lib():
     L.randqlp_factor_csr.argtypes = [vp, vp, vp, i64, i64, i64, i32, i32, i32, u64, vp, vp, vp,
                                      ctypes.POINTER(Opts)]
     L.randqlp_factor_csr.restype = i32
+    L.randqlp_factor_async.argtypes = [vp, i64, i64, i32, i32, i32, u64, vp, vp, vp,
+                                       ctypes.POINTER(Opts), vp]
+    L.randqlp_factor_async.restype = i32
     L.randqlp_factor_noalloc.restype = i32
     L.randqlp_factor_auto.argtypes = [vp, i64, i64, i32, i32, i32, u64, vp, vp, vp, vp,
                                       ctypes.POINTER(Opts), ctypes.POINTER(AutoInfo)]
@@ -312,6 +316,43 @@ def factor(A, k, p, q, seed, panel="auto", precision=None, return_info=False):
     if return_info:
         return Q, L, P, info.as_dict()
     return Q, L, P
+
+
+class AsyncFactor:
+    """Buffers and arguments of one asynchronous factorisation
+    (randqlp_factor_async), allocated once: Q, L, P, the workspace and the
+    device status words.  launch() only enqueues on the current stream, so
+    it can be captured into a graph (torch.cuda.graph) and replayed."""
+
+    def __init__(self, A, k, p, q, seed, panel="auto", precision=None):
+        torch = _torch()
+        self.A, self.Q, self.L, self.P, self.opts = _prepare(A, k, p, q, panel, precision)
+        m, n = self.A.shape
+        nb = lib().randqlp_workspace_size(m, n, k, p, q, ctypes.byref(self.opts))
+        self.ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=self.A.device)
+        self.opts.workspace = ctypes.c_void_p(self.ws.data_ptr())
+        self.opts.workspace_bytes = self.ws.numel()
+        self.status = torch.zeros(4, dtype=torch.int32, device=self.A.device)
+        self.args = (k, p, q, seed)
+
+    def launch(self):
+        k, p, q, seed = self.args
+        m, n = self.A.shape
+        self.opts.stream = _stream_ptr(self.A.device)
+        _check(lib().randqlp_factor_async(
+            ctypes.c_void_p(self.A.data_ptr()), m, n, k, p, q, seed,
+            ctypes.c_void_p(self.Q.data_ptr()), ctypes.c_void_p(self.L.data_ptr()),
+            ctypes.c_void_p(self.P.data_ptr()), ctypes.byref(self.opts),
+            ctypes.c_void_p(self.status.data_ptr())))
+        return self.Q, self.L, self.P, self.status
+
+
+def factor_async(A, k, p, q, seed, panel="auto", precision=None):
+    """Enqueue one factorisation without synchronising; returns (Q, L, P,
+    status) -- status (4 int32, device) is valid once the stream has reached
+    the end of the work, and status[0] != 0 means the factors are not to be
+    trusted (use factor())."""
+    return AsyncFactor(A, k, p, q, seed, panel, precision).launch()
 
 
 def factor_csr(rowptr, colind, vals, shape, k, p, q, seed, panel="auto", return_info=False):

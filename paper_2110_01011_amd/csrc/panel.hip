@@ -864,6 +864,11 @@ __global__ __launch_bounds__(256) void zero_ints_kernel(int* __restrict__ p, int
   if (idx < n) p[idx] = 0;
 }
 
+__global__ __launch_bounds__(64) void copy_ints_kernel(const int* __restrict__ src,
+                                                       int* __restrict__ dst, int n) {
+  if ((int)threadIdx.x < n) dst[threadIdx.x] = src[threadIdx.x];
+}
+
 }  // namespace
 
 hipError_t launch_cholesky_tile(const double* G, int64_t d, int64_t ldg, double shift,
@@ -1043,6 +1048,13 @@ hipError_t launch_lower_grouped(const GroupLower* descs, int count, hipStream_t 
 hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(zero_ints_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_ints(const int* src, int* dst, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  if (n > 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(copy_ints_kernel, dim3(1), dim3(64), 0, st, src, dst, n);
   return hipGetLastError();
 }
 

@@ -1242,6 +1242,32 @@ rqlp_status randqlp_factor_csr(const int64_t* rowptr, const int32_t* colind, con
   return RQLP_OK;
 }
 
+rqlp_status randqlp_factor_async(const void* A, int64_t m, int64_t n, int k, int p, int q,
+                                 uint64_t seed, void* Q, void* L, void* P,
+                                 const rqlp_opts* opts, int* status) {
+  if (!status) return fail(RQLP_E_INVALID_ARG, "null status pointer");
+  if (!opts || !opts->workspace)
+    return fail(RQLP_E_INVALID_ARG, "the asynchronous form needs opts with a workspace");
+  Ctx c;
+  FactorArgs f;
+  rqlp_opts o;
+  std::unique_lock<std::mutex> lk;
+  rqlp_status s = setup_factor(A, m, n, k, p, q, seed, Q, L, P, opts, false, c, f, o, lk);
+  if (s != RQLP_OK) return s;
+  c.noalloc = true;  // no pinned buffer, no profiling events: nothing but launches
+  // AUTO has no host to rerun from: the fast path, judged by the caller
+  hipError_t e = run_pipeline(c, f, start_mode(o));
+  if (e == hipSuccess) e = launch_copy_ints(c.flags(), status, 4, c.st);
+  if (e != hipSuccess) return fail(RQLP_E_HIP, "launch failed: %s", hipGetErrorString(e));
+  if (o.info) {
+    std::memset(o.info, 0, sizeof *o.info);
+    o.info->d = (int32_t)c.d;
+    o.info->q_used = q;
+  }
+  g_last_error.clear();
+  return RQLP_OK;
+}
+
 rqlp_status randqlp_factor_noalloc(const void* A, int64_t m, int64_t n, int k, int p, int q,
                                    uint64_t seed, void* Q, void* L, void* P,
                                    const rqlp_opts* opts) {

@@ -289,6 +289,8 @@ struct GroupLower {
 hipError_t launch_lower_grouped(const GroupLower* descs, int count, hipStream_t st);
 // Zero n ints (a kernel, so that graph capture records no memset node).
 hipError_t launch_zero_ints(int* p, int64_t n, hipStream_t st);
+// dst[0..n) = src[0..n) for n <= 64 ints (a kernel: no memcpy node in a graph).
+hipError_t launch_copy_ints(const int* src, int* dst, int n, hipStream_t st);
 
 // Gaussian sketches of a grouped launch: blocks (idx, local block).
 struct GroupGauss {

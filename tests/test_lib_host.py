@@ -203,3 +203,16 @@ def test_csr_entry_validates_on_the_host(L):
                                 dummy, ctypes.byref(o)) == 6
     assert L.randqlp_factor_csr(dummy, dummy, dummy, 1 << 21, 10, 5, 3, 1, 0, 0, dummy, dummy,
                                 dummy, None) == 6
+
+
+def test_async_entry_validates(L):
+    dummy = ctypes.c_void_p(256)
+    o = rq.default_opts()
+    # null status, no opts, no workspace
+    assert L.randqlp_factor_async(dummy, 100, 80, 5, 2, 1, 0, dummy, dummy, dummy,
+                                  ctypes.byref(o), None) == 1
+    assert L.randqlp_factor_async(dummy, 100, 80, 5, 2, 1, 0, dummy, dummy, dummy, None,
+                                  dummy) == 1
+    assert L.randqlp_factor_async(dummy, 100, 80, 5, 2, 1, 0, dummy, dummy, dummy,
+                                  ctypes.byref(o), dummy) == 1
+    assert "workspace" in L.randqlp_last_error().decode()
