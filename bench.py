@@ -652,7 +652,8 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": ("gemm16_kernel (16-bit products with A)" if fprec else
-                           f"gemm_rem_kernel ({args.precision} products with A)"),
+                           "gemm_stream_f64_kernel (f64 products with A)" if args.precision == "f64"
+                           else f"gemm_rem_kernel ({args.precision} products with A)"),
                 "avg_ms": round(avg_ms, 4),
                 "flops_per_launch": kflops / max(launches, 1),
                 "bytes_per_launch": kbytes / max(launches, 1)}

@@ -55,6 +55,45 @@ def test_gemm_f64_within_rounding_bound(rq, m, n, d, trans):
     assert np.all(np.abs(C - ref) <= bound)
 
 
+# Layouts of the fp64 products with A beyond tight, aligned operands: a
+# ragged last k-tile with 4 vector-ALU columns, two column tiles, a panel that
+# is only 8-byte aligned (the form without direct LDS loads), an A block with
+# lda > rows, and two k splits with a ragged end.
+STREAM_CASES = [
+    dict(m=4100, n=1000, d=212, trans=1),
+    dict(m=1000, n=4096, d=300, trans=0),
+    dict(m=3000, n=500, d=210, trans=1, x_offset=1),
+    dict(m=1000, n=3000, d=64, trans=0, a_rows=1200, a_offset=100),
+    dict(m=300, n=2000, d=40, trans=1),
+]
+
+
+@pytest.mark.parametrize("case", STREAM_CASES, ids=lambda c: "-".join(f"{k}{v}" for k, v in c.items()))
+def test_gemm_f64_layouts(rq, case):
+    import torch
+    m, n, d, trans = case["m"], case["n"], case["d"], case["trans"]
+    log(f"gemm f64 layout {case}")
+    r = np.random.default_rng(m + 3 * n + 7 * d)
+    a_rows, a_off = case.get("a_rows", m), case.get("a_offset", 0)
+    A_big = np.asfortranarray(r.standard_normal((a_rows, n)))
+    A = A_big[a_off:a_off + m]
+    K = m if trans else n
+    x_off = case.get("x_offset", 0)
+    X_big = r.standard_normal((K + x_off, d))
+    X = X_big[x_off:]
+    Ad = to_dev(A_big)[a_off:a_off + m]
+    Xd = to_dev(X_big)[x_off:]
+    assert Ad.stride() == (1, a_rows) and Xd.stride() == (1, K + x_off)
+    if x_off:
+        assert Xd.data_ptr() % 16 == 8
+    C = to_np(rq.gemm(Ad, Xd, trans))
+    Aop = A.T if trans else A
+    ref = Aop @ X
+    bound = 2 * K * U64 * (np.abs(Aop) @ np.abs(X)) + 1e-300
+    assert C.shape == ref.shape
+    assert np.all(np.abs(C - ref) <= bound)
+
+
 @pytest.mark.parametrize("m,n,d", [(1000, 700, 25), (333, 517, 210), (5, 7, 3)])
 @pytest.mark.parametrize("trans", [1, 0])
 def test_gemm_f32_within_rounding_bound(rq, m, n, d, trans):
