@@ -42,20 +42,21 @@ def _plain(o):
     raise TypeError(f"not JSON serialisable: {type(o).__name__}")
 
 
-# Sources of the product kernel: a traffic measurement is only reported
-# while they are unchanged since the counters were taken.
-KERNEL_SOURCES = ["paper_2110_01011_amd/csrc/gemm.hip"]
+# Sources of the product kernel per precision: a traffic measurement is
+# only reported while they are unchanged since the counters were taken.
+KERNEL_SOURCES = {"f64": ["paper_2110_01011_amd/csrc/gemm_f64.hip"],
+                  "f32": ["paper_2110_01011_amd/csrc/gemm.hip"]}
 
 
-def kernel_source_sha():
+def kernel_source_sha(precision):
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[precision]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def read_traffic(path):
+def read_traffic(path, precision):
     """HBM bytes per product launch from a counter summary (key: value lines),
     or None when it is missing or taken on other kernel sources."""
     full = os.path.join(ROOT, path)
@@ -67,7 +68,7 @@ def read_traffic(path):
             if ":" in line and not line.startswith(" "):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != kernel_source_sha():
+    if precision not in KERNEL_SOURCES or kv.get("kernel_source_sha256") != kernel_source_sha(precision):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -648,7 +649,8 @@ def main():
     peak = PEAK_TFLOPS["bf16" if fprec else args.precision]
     traffic = None
     if args.size == 8000:
-        traffic = read_traffic(f"profiles/gemm_kernel_rank200_8000_{args.precision}_traffic.txt")
+        traffic = read_traffic(f"profiles/gemm_kernel_rank200_8000_{args.precision}_traffic.txt",
+                               args.precision)
     roofline = {"bound": "mfma", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(achieved / peak, 4), "traffic": traffic,
                 "kernel": ("gemm16_kernel (16-bit products with A)" if fprec else

@@ -18,8 +18,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "librandqlp.so")
-SOURCES = ["philox.hip", "gemm.hip", "gemm16.hip", "panel.hip", "learned.hip", "batched.hip",
-           "sparse.hip", "randqlp.hip"]
+SOURCES = ["philox.hip", "gemm.hip", "gemm_f64.hip", "gemm16.hip", "panel.hip", "learned.hip",
+           "batched.hip", "sparse.hip", "randqlp.hip"]
 ARCH = os.environ.get("RANDQLP_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

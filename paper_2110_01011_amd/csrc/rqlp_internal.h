@@ -204,6 +204,16 @@ void choose_splits(int64_t tiles, int64_t K, int bk, int64_t max_s, int64_t slot
                    double tile_flops_per_k, double rate, double out_bytes, int64_t* chunk_out,
                    int* splits_out);
 constexpr int kTargetWG = 1024;
+
+// fp64 skinny products with A (gemm_f64.hip): 32-deep k-tiles, up to 13
+// MFMA column blocks (+ 2 or 4 vector-ALU columns) in one 128-row tile.
+// The panel B must be 16-byte aligned with an even ldb.
+constexpr int kStrBK = 32, kStrMaxWN = 13;
+int gemm_stream_f64_occupancy(int trans_a, int wn);
+void launch_gemm_stream_f64(int trans_a, int wn, int rv, int64_t tiles_m, int64_t tiles_n,
+                            int splits, const double* A, int64_t lda, const double* B,
+                            int64_t ldb, double* C, int64_t ldc, int64_t strideS, int64_t M,
+                            int64_t N, int64_t K, int64_t kchunk, hipStream_t st);
 // Workgroups of one kernel instantiation that fit on a CU at once (from its
 // register and LDS use; 1 when the query fails, e.g. without a device).
 template <typename F>
