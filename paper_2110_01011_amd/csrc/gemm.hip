@@ -305,8 +305,11 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const TP* __restrict
 // Small outputs with many splits (the d x d Gram matrices): four threads per
 // output element, thread q summing the splits q, q + 4, ... in order, then
 // the four quarters added in a fixed order -- deterministic, and four times
-// the loads in flight of one thread per element.  Element e = i + j M of the
-// tight M x N partials; gram_bm as in splitk_reduce_kernel.
+// the loads in flight of one thread per element; each thread issues all its
+// loads (up to 16) before adding.  Element e = i + j M of the tight M x N
+// partials.  gram_bm > 0 (a Gram matrix whose partials hold the upper tiles
+// of gram_bm x gram_bm): only elements i <= j are read, from their own
+// column (coalesced), and each is written to (i, j) and (j, i).
 template <typename TP, typename TO>
 __global__ __launch_bounds__(256) void splitk_reduce4_kernel(const TP* __restrict__ P, int64_t M,
                                                              int64_t N, int S,
@@ -316,23 +319,29 @@ __global__ __launch_bounds__(256) void splitk_reduce4_kernel(const TP* __restric
   const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int64_t total = M * N;
   const int64_t e = (int64_t)blockIdx.x * 64 + l;
-  int64_t i = 0, j = 0;
+  const int64_t i = e % M, j = e / M;
+  const bool active = e < total && (gram_bm == 0 || i <= j);
   TP s = (TP)0;
-  if (e < total) {
-    i = e % M;
-    j = e / M;
-    int64_t si = i, sj = j;
-    if (gram_bm > 0 && (i / gram_bm) > (j / gram_bm)) {
-      si = j;
-      sj = i;
+  if (active) {
+    const TP* p = P + e;
+    constexpr int U = 16;
+    TP v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int t = q + 4 * u;
+      v[u] = t < S ? p[(int64_t)t * total] : (TP)0;
     }
-    const TP* p = P + si + sj * M;
-#pragma unroll 4
-    for (int t = q; t < S; t += 4) s += p[(int64_t)t * total];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s += v[u];  // adding +0 past S leaves s unchanged
+    for (int t = q + 4 * U; t < S; t += 4) s += p[(int64_t)t * total];
   }
   part[q][l] = s;
   __syncthreads();
-  if (q == 0 && e < total) C[i + j * ldc] = (TO)((part[0][l] + part[1][l]) + (part[2][l] + part[3][l]));
+  if (q == 0 && active) {
+    const TO r = (TO)((part[0][l] + part[1][l]) + (part[2][l] + part[3][l]));
+    C[i + j * ldc] = r;
+    if (gram_bm > 0 && i < j) C[j + i * ldc] = r;
+  }
 }
 
 // The one-thread-per-element reduction is bound by the latency of its S
