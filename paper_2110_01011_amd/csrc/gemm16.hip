@@ -2,29 +2,35 @@
 // rounded to 16 bits (bf16 or fp16) and fp32 accumulation on the 16x16x32
 // MFMA, plus the conversions that produce the 16-bit operands.
 #include <algorithm>
+#include <utility>
 
 #include "rqlp_internal.h"
 
 namespace rqlp {
 namespace {
 
-// Precision form: C (fp32) = sum_k A16[k + i lda] B16[k + j ldb] with both
-// operands 16-bit (bf16 or fp16) and contiguous along the contraction, fp32
-// accumulation on the 16x16x32 MFMA.  A16 is the one-time rounded copy of A
-// (or of A^T), B16 the rounded panel (convert_panel16_kernel).  Both are
-// zero-padded along the contraction to a multiple of 64 (k16BK), so every
-// tile is whole and the main loop carries no bounds checks; rows >= M and
-// columns >= N read a clamped (valid) row or column and are never stored.
+// Precision form: C (fp32) = sum_k A16(i, k) B16[k + j ldb] with both
+// operands 16-bit (bf16 or fp16), fp32 accumulation on the 16x16x32 MFMA.
+// A16 is the one-time rounded copy of A (or of A^T) in a packed layout
+// (convert16_kernel): for each 16-row block and 64-deep k-tile one 2 KB
+// chunk, k-tiles of a block consecutive, and within a chunk element
+// (r, k) at 512 ((k % 16) / 8) + 8 (16 (k / 16) + r) + k % 8 -- exactly the
+// two 16-byte fragments lane 16 (k / 16) + r loads, so each fragment load
+// of a wave is 1 KB contiguous and a block's k-chunk streams through DRAM
+// pages in order.  B16 is the rounded panel (convert_panel16_kernel),
+// contiguous along the contraction.  Both are zero-padded along the
+// contraction to a multiple of 64 (k16BK), so every tile is whole and the
+// main loop carries no bounds checks; rows >= M and columns >= N read a
+// clamped (valid) block or padding column and are never stored.
 //
 // Workgroup tile (32 WAVES) x (16 WN): the waves are stacked along M, each
 // owning 32 rows (two 16-row blocks) and all 16 WN columns.  A rows belong to
 // a single wave, so A fragments go from HBM straight into registers (one
-// 32-byte load per lane and block covers two MFMA k-steps, prefetched one
-// tile ahead); the panel tile, shared by the waves, is staged through LDS
-// (double-buffered, 16-byte row padding so the 16 columns of a fragment read
-// fall in distinct banks).  Within a 64-deep tile, MFMA k-step s takes, for
-// lane group g = lane / 16, the tile rows 16 g + 8 s + [0, 8): the same
-// permutation of k for both operands, so the sum is unchanged.
+// 16-byte load per lane, block and MFMA k-step, two tiles ahead); the panel
+// tile, shared by the waves, is staged through LDS.  Within a 64-deep tile,
+// MFMA k-step s takes, for lane group g = lane / 16, the tile rows 16 g +
+// 8 s + [0, 8): the same permutation of k for both operands, so the sum is
+// unchanged.
 //
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2); the linear workgroup id is remapped so that each XCD works through a
@@ -68,11 +74,9 @@ __device__ __forceinline__ __bf16 to16(float x, __bf16*) {
 __device__ __forceinline__ _Float16 to16(float x, _Float16*) { return (_Float16)x; }
 
 constexpr int k16BK = 64;     // contraction depth of one tile (and the zero padding unit)
-// Waves per workgroup (32 rows each): 8 up to 14 column blocks, so that each
-// panel tile read from L2 serves 256 rows (one workgroup per CU, two waves
-// per SIMD either way); 4 for wider tiles, where 8 measured slower.
-constexpr int k16WideWN = 14;
-constexpr int waves16(int wn) { return wn <= k16WideWN ? 8 : 4; }
+// Waves per workgroup (32 rows each): 8, so that each panel tile read from
+// L2 serves 256 rows (one workgroup per CU, two waves per SIMD).
+constexpr int waves16(int) { return 8; }
 constexpr int bm16(int wn) { return 32 * waves16(wn); }
 constexpr int k16MaxWN = 17;  // up to 272 columns per workgroup
 constexpr int kXcds = 8;
@@ -85,18 +89,31 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t L, int64_t T) {
   return (x < rem) ? x * (per + 1) + j : rem * (per + 1) + (x - rem) * per + j;
 }
 
+// 16 bytes per lane from base + voffset + soffset (bytes) into LDS at lds +
+// 16 lane, by the buffer form of the direct load: base and nbytes (the
+// readable extent) are uniform.  Counted on vmcnt only.
+__device__ __forceinline__ void lds_load16(const void* base, int nbytes, int voffset, int soffset,
+                                           void* lds) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nbytes, 0x00020000),
+      (__attribute__((address_space(3))) void*)lds, 16, voffset, soffset, 0, 0);
+}
+
+// f(std::integral_constant<int, I>{}) for I in the sequence, in order.
+template <int... I, typename F>
+__device__ __forceinline__ void for_each_index(std::integer_sequence<int, I...>, F&& f) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+
 template <typename T16, int WN>
-__global__ __launch_bounds__(64 * waves16(WN), waves16(WN) == 8 ? 1 : 2) void gemm16_kernel(
-    const T16* __restrict__ A, int64_t lda, const T16* __restrict__ B, int64_t ldb,
+__global__ __launch_bounds__(64 * waves16(WN), 1) void gemm16_kernel(
+    const T16* __restrict__ A, const T16* __restrict__ B, int64_t ldb,
     float* __restrict__ C, int64_t ldc, int64_t strideS, int64_t M, int64_t N, int64_t Kp,
     int64_t kchunk, int tiles_m, int tiles_n, const T16* __restrict__ A2,
     const T16* __restrict__ B2, int seg_splits) {
-  constexpr int NT = 64 * waves16(WN);
-  constexpr int WM = 2, BK = k16BK, LK = BK + 8, CH = BK / 8;
+  constexpr int WM = 2, BK = k16BK;
   constexpr int BN = 16 * WN;
-  constexpr int CB = BN * CH, NB = (CB + NT - 1) / NT;
   typedef typename Mfma16<T16>::v8 v8;
-  __shared__ __attribute__((aligned(16))) T16 Bs[2][BN][LK];
 
   const int64_t T = (int64_t)gridDim.x;
   const int64_t w = xcd_remap(blockIdx.x, T);
@@ -115,26 +132,53 @@ __global__ __launch_bounds__(64 * waves16(WN), waves16(WN) == 8 ? 1 : 2) void ge
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int grp = lane >> 4, r16 = lane & 15;
 
-  // this lane's A rows (clamped); its 16 k of a tile start at 16 * grp
+  // this lane's fragments of the wave's two A blocks (clamped to the last
+  // block holding rows < M); tile t's are 1024 t elements further
   const T16* arow[WM];
 #pragma unroll
   for (int a = 0; a < WM; ++a) {
-    int64_t row = i0 + wave * 32 + a * 16 + r16;
-    row = row < M ? row : M - 1;
-    arow[a] = A + row * lda + 16 * grp;
+    int64_t rb = (i0 + wave * 32 + a * 16) / 16;
+    rb = rb < (M - 1) / 16 ? rb : (M - 1) / 16;
+    arow[a] = A + rb * 16 * Kp + 8 * lane;
   }
-  // this thread's panel chunks (clamped columns)
-  const T16* bsrc[NB];
-  int bdst[NB];
+  // The panel tile goes into LDS by 16-byte direct loads: block q = 2 b + s
+  // (column block b, MFMA step s) is 1 KB, where lane (g, r) of a wave finds
+  // at position 8 lane the fragment it multiplies -- tile rows 16 g + 8 s
+  // .. + 7 of column 16 b + r, 16 contiguous bytes of the column-major
+  // panel, fetched by the same lane of the loading wave.  Fragment reads
+  // are 1 KB contiguous per wave (no bank conflicts) and no staging
+  // registers or LDS stores are needed.  Every wave issues the same number
+  // of direct loads (NQW); the blocks past 2 WN land in a pad.
+  constexpr int NW = waves16(WN), NQ = 2 * WN, NQW = (NQ + NW - 1) / NW;
+  constexpr int BLK = 512;  // 16-bit elements per 1 KB block
+  __shared__ __attribute__((aligned(16))) T16 Bs0[NQW * NW * BLK];
+  __shared__ __attribute__((aligned(16))) T16 Bs1[NQW * NW * BLK];
+  __shared__ __attribute__((aligned(16))) T16 Bs2[NQW * NW * BLK];
+  // Wave w loads blocks q = w + NW u: column block q / 2 = NW u / 2 + w / 2,
+  // step q % 2 = w % 2 (NW is even).  Each block has a buffer resource whose
+  // base is that wave-uniform part of the address; the lane adds its column
+  // r and row group g (voffset), the tile its k0 (soffset).  The buffer
+  // form of the direct load is counted on vmcnt alone, so the fragment
+  // reads below wait for their own LDS reads only (the global form, being
+  // FLAT-encoded, is also counted on lgkmcnt and makes the compiler wait
+  // for every outstanding LDS read before each fragment is used).
+  // Offsets are 32-bit: the launcher bounds ldb.  Columns past N (the
+  // ragged last tile and the pad blocks) are read from the panel's slack
+  // columns (kGemm16PanelSlack) and never stored.
+  static_assert(NW % 2 == 0, "waves per workgroup must be even");
+  static_assert(16 * (NQW * NW / 2) <= 16 * WN + kGemm16PanelSlack, "panel slack too small");
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const T16* qbase[NQW];
+  int qbytes[NQW];
 #pragma unroll
-  for (int e = 0; e < NB; ++e) {
-    const int ch = tid + e * NT;
-    const int col = (ch < CB ? ch : CB - 1) / CH, kc = (ch % CH) * 8;
-    int64_t gj = j0 + col;
-    gj = gj < N ? gj : N - 1;
-    bsrc[e] = B + gj * ldb + kc;
-    bdst[e] = col * LK + kc;
+  for (int u = 0; u < NQW; ++u) {
+    const int64_t col = j0 + 16 * (NW / 2 * u + (wv >> 1));
+    qbase[u] = B + col * ldb + 8 * (wv & 1);
+    // bytes of the panel (N + kGemm16PanelSlack columns) from the base on
+    qbytes[u] = (int)std::min<int64_t>(((N + kGemm16PanelSlack - col) * ldb - 8 * (wv & 1)) * 2,
+                                       0x7fffffff);
   }
+  const int voff = (int)((r16 * ldb + 16 * grp) * 2);
 
   float4_t acc[WM][WN];
 #pragma unroll
@@ -142,70 +186,133 @@ __global__ __launch_bounds__(64 * waves16(WN), waves16(WN) == 8 ? 1 : 2) void ge
 #pragma unroll
     for (int b = 0; b < WN; ++b) acc[a][b] = float4_t{0, 0, 0, 0};
 
-  v8 acur[WM][2], anext[WM][2], rb[NB];
-  auto loadA = [&](v8 (&dst)[WM][2], int64_t k0) {
+  // Three tiles in flight: A fragments in a ring of registers, panel tiles
+  // in a ring of LDS buffers; tile t + 2 loads while tile t is multiplied.
+  v8 ra0[WM][2], ra1[WM][2], ra2[WM][2];
+  auto load = [&](int64_t t, v8 (&dst)[WM][2], T16* bs) {
+    const int64_t k0 = kbeg + t * BK;
+#pragma unroll
+    for (int u = 0; u < NQW; ++u)
+      lds_load16(qbase[u], qbytes[u], voff, (int)(k0 * 2), bs + (u * NW + wave) * BLK);
 #pragma unroll
     for (int a = 0; a < WM; ++a) {
-      dst[a][0] = *(const v8*)(arow[a] + k0);
-      dst[a][1] = *(const v8*)(arow[a] + k0 + 8);
+      dst[a][0] = *(const v8*)(arow[a] + 16 * k0);
+      dst[a][1] = *(const v8*)(arow[a] + 16 * k0 + 512);
     }
   };
-  auto loadB = [&](int64_t k0) {
-#pragma unroll
-    for (int e = 0; e < NB; ++e)
-      if (NB * NT == CB || tid + e * NT < CB) rb[e] = *(const v8*)(bsrc[e] + k0);
+  // 2 WN fragment reads per tile, each feeding WM MFMAs, in groups of G:
+  // the reads of group g + 1 are issued before the MFMAs of group g (two
+  // register sets, a scheduling fence between groups), so LDS latency
+  // overlaps the MFMAs; read one at a time before its MFMAs, each fragment
+  // was waited on and the matrix cores idled.
+  constexpr int G = 4, NF = 2 * WN, NG = (NF + G - 1) / G;
+  auto frag = [&](const T16* bs, int i) {
+    const int b = i % WN, sb = i / WN;
+    return *(const v8*)(bs + (2 * b + sb) * BLK + 8 * lane);
   };
-  auto storeB = [&](int buf) {
+  auto compute = [&](const v8 (&ra)[WM][2], const T16* bs) {
+    v8 bf[2][G];
 #pragma unroll
-    for (int e = 0; e < NB; ++e)
-      if (NB * NT == CB || tid + e * NT < CB) *(v8*)(&Bs[buf][0][0] + bdst[e]) = rb[e];
+    for (int u = 0; u < G; ++u)
+      if (u < NF) bf[0][u] = frag(bs, u);
+    auto group = [&](auto gic) {
+      constexpr int gi = decltype(gic)::value;
+      constexpr int nr = std::min(G, std::max(0, NF - (gi + 1) * G));  // reads of group gi + 1
+      constexpr int nm = WM * std::min(G, NF - gi * G);                // MFMAs of group gi
+#pragma unroll
+      for (int u = 0; u < nr; ++u) bf[(gi + 1) & 1][u] = frag(bs, (gi + 1) * G + u);
+#pragma unroll
+      for (int u = 0; u < nm / WM; ++u) {
+        const int i = gi * G + u;
+        const int b = i % WN, sb = i / WN;
+#pragma unroll
+        for (int a = 0; a < WM; ++a)
+          acc[a][b] = Mfma16<T16>::mma(ra[a][sb], bf[gi & 1][u], acc[a][b]);
+      }
+      // this group's fragments stay live to the end of the group, so the
+      // next group's reads cannot take their registers (and wait for them)
+#pragma unroll
+      for (int u = 0; u < nm / WM; ++u) asm volatile("" ::"v"(bf[gi & 1][u]));
+      if constexpr (nr > 0) __builtin_amdgcn_sched_group_barrier(0x100, nr, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, nm, 0);
+      __builtin_amdgcn_sched_barrier(0);
+    };
+    __builtin_amdgcn_sched_barrier(0);
+    for_each_index(std::make_integer_sequence<int, NG>{}, group);
+  };
+  // The loads of one tile per wave: NQW direct loads + 2 WM fragment loads.
+  // Waiting until at most that many are outstanding completes the tile
+  // before them (loads return in order), and the barrier then hands it to
+  // all waves.  __syncthreads() would wait for every load (its fence
+  // implies vmcnt(0)), tile t + 2's included.  The wait is the builtin, so
+  // the compiler knows which loads it covers (no conservative wait before
+  // the next tile's LDS reads); the empty asm statements with a memory
+  // clobber keep memory accesses from moving across the barrier.  The
+  // buffer a tile's direct loads overwrite was read for tile t - 1, before
+  // the previous barrier.
+  constexpr int L = NQW + 2 * WM;
+  static_assert(L < 64, "vmcnt range");
+  constexpr int wait_imm = (L & 15) | ((L >> 4) << 14) | (7 << 4) | (15 << 8);
+  auto sync_tile = [&]() {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(wait_imm);
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_sched_barrier(0);
   };
 
   const int64_t nk = (kend - kbeg) / BK;  // whole tiles (kbeg, kend multiples of BK)
   if (nk > 0) {
-    loadA(acur, kbeg);
-    loadB(kbeg);
-    storeB(0);
-    __syncthreads();
-    for (int64_t it = 0; it < nk; ++it) {
-      const int buf = (int)(it & 1);
-      const bool more = it + 1 < nk;
-      if (more) {
-        const int64_t k1 = kbeg + (it + 1) * BK;
-        loadB(k1);
-        loadA(anext, k1);
-      }
-#pragma unroll
-      for (int s = 0; s < 2; ++s)
-#pragma unroll
-        for (int b = 0; b < WN; ++b) {
-          const v8 bf = *(const v8*)&Bs[buf][b * 16 + r16][16 * grp + 8 * s];
-#pragma unroll
-          for (int a = 0; a < WM; ++a) acc[a][b] = Mfma16<T16>::mma(acur[a][s], bf, acc[a][b]);
-        }
-      if (more) {
-        storeB(buf ^ 1);
-#pragma unroll
-        for (int a = 0; a < WM; ++a) {
-          acur[a][0] = anext[a][0];
-          acur[a][1] = anext[a][1];
-        }
-      }
+    // loads past the last tile re-read it (unused), so every step issues
+    // the same loads
+    auto tc = [&](int64_t t) { return t < nk ? t : nk - 1; };
+    load(0, ra0, Bs0);
+    load(tc(1), ra1, Bs1);
+    sync_tile();
+    int64_t t = 0;
+    for (; t + 2 < nk; t += 3) {
+      load(tc(t + 2), ra2, Bs2);
+      compute(ra0, Bs0);
+      sync_tile();
+      load(tc(t + 3), ra0, Bs0);
+      compute(ra1, Bs1);
+      sync_tile();
+      load(tc(t + 4), ra1, Bs1);
+      compute(ra2, Bs2);
+      sync_tile();
+    }
+    // 1 or 2 tiles left: the last one's loads may still be in flight (the
+    // waits above leave one tile outstanding), so wait for all of them and
+    // hand both tiles to every wave
+    if (t < nk) {
       __syncthreads();
+      compute(ra0, Bs0);
+      if (t + 1 < nk) compute(ra1, Bs1);
     }
   }
+  // Lane (g, r) holds rows 4 g .. 4 g + 3 of column r of each block: one
+  // 16-byte store where C's address and ldc allow it and the four rows
+  // exist; the two blocks of a column are stored back to back (one 128-byte
+  // line when aligned).
   float* Cs = C + (int64_t)split * strideS;
+  const bool vec = ((((uintptr_t)Cs) & 15) == 0) && ((ldc & 3) == 0);
 #pragma unroll
-  for (int a = 0; a < WM; ++a)
+  for (int b = 0; b < WN; ++b) {
+    const int64_t col = j0 + b * 16 + r16;
 #pragma unroll
-    for (int b = 0; b < WN; ++b) {
-      const int64_t col = j0 + b * 16 + r16;
+    for (int a = 0; a < WM; ++a) {
+      const int64_t row0 = i0 + wave * 32 + a * 16 + acc_row_f32(lane, 0);
+      if (col >= N) continue;
+      if (vec && row0 + 3 < M) {
+        *(float4_t*)(Cs + row0 + col * ldc) = acc[a][b];
+      } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = i0 + wave * 32 + a * 16 + acc_row_f32(lane, r);
-        if (row < M && col < N) Cs[row + col * ldc] = acc[a][b][r];
+        for (int r = 0; r < 4; ++r)
+          if (row0 + r < M) Cs[row0 + r + col * ldc] = acc[a][b][r];
       }
     }
+  }
 }
 
 // X (rows x d fp32, ldx) -> X16 (rows x d, ldy), rounded to nearest even;
@@ -228,14 +335,15 @@ __global__ __launch_bounds__(256) void convert_panel16_kernel(const float* __res
   }
 }
 
-// A (m x n fp32, lda) -> A16 (m x n, ld16) and At16 = A^T (n x m, ldt16), both
-// rounded to 16 bits (nearest even).  ld16 and ldt16 are m and n rounded up
-// to multiples of 64; the padding rows of both copies are written as zeros
-// (the contraction padding of gemm16_kernel).  64 x 64 tiles through LDS keep
-// the transposed writes coalesced; the grid covers exactly the padded sizes.
-// Each thread takes two adjacent elements, so every 16-bit store is a 4-byte
-// pair (the even leading dimensions keep pairs aligned), and the fp32 loads
-// are 8-byte pairs when A's address and lda allow.
+// A (m x n fp32, lda) -> A16 and At16, A and A^T rounded to 16 bits (nearest
+// even) in the packed operand layout of gemm16_kernel: A16's rows are A's n
+// columns with contraction k = A's row (length k16 = m rounded up to 64),
+// At16's rows are A's m rows with k = A's column (kt16 = n rounded up).
+// Each copy covers its rows rounded up to 64; padding rows and padding k
+// are zeros.  One workgroup takes a 64 x 64 tile of A: read once (8-byte
+// pairs when A's address and lda allow, each thread a 2 x 2 block), rounded
+// into LDS in both orientations, then stored as four whole 2 KB chunks of
+// each copy.
 // If rerr is given, each workgroup also writes the sum of squared rounding
 // errors (a - a16)^2 of its tile (fp64) to rerr[its linear index] and the
 // tile's sum of squares a^2 to rerr[nblocks + its linear index].  A16lo /
@@ -292,16 +400,23 @@ __global__ __launch_bounds__(256) void unscale_kernel(float* __restrict__ C, int
 template <typename T16>
 __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict__ A, int64_t m,
                                                         int64_t n, int64_t lda,
-                                                        T16* __restrict__ A16, int64_t ld16,
-                                                        T16* __restrict__ At16, int64_t ldt16,
+                                                        T16* __restrict__ A16, int64_t k16,
+                                                        T16* __restrict__ At16, int64_t kt16,
                                                         double* __restrict__ rerr,
                                                         T16* __restrict__ A16lo,
                                                         T16* __restrict__ At16lo,
                                                         const unsigned* __restrict__ amax_bits,
                                                         int* __restrict__ scale_out) {
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
   typedef T16 pair_t __attribute__((ext_vector_type(2)));
-  __shared__ T16 tile[64][66];
-  __shared__ T16 tlo[64][66];
+  // The rounded tile twice, [j][i] for A16 and [i][j] for At16, in 4-byte
+  // pairs; the residuals go through the same arrays in a second round (the
+  // LDS footprint allows eight workgroups per CU).  Rows are 35 words
+  // apart: thread tx's pair writes to rows 2 tx (+1) of the [i][j] copy
+  // then fall in distinct banks (35 is odd).
+  constexpr int LD = 70;
+  __shared__ __attribute__((aligned(16))) T16 tj[64][LD];
+  __shared__ __attribute__((aligned(16))) T16 ti[64][LD];
   __shared__ double red[256];
   const int64_t i0 = (int64_t)blockIdx.x * 64, j0 = (int64_t)blockIdx.y * 64;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
@@ -311,47 +426,77 @@ __global__ __launch_bounds__(256) void convert16_kernel(const float* __restrict_
   const float sc = ldexpf(1.0f, sexp), inv = ldexpf(1.0f, -sexp);
   if (scale_out && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *scale_out = sexp;
   double err = 0.0, nrm = 0.0;
-  for (int jj = ty; jj < 64; jj += 8) {
-    const int64_t i = i0 + 2 * tx, j = j0 + jj;
-    float a[2] = {0.0f, 0.0f};
-    if (j < n) {
-      const float* src = A + i + j * lda;
-      if (pairs && i + 1 < m) {
-        const float2 t = *(const float2*)src;
-        a[0] = t.x;
-        a[1] = t.y;
-      } else {
-        if (i < m) a[0] = src[0];
-        if (i + 1 < m) a[1] = src[1];
+  // thread (tx, ty): rows 2 tx, 2 tx + 1 and column pairs ty + 8 r of the
+  // tile, r = 0..3; v / vl [r][column][row]
+  T16 v[4][2][2], vl[4][2][2];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int jp = ty + 8 * r;
+    const int64_t i = i0 + 2 * tx;
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int64_t j = j0 + 2 * jp + c;
+      float a[2] = {0.0f, 0.0f};
+      if (j < n) {
+        const float* src = A + i + j * lda;
+        if (pairs && i + 1 < m) {
+          const float2 t = *(const float2*)src;
+          a[0] = t.x;
+          a[1] = t.y;
+        } else {
+          if (i < m) a[0] = src[0];
+          if (i + 1 < m) a[1] = src[1];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const float as = a[u] * sc;
+        v[r][c][u] = to16(as, (T16*)nullptr);
+        vl[r][c][u] = to16(as - (float)v[r][c][u], (T16*)nullptr);
+        const double e = (double)a[u] - (double)((float)v[r][c][u] * inv);
+        err += e * e;
+        nrm += (double)a[u] * (double)a[u];
       }
     }
-    T16 v[2], vl[2];
-#pragma unroll
-    for (int u = 0; u < 2; ++u) {
-      const float as = a[u] * sc;
-      v[u] = to16(as, (T16*)nullptr);
-      vl[u] = to16(as - (float)v[u], (T16*)nullptr);
-      const double e = (double)a[u] - (double)((float)v[u] * inv);
-      err += e * e;
-      nrm += (double)a[u] * (double)a[u];
-    }
-    if (j < n) {  // i + 1 < ld16 always
-      *(pair_t*)(A16 + i + j * ld16) = pair_t{v[0], v[1]};
-      if (A16lo) *(pair_t*)(A16lo + i + j * ld16) = pair_t{vl[0], vl[1]};
-    }
-    tile[jj][2 * tx] = v[0];
-    tile[jj][2 * tx + 1] = v[1];
-    tlo[jj][2 * tx] = vl[0];
-    tlo[jj][2 * tx + 1] = vl[1];
   }
-  __syncthreads();
-  for (int ii = ty; ii < 64; ii += 8) {
-    const int64_t j = j0 + 2 * tx, i = i0 + ii;
-    if (i < m) {  // j + 1 < ldt16 always
-      *(pair_t*)(At16 + j + i * ldt16) = pair_t{tile[2 * tx][ii], tile[2 * tx + 1][ii]};
-      if (At16lo)
-        *(pair_t*)(At16lo + j + i * ldt16) = pair_t{tlo[2 * tx][ii], tlo[2 * tx + 1][ii]};
+  auto stage = [&](const T16 (&x)[4][2][2]) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int jp = ty + 8 * r;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) *(pair_t*)&tj[2 * jp + c][2 * tx] = pair_t{x[r][c][0], x[r][c][1]};
+#pragma unroll
+      for (int u = 0; u < 2; ++u) *(pair_t*)&ti[2 * tx + u][2 * jp] = pair_t{x[r][0][u], x[r][1][u]};
     }
+  };
+  // Packed stores: the 64 x 64 tile is, in both copies, one 64-deep k-tile
+  // of four 16-row blocks, i.e. four whole 2 KB chunks; unit u = (block,
+  // half, lane) is 16 bytes, 8 consecutive k of one row (four LDS words).
+  // A16's rows are A's columns (k = i), At16's are A's rows (k = j).
+  // Elements outside A are zeros in the tiles.
+  const int64_t nk = k16 / k16BK, nkt = kt16 / k16BK;
+  auto row8 = [](const T16* p) {
+    const unsigned* w = (const unsigned*)p;
+    return u32x4{w[0], w[1], w[2], w[3]};
+  };
+  auto store = [&](T16* Y, T16* Yt) {
+    for (int u = threadIdx.x; u < 512; u += 256) {
+      const int blk = u >> 7, h = (u >> 6) & 1, ln = u & 63;
+      const int rr = 16 * blk + (ln & 15), kk = 16 * (ln >> 4) + 8 * h;
+      const int64_t oa = (((j0 / 16 + blk) * nk + i0 / k16BK) * 2 + h) * 512 + 8 * ln;
+      const int64_t ot = (((i0 / 16 + blk) * nkt + j0 / k16BK) * 2 + h) * 512 + 8 * ln;
+      if (Y) *(u32x4*)(Y + oa) = row8(&tj[rr][kk]);
+      if (Yt) *(u32x4*)(Yt + ot) = row8(&ti[rr][kk]);
+    }
+  };
+  stage(v);
+  __syncthreads();
+  store(A16, At16);
+  if (A16lo || At16lo) {
+    __syncthreads();
+    stage(vl);
+    __syncthreads();
+    store(A16lo, At16lo);
   }
   if (rerr) {
     const int64_t nb = (int64_t)gridDim.x * gridDim.y;
@@ -420,7 +565,7 @@ static void run_gemm16(const Gemm16Args& g, const Plan16& p, int nseg, float* ds
                        int64_t lddst, int64_t strideS, hipStream_t st) {
   const unsigned T = (unsigned)(p.tiles_m * p.tiles_n * p.splits * nseg);
   hipLaunchKernelGGL((gemm16_kernel<T16, WN>), dim3(T), dim3(64 * waves16(WN)), 0, st,
-                     (const T16*)g.A, g.lda, (const T16*)g.B, g.ldb, dst, lddst, strideS, g.M,
+                     (const T16*)g.A, (const T16*)g.B, g.ldb, dst, lddst, strideS, g.M,
                      g.N, pad16(g.K), p.kchunk, (int)p.tiles_m, (int)p.tiles_n,
                      (const T16*)g.A2, (const T16*)g.B2, p.splits);
 }
@@ -446,9 +591,12 @@ static hipError_t gemm16_typed(const Gemm16Args& g, hipStream_t st) {
   if (!direct && (g.partial == nullptr ||
                   g.partial_bytes < (size_t)slabs * (size_t)strideS * sizeof(float)))
     return hipErrorInvalidValue;
-  // whole 16-byte fragment loads over the zero-padded contraction; the
-  // residual copies share the leading dimensions of A and B
-  if (g.lda < pad16(g.K) || g.ldb < pad16(g.K) || (g.lda % 8) != 0 || (g.ldb % 8) != 0 ||
+  // whole 16-byte fragment loads over the zero-padded contraction (A packed
+  // with its contraction padded to the tile depth); the residual copies
+  // share the layouts of A and B; the panel's
+  // buffer offsets (about 32 ldb bytes at most) fit in 31 bits
+  if (g.lda != pad16(g.K) || g.ldb < pad16(g.K) || (g.ldb % 8) != 0 ||
+      g.ldb >= ((int64_t)1 << 26) ||
       (((uintptr_t)g.A | (uintptr_t)g.B | (uintptr_t)g.A2 | (uintptr_t)g.B2) & 15) != 0 ||
       ((g.A2 == nullptr) != (g.B2 == nullptr)) || (g.A2 && g.f16))
     return hipErrorInvalidValue;
@@ -472,6 +620,10 @@ size_t gemm16_partial_bytes(int64_t M, int64_t N, int64_t K, bool f16, int nseg)
 }
 
 int64_t gemm16_ld(int64_t K) { return pad16(K); }
+
+size_t gemm16_packed_bytes(int64_t rows, int64_t K) {
+  return (size_t)((rows + k16BK - 1) / k16BK * k16BK) * (size_t)pad16(K) * 2;
+}
 
 hipError_t launch_convert_panel16(const float* X, int64_t rows, int64_t d, int64_t ldx, void* Y,
                                   int64_t ldy, bool f16, hipStream_t st, void* Ylo) {
@@ -505,9 +657,10 @@ hipError_t launch_convert16(const float* A, int64_t m, int64_t n, int64_t lda, v
     amax = nullptr;
     scale_out = nullptr;
   }
-  // pair stores: even leading dimensions and 4-byte aligned copies
-  if (ld16 < pad16(m) || ldt16 < pad16(n) || (ld16 & 1) || (ldt16 & 1) ||
-      (((uintptr_t)A16 | (uintptr_t)At16 | (uintptr_t)A16lo | (uintptr_t)At16lo) & 3))
+  // packed copies: contraction lengths padded to the tile depth, 16-byte
+  // aligned chunks
+  if (ld16 != pad16(m) || ldt16 != pad16(n) ||
+      (((uintptr_t)A16 | (uintptr_t)At16 | (uintptr_t)A16lo | (uintptr_t)At16lo) & 15))
     return hipErrorInvalidValue;
   dim3 grid((unsigned)((m + 63) / 64), (unsigned)((n + 63) / 64));
   if (f16)

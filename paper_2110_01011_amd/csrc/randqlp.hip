@@ -170,18 +170,18 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
   if (mixed) {
     L.ld16 = gemm16_ld(m);
     L.ldt16 = gemm16_ld(n);
-    L.a16 = take((size_t)L.ld16 * n * 2);
-    L.at16 = take((size_t)L.ldt16 * m * 2);
+    L.a16 = take(gemm16_packed_bytes(n, m));
+    L.at16 = take(gemm16_packed_bytes(m, n));
     L.ldp16 = gemm16_ld(std::max(m, n));
-    L.p16 = take((size_t)L.ldp16 * d * 2);
+    L.p16 = take((size_t)L.ldp16 * (d + kGemm16PanelSlack) * 2);
     L.amax = take(16);  // max |a| of the fp16 form's scale
   } else {
     L.ld16 = L.ldt16 = L.ldp16 = 0;
     L.a16 = L.at16 = L.p16 = L.amax = 0;
   }
   if (mixed && split) {
-    L.a16lo = take((size_t)L.ld16 * n * 2);
-    L.p16lo = take((size_t)L.ldp16 * d * 2);
+    L.a16lo = take(gemm16_packed_bytes(n, m));
+    L.p16lo = take((size_t)L.ldp16 * (d + kGemm16PanelSlack) * 2);
   } else {
     L.a16lo = L.p16lo = 0;
   }
@@ -1613,20 +1613,21 @@ rqlp_status randqlp_gemm(int trans_a, const void* A, int64_t m, int64_t n, int64
   char* ws = nullptr;
   hipError_t e = hipSuccess;
   if (precision >= RQLP_MIXED_BF16) {
-    // 16-bit copies of op(A) (contraction-contiguous) and of X, then the
-    // precision-form product kernel.
+    // 16-bit copies of op(A) (packed) and of X (contraction-contiguous),
+    // then the precision-form product kernel.
     // RQLP_MIXED_BF16X3: the split product, with the residual copies of
     // op(A) and X after the rounded ones.
     const bool f16 = precision == RQLP_MIXED_F16;
     const bool split = precision == RQLP_MIXED_BF16X3;
     const int64_t ld16 = gemm16_ld(m), ldt16 = gemm16_ld(n), ldx16 = gemm16_ld(K);
     const size_t part = gemm16_partial_bytes(rows, d, K, f16, split ? 3 : 1);
-    const size_t bytes_op = trans_a ? (size_t)ld16 * n * 2 : (size_t)ldt16 * m * 2;
-    const size_t off_a = 0, off_at = align_up((size_t)ld16 * n * 2);
-    const size_t off_x = off_at + align_up((size_t)ldt16 * m * 2);
-    const size_t off_alo = off_x + align_up((size_t)ldx16 * d * 2);
+    const size_t bytes_op = trans_a ? gemm16_packed_bytes(n, m) : gemm16_packed_bytes(m, n);
+    const size_t off_a = 0, off_at = align_up(gemm16_packed_bytes(n, m));
+    const size_t off_x = off_at + align_up(gemm16_packed_bytes(m, n));
+    const size_t xbytes = (size_t)ldx16 * (d + kGemm16PanelSlack) * 2;
+    const size_t off_alo = off_x + align_up(xbytes);
     const size_t off_xlo = off_alo + (split ? align_up(bytes_op) : 0);
-    const size_t off_p = off_xlo + (split ? align_up((size_t)ldx16 * d * 2) : 0);
+    const size_t off_p = off_xlo + (split ? align_up(xbytes) : 0);
     const size_t off_s = off_p + align_up(std::max<size_t>(part, 256));  // fp16 scale words
     rqlp_status s = acquire_ws(o, off_s + 256, &ws, lk);
     if (s != RQLP_OK) return s;

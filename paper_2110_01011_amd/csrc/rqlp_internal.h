@@ -71,15 +71,17 @@ hipError_t launch_gemm(const GemmArgs& g, hipStream_t st);
 size_t gemm_partial_bytes(int trans_a, int64_t M, int64_t N, int64_t K, Dtype in_t,
                           Dtype out_t, bool gram);
 
-// Precision form: C (M x N fp32) = A16^T X, A16 a 16-bit matrix with the
-// contraction index contiguous (A16[k + i*lda]), X fp32 (X[k + j*ldb]) rounded
-// to 16 bits on load; split-K partials in `partial` (fixed-order reduction).
-// With A2 and B2 (bf16 only): the rounding residuals of A and X in the layouts
-// of A and B, and C = A16^T B16 + A16^T B2 + A2^T B16 (split bf16 product).
+// Precision form: C (M x N fp32) = A16 B16, A16 (M x K) a 16-bit copy in the
+// packed layout launch_convert16 writes (lda = gemm16_ld(K)), B16 (K x N) a
+// 16-bit panel with the contraction index contiguous (B16[k + j*ldb]);
+// split-K partials in `partial` (fixed-order reduction).  With A2 and B2
+// (bf16 only): the rounding residuals of A and B in the layouts of A and B,
+// and C = A16 B16 + A16 B2 + A2 B16 (split bf16 product).
 struct Gemm16Args {
   bool f16;  // false: bf16, true: fp16
-  const void* A; int64_t lda;  // 16-bit, contraction-contiguous, lda % 8 == 0
-  const void* B; int64_t ldb;  // 16-bit panel, contraction-contiguous, ldb % 8 == 0
+  const void* A; int64_t lda;  // 16-bit, packed, lda == gemm16_ld(K), 16-byte aligned
+  const void* B; int64_t ldb;  // 16-bit panel, contraction-contiguous, ldb % 8 == 0,
+                               // kGemm16PanelSlack readable columns past N
   float* C; int64_t ldc;
   const void* A2 = nullptr;  // residual of A (lda), or null
   const void* B2 = nullptr;  // residual of the panel (ldb), or null
@@ -90,17 +92,25 @@ struct Gemm16Args {
   void* ev_end = nullptr;
 };
 hipError_t launch_gemm16(const Gemm16Args& g, hipStream_t st);
+// Columns past N of the panel (and of its residual) that the 16-bit product
+// kernel reads without bounds checks; their values never reach C.
+constexpr int64_t kGemm16PanelSlack = 320;
 size_t gemm16_partial_bytes(int64_t M, int64_t N, int64_t K, bool f16, int nseg = 1);
 // Leading dimension of a 16-bit operand with contraction length K: K rounded
 // up to the kernel's tile depth; the padding must hold zeros.
 int64_t gemm16_ld(int64_t K);
+// Bytes of a packed 16-bit operand with `rows` rows and contraction K (rows
+// rounded up to 64, K to gemm16_ld(K)).
+size_t gemm16_packed_bytes(int64_t rows, int64_t K);
 // X (rows x d fp32, ldx) -> Y (rows x d, 16-bit, ldy), nearest even; ldy a
 // multiple of the tile depth >= gemm16_ld(rows); rows [rows, ldy) zeroed.
 // Ylo (optional, same layout): the rounded residual x - y.
 hipError_t launch_convert_panel16(const float* X, int64_t rows, int64_t d, int64_t ldx, void* Y,
                                   int64_t ldy, bool f16, hipStream_t st, void* Ylo = nullptr);
-// A (m x n fp32) -> A16 (m x n, ld16) and At16 = A^T (n x m, ldt16), 16-bit,
-// with ld16 >= gemm16_ld(m), ldt16 >= gemm16_ld(n) and zero padding rows.
+// A (m x n fp32) -> packed 16-bit copies A16 (rows: A's n columns,
+// contraction m, ld16 = gemm16_ld(m), gemm16_packed_bytes(n, m) bytes) and
+// At16 (rows: A's m rows, contraction n, ldt16 = gemm16_ld(n),
+// gemm16_packed_bytes(m, n) bytes), 16-byte aligned, zero padding.
 // rerr (optional): per-workgroup sums of the squared rounding errors, one
 // double for each of the nb = convert16_blocks(m, n) workgroups, followed by
 // the nb per-workgroup sums of squares of A (2 nb doubles in all).  A16lo /
