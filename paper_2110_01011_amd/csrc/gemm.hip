@@ -546,7 +546,7 @@ hipError_t gemm_typed(const GemmArgs& g, hipStream_t st) {
     hipLaunchKernelGGL((gemm_kernel<TI, TC, TO, true, kWavesM, kWavesN, kGramWM, 1, kBK>), grid,
                        dim3(64 * kWavesM * kWavesN), 0, st, (const TI*)g.A, g.lda,
                        (const TI*)g.B, g.ldb, dst, lddst, strideS, g.M, g.N, g.K, p.kchunk, 1);
-  } else if (p.stream && (g.ldb % 2) == 0 && ((uintptr_t)g.B % 16) == 0) {
+  } else if (p.stream && (g.ldb % 2) == 0 && g.ldb < (1 << 20) && ((uintptr_t)g.B % 16) == 0) {
     if constexpr (std::is_same<TI, double>::value && std::is_same<TO, double>::value)
       launch_gemm_stream_f64(g.trans_a, p.wn, p.rv, p.tiles_m, p.tiles_n, p.splits,
                              (const double*)g.A, g.lda, (const double*)g.B, g.ldb, dst, lddst,

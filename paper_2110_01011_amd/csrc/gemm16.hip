@@ -89,16 +89,6 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t L, int64_t T) {
   return (x < rem) ? x * (per + 1) + j : rem * (per + 1) + (x - rem) * per + j;
 }
 
-// 16 bytes per lane from base + voffset + soffset (bytes) into LDS at lds +
-// 16 lane, by the buffer form of the direct load: base and nbytes (the
-// readable extent) are uniform.  Counted on vmcnt only.
-__device__ __forceinline__ void lds_load16(const void* base, int nbytes, int voffset, int soffset,
-                                           void* lds) {
-  __builtin_amdgcn_raw_ptr_buffer_load_lds(
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nbytes, 0x00020000),
-      (__attribute__((address_space(3))) void*)lds, 16, voffset, soffset, 0, 0);
-}
-
 // f(std::integral_constant<int, I>{}) for I in the sequence, in order.
 template <int... I, typename F>
 __device__ __forceinline__ void for_each_index(std::integer_sequence<int, I...>, F&& f) {
@@ -193,7 +183,7 @@ __global__ __launch_bounds__(64 * waves16(WN), 1) void gemm16_kernel(
     const int64_t k0 = kbeg + t * BK;
 #pragma unroll
     for (int u = 0; u < NQW; ++u)
-      lds_load16(qbase[u], qbytes[u], voff, (int)(k0 * 2), bs + (u * NW + wave) * BLK);
+      buffer_load_lds16(qbase[u], qbytes[u], voff, (int)(k0 * 2), bs + (u * NW + wave) * BLK);
 #pragma unroll
     for (int a = 0; a < WM; ++a) {
       dst[a][0] = *(const v8*)(arow[a] + 16 * k0);

@@ -29,10 +29,10 @@ namespace {
 // (no bank conflicts).  The vector-ALU columns take one more 128-double
 // block (pair p of column c at 8 p + 2 c + e); RV of its 4 columns are
 // computed (2 when the tile is at most 16 WN + 2 wide, e.g. d = 210).
-// Direct loads need B 16-byte aligned with an even ldb (the launcher
-// checks); a k-tile that ends past the split (the last one when K is not a
-// multiple of 32) is staged through registers instead, with zeros past the
-// end.  Rows past M and columns past N read clamped in-bounds data whose
+// Direct loads need B 16-byte aligned with an even ldb below 2^20 (the
+// launcher checks; buffer offsets are 32-bit); a k-tile that ends past the
+// split (the last one when K is not a multiple of 32) is staged through
+// registers instead, with zeros past the end.  Rows past M and columns past N read clamped in-bounds data whose
 // results are never stored.
 constexpr int kStrWaves = 8;
 template <int WN>
@@ -82,13 +82,19 @@ __global__ __launch_bounds__(64 * kStrWaves) void gemm_stream_f64_kernel(
   };
   const int64_t arow = (i0 + wave * 16 + r16 < M) ? i0 + wave * 16 + r16 : M - 1;
   const double* const pa = TA ? A + arow * lda + 2 * g : A + arow + 2 * g * lda;
-  // block q = wave + 8 i of the wave: column 16 (wave / 4) + 32 i + r of the
-  // tile, k offset 8 (wave % 4) + 2 g
-  const double* const pb = B + (j0 + 16 * (wave >> 2) + r16) * ldb + 8 * (wave & 3) + 2 * g;
+  // Direct loads of the panel use buffer addressing from the tile's first
+  // column: a uniform base and extent, a per-lane 32-bit byte offset fixed
+  // for the loop, and the tile's uniform k offset (the launcher bounds ldb
+  // so that the offsets fit).  Block q = wave + 8 i of the wave: column
+  // 16 (wave / 4) + 32 i + r of the tile, k offset 8 (wave % 4) + 2 g.
+  const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const double* const bt = B + j0 * ldb;
+  const int bt_bytes = (int)min(((N - 1 - j0) * ldb + K) * 8, (int64_t)0x7fffffff);
+  const int vb = (int)(((16 * (wv >> 2) + r16) * ldb + 8 * (wv & 3) + 2 * g) * 8);
   // the vector-ALU block (q = 4 WN, one wave): column 16 WN + l % 4 (clamped
   // to N - 1), k offset 2 (l / 4)
   const int64_t rcol = (j0 + 16 * WN + (lane & 3) < N) ? j0 + 16 * WN + (lane & 3) : N - 1;
-  const double* const pr = B + rcol * ldb + 2 * (lane >> 2);
+  const int vr = (int)(((rcol - j0) * ldb + 2 * (lane >> 2)) * 8);
   // A fragments of tile t (k = 8 h + 2 g + e for step 2 h + e); in a tile
   // that ends past the split, k is clamped to its last k (B is zero there)
   auto load_a = [&](int64_t t, double (&ra)[BK / 4]) {
@@ -124,25 +130,19 @@ __global__ __launch_bounds__(64 * kStrWaves) void gemm_stream_f64_kernel(
   // Full tile: direct loads, wave w issuing blocks w, w + 8, ...; a block
   // whose 16 columns all lie before N needs no clamping (uniform test)
   auto dma_b = [&](int64_t t, double* bs) {
-    const int64_t kb = kbeg + t * BK;
+    const int kb8 = (int)((kbeg + t * BK) * 8);
 #pragma unroll
     for (int q0 = 0; q0 < NQ; q0 += NW) {
-      const int q = q0 + wave;
+      const int q = q0 + wv;
       if (q < 4 * WN && j0 + 16 * (q >> 2) + 15 < N) {
-        __builtin_amdgcn_global_load_lds((const void*)(pb + opaque(kb + (int64_t)(4 * q0) * ldb)),
-                                         (__attribute__((address_space(3))) void*)(bs + 128 * q),
-                                         16, 0, 0);
+        buffer_load_lds16(bt, bt_bytes, vb, kb8 + (int)(4 * q0 * ldb * 8), bs + 128 * q);
       } else if (q == 4 * WN) {
-        __builtin_amdgcn_global_load_lds((const void*)(pr + opaque(kb)),
-                                         (__attribute__((address_space(3))) void*)(bs + 128 * q),
-                                         16, 0, 0);
+        buffer_load_lds16(bt, bt_bytes, vr, kb8, bs + 128 * q);
       } else if (q < NQ) {
         int col, kk;
         b_src(q, fresh(lane), col, kk);
         const int64_t gc = (j0 + col < N) ? j0 + col : N - 1;
-        __builtin_amdgcn_global_load_lds((const void*)(B + gc * ldb + kb + kk),
-                                         (__attribute__((address_space(3))) void*)(bs + 128 * q),
-                                         16, 0, 0);
+        buffer_load_lds16(bt, bt_bytes, (int)(((gc - j0) * ldb + kk) * 8), kb8, bs + 128 * q);
       }
     }
   };

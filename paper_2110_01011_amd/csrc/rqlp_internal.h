@@ -18,6 +18,19 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 // four consecutive rows 4 (lane/16) + r.
 __device__ __forceinline__ int acc_row_f64(int lane, int r) { return (lane >> 4) + 4 * r; }
 __device__ __forceinline__ int acc_row_f32(int lane, int r) { return 4 * (lane >> 4) + r; }
+
+// 16 bytes per lane from base + voffset + soffset (bytes) into LDS at lds +
+// 16 lane, by the buffer form of the direct load: base and nbytes (the
+// readable extent from base; reads past it return zeros) are wave-uniform,
+// soffset is uniform.  The buffer form is counted on vmcnt only; the
+// FLAT-encoded global form is also counted on lgkmcnt, and the compiler then
+// waits for every outstanding LDS read before using any of them.
+__device__ __forceinline__ void buffer_load_lds16(const void* base, int nbytes, int voffset,
+                                                  int soffset, void* lds) {
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, nbytes, 0x00020000),
+      (__attribute__((address_space(3))) void*)lds, 16, voffset, soffset, 0, 0);
+}
 template <typename T>
 __device__ __forceinline__ int acc_row(int lane, int r);
 template <>
