@@ -54,16 +54,20 @@ __device__ __forceinline__ int tile_wave_idx(int wave) { return wave < 4 ? wave 
 // own one column of X, which they build in the same pivot steps by forward
 // substitution (X row s = Y row s / l_ss, then Y row j -= l_js X row s), so
 // both use the same broadcast column of L.  Every lane evaluates the pivot
-// test and 1/sqrt on its own diagonal entry; the pivot step only moves 1/l_ss
-// (from lane s) and the new column of L (one readlane per row) across lanes,
-// and nothing on the pivot chain touches memory.  A dependent pivot (<=
+// test and 1/sqrt on its own diagonal entry.  The pivot chain runs through
+// registers and lane reads only: lane s + 1 forms its next pivot from its own
+// l (the value the broadcast would give it), and 1/sqrt of it is issued
+// before the rest of step s; every lane takes 1/l_ss (from lane s) and
+// l_{s+1,s} (from lane s + 1) by lane reads, which is all step s + 1 needs.
+// The rest of the column of L, for the updates of entries s + 2 .. 15, goes
+// through a per-step row of LDS (bc) and is read back as broadcasts.  A dependent pivot (<=
 // tol_dep of the column's original diagonal, or non-finite) gives a zero
 // column of L and a zero row of X.  The pivot tests are evaluated after the
 // chain: flags go to *sflag, the per-column dependence marks to colf (LDS).
 __device__ __forceinline__ void factor_diag_tile(double (*dg)[17], double (*dgi)[17],
-                                                 const double* odiag, int J, int d,
-                                                 double tol_dep, double tol_warn, int* colf,
-                                                 int* sflag) {
+                                                 double (*bc)[16], const double* odiag, int J,
+                                                 int d, double tol_dep, double tol_warn,
+                                                 int* colf, int* sflag) {
   const int lane = threadIdx.x & 63;
   const int i = lane & 15;
   const bool rowlane = lane < 16;
@@ -74,23 +78,26 @@ __device__ __forceinline__ void factor_diag_tile(double (*dg)[17], double (*dgi)
 #pragma unroll
   for (int c = 0; c < 16; ++c) a[c] = rowlane ? dg[i][c] : ((c == i) ? 1.0 : 0.0);
   double p = a[0];  // the next pivot, on lane s
+  // NaN and dependent pivots: 0
+  double y = readlane_d((p > thr) ? rsqrt(p) : 0.0, 0);  // 1 / l_ss
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
     mypiv = (i == s) ? p : mypiv;
-    const double yl = (p > thr) ? rsqrt(p) : 0.0;  // NaN and dependent pivots: 0
-    const double y = readlane_d(yl, s);              // 1 / l_ss
     // rows: l_is (l_ss itself on lane s, 0 above the diagonal); columns of
     // X: the finished entry X[s][c]
     const double w = a[s] * y;
     const double v = (!rowlane || i >= s) ? w : 0.0;
     a[s] = v;
     if (s + 1 < 16) {
-      // lane s + 1 updates its own diagonal entry from its own l (the same
-      // value the broadcast gives it), which keeps the broadcast off the
-      // pivot chain
+      // lane s + 1's next pivot from its own l, and its 1/sqrt, first
       p = fma(-w, w, a[s + 1]);
+      const double yn = (p > thr) ? rsqrt(p) : 0.0;
+      if (rowlane) bc[s][i] = v;
+      a[s + 1] = fma(-v, readlane_d(v, s + 1), a[s + 1]);
+      y = readlane_d(yn, s + 1);
+      wave_sync_lds();
 #pragma unroll
-      for (int j = s + 1; j < 16; ++j) a[j] = fma(-v, readlane_d(v, j), a[j]);
+      for (int j = s + 2; j < 16; ++j) a[j] = fma(-v, bc[s][j], a[j]);
     }
   }
   if (lane < 32) {
@@ -282,6 +289,7 @@ __device__ __forceinline__ void cholesky_body(
     int* __restrict__ col_flags, int* __restrict__ flags,
     const double* __restrict__ odiag_src, int64_t odiag_stride) {
   __shared__ double dg2[2][16][17];  // diagonal tile J in dg2[J & 1]
+  __shared__ double bc[16][16];      // the factor wave's column broadcasts
   __shared__ double dgi_all[CHOL_MAX_D / 16][16][17];  // inverse of L_JJ for every J
   __shared__ double tpan[16][17], tdia[16][17];       // stashed tiles (J+1, J), (J+1, J+1)
   __shared__ double wl[16][17];                       // the factor wave's L_{J+1,J}
@@ -321,7 +329,7 @@ __device__ __forceinline__ void cholesky_body(
       __builtin_amdgcn_s_sleep(1);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     for (int J = 0; J < nt; ++J) {
-      factor_diag_tile(dg2[J & 1], dgi_all[J], odiag, J, d, tol_dep, tol_warn, colf, &sflag);
+      factor_diag_tile(dg2[J & 1], dgi_all[J], bc, odiag, J, d, tol_dep, tol_warn, colf, &sflag);
       __syncthreads();  // L_JJ and its inverse are ready; tiles (J+1, J), (J+1, J+1) stashed
       if (J + 1 < nt) {
         // Lookahead: L_{J+1,J}^T = L_JJ^{-1} T_{J+1,J}, then tile (J+1, J+1)
