@@ -54,13 +54,19 @@ __device__ __forceinline__ int tile_wave_idx(int wave) { return wave < 4 ? wave 
 // own one column of X, which they build in the same pivot steps by forward
 // substitution (X row s = Y row s / l_ss, then Y row j -= l_js X row s), so
 // both use the same broadcast column of L.  Every lane evaluates the pivot
-// test and 1/sqrt on its own diagonal entry.  The pivot chain runs through
-// registers and lane reads only: lane s + 1 forms its next pivot from its own
-// l (the value the broadcast would give it), and 1/sqrt of it is issued
-// before the rest of step s; every lane takes 1/l_ss (from lane s) and
-// l_{s+1,s} (from lane s + 1) by lane reads, which is all step s + 1 needs.
-// The rest of the column of L, for the updates of entries s + 2 .. 15, goes
-// through a per-step row of LDS (bc) and is read back as broadcasts.  A dependent pivot (<=
+// test and 1/sqrt on its own diagonal entry (without a branch: 1/sqrt of 1
+// where the test fails).  The pivot chain runs through registers and lane
+// reads only: lane s + 1 forms its next pivot from its own l (the value the
+// broadcast would give it), and 1/sqrt of it is issued before the rest of
+// step s; every lane takes 1/l_ss (from lane s), l_{s+1,s} and l_{s+2,s}
+// (from lanes s + 1, s + 2) by lane reads, which is all steps s + 1 and
+// s + 2 need of step s.  The rest of the column of L, for the updates of
+// entries s + 3 .. 15, goes through a per-step row of LDS (bc): read back
+// as broadcasts at the start of step s + 1 and applied after that step's
+// pivot work (scheduling fences keep the two apart), so the LDS latency is
+// off the chain.  The wave's own LDS accesses complete in order, so no wait
+// separates the write and the reads.  The updates of an entry thus arrive
+// in a fixed order that differs from k order (rounding level only).  A dependent pivot (<=
 // tol_dep of the column's original diagonal, or non-finite) gives a zero
 // column of L and a zero row of X.  The pivot tests are evaluated after the
 // chain: flags go to *sflag, the per-column dependence marks to colf (LDS).
@@ -77,11 +83,23 @@ __device__ __forceinline__ void factor_diag_tile(double (*dg)[17], double (*dgi)
   double a[16];
 #pragma unroll
   for (int c = 0; c < 16; ++c) a[c] = rowlane ? dg[i][c] : ((c == i) ? 1.0 : 0.0);
+  // 1 / sqrt(p) where p passes the pivot test, else 0 (NaN and dependent
+  // pivots included)
+  auto rinv = [&](double p) {
+    const bool ok = p > thr;
+    const double r = rsqrt(ok ? p : 1.0);
+    return ok ? r : 0.0;
+  };
   double p = a[0];  // the next pivot, on lane s
-  // NaN and dependent pivots: 0
-  double y = readlane_d((p > thr) ? rsqrt(p) : 0.0, 0);  // 1 / l_ss
+  double y = readlane_d(rinv(p), 0);  // 1 / l_ss
+  double vp = 0.0;                    // v of the previous step
 #pragma unroll
   for (int s = 0; s < 16; ++s) {
+    // the previous step's column, entries s + 2 .. 15
+    double bj[16];
+#pragma unroll
+    for (int j = s + 2; j < 16; ++j) bj[j] = (s >= 1) ? bc[s - 1][j] : 0.0;
+    __builtin_amdgcn_sched_barrier(0);
     mypiv = (i == s) ? p : mypiv;
     // rows: l_is (l_ss itself on lane s, 0 above the diagonal); columns of
     // X: the finished entry X[s][c]
@@ -91,14 +109,18 @@ __device__ __forceinline__ void factor_diag_tile(double (*dg)[17], double (*dgi)
     if (s + 1 < 16) {
       // lane s + 1's next pivot from its own l, and its 1/sqrt, first
       p = fma(-w, w, a[s + 1]);
-      const double yn = (p > thr) ? rsqrt(p) : 0.0;
-      if (rowlane) bc[s][i] = v;
+      const double yn = rinv(p);
       a[s + 1] = fma(-v, readlane_d(v, s + 1), a[s + 1]);
+      if (s + 2 < 16) a[s + 2] = fma(-v, readlane_d(v, s + 2), a[s + 2]);
       y = readlane_d(yn, s + 1);
-      wave_sync_lds();
-#pragma unroll
-      for (int j = s + 2; j < 16; ++j) a[j] = fma(-v, bc[s][j], a[j]);
+      if (s + 3 < 16 && rowlane) bc[s][i] = v;
     }
+    __builtin_amdgcn_sched_barrier(0);
+    if (s >= 1) {
+#pragma unroll
+      for (int j = s + 2; j < 16; ++j) a[j] = fma(-vp, bj[j], a[j]);
+    }
+    vp = v;
   }
   if (lane < 32) {
     // rows of L to dg (zeros above the diagonal), columns of X to dgi: one
