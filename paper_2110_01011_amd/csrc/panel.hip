@@ -474,17 +474,26 @@ __device__ __forceinline__ void trsm_body(const TX* X, int64_t rows, int d, int6
       }
     }
   }
-  // B fragment of k-step q of block Jb: R[4 q + lk][16 Jb + li]
+  // B fragment of k-step q of block Jb (Jb >= 1): R[4 q + lk][16 Jb + li].
+  // Every load is issued and its value used as loaded, so that the batch
+  // stays in flight until its MFMAs (a load behind a branch, or a select
+  // on its value, makes the compiler wait for it at once): the k-step is
+  // clamped to the block's last (its A operand is zero there) and a column
+  // past d to column 0 (its results land in padding columns of the panel,
+  // which no later block reads and which are not stored).  The pointers are
+  // global ones, so the loads are counted on vmcnt only.
+  typedef __attribute__((address_space(1))) const double gdouble;
+  const gdouble* const Rg = (const gdouble*)R;
+  const gdouble* const Dg = (const gdouble*)dinv;
   auto load_batch = [&](int Jb, int base, double* dst) {
     const int colR = 16 * Jb + li;
-    const bool colok = colR < d;
-    const double* Rc = R + (int64_t)(colok ? colR : 0) * ldr + lk;
+    const gdouble* Rc = Rg + (int64_t)(colR < d ? colR : 0) * ldr + lk;
     const int nk = 4 * Jb;
 #pragma unroll
-    for (int q = 0; q < B; ++q) dst[q] = (base + q < nk && colok) ? Rc[(base + q) * 4] : 0.0;
+    for (int q = 0; q < B; ++q) dst[q] = Rc[min(base + q, nk - 1) * 4];
   };
   auto load_inv = [&](int Jb, double* dst) {
-    const double* T = dinv + (int64_t)Jb * 256;
+    const gdouble* T = Dg + (int64_t)Jb * 256;
 #pragma unroll
     for (int q4 = 0; q4 < 4; ++q4) dst[q4] = T[q4 * 4 + lk + li * 16];
   };
