@@ -85,6 +85,11 @@ __device__ __forceinline__ void gemm_body(const TI* __restrict__ A, int64_t lda,
     for (int c = 0; c < (REMV > 0 ? REMV : 1); ++c) vacc[a][c] = (TC)0;
 
   TI ra[NA], rb[NB];
+  // global-address-space views (the grouped kernels pass pointers read from
+  // descriptors, which the compiler would otherwise access with FLAT
+  // instructions)
+  const global_ptr<const TI> Ag = (global_ptr<const TI>)A;
+  const global_ptr<const TI> Bg = (global_ptr<const TI>)B;
 
   auto gload = [&](int64_t k0) {
 #pragma unroll
@@ -101,7 +106,7 @@ __device__ __forceinline__ void gemm_body(const TI* __restrict__ A, int64_t lda,
       const int64_t gi = i0 + ii, gk = k0 + kk;
       TI v = (TI)0;
       if ((NA * NT == BM * BK || idx < BM * BK) && gi < M && gk < kend)
-        v = TA ? A[gk + gi * lda] : A[gi + gk * lda];
+        v = TA ? Ag[gk + gi * lda] : Ag[gi + gk * lda];
       ra[e] = v;
     }
 #pragma unroll
@@ -110,7 +115,7 @@ __device__ __forceinline__ void gemm_body(const TI* __restrict__ A, int64_t lda,
       const int kk = idx % BK, jj = idx / BK;
       const int64_t gj = j0 + jj, gk = k0 + kk;
       TI v = (TI)0;
-      if ((NB * NT == BK * BN || idx < BK * BN) && gj < N && gk < kend) v = B[gk + gj * ldb];
+      if ((NB * NT == BK * BN || idx < BK * BN) && gj < N && gk < kend) v = Bg[gk + gj * ldb];
       rb[e] = v;
     }
   };
@@ -174,7 +179,7 @@ __device__ __forceinline__ void gemm_body(const TI* __restrict__ A, int64_t lda,
     }
   }
 
-  TO* Cs = C + (int64_t)split * strideS;
+  const global_ptr<TO> Cs = (global_ptr<TO>)C + (int64_t)split * strideS;
 #pragma unroll
   for (int a = 0; a < WM; ++a)
 #pragma unroll

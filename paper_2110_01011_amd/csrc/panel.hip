@@ -166,19 +166,19 @@ __device__ __forceinline__ void chol_tile_wave(
   int tI[kCholSlots], tJ[kCholSlots];
   // Byte offsets stay 32-bit (d <= 224 and the leading dimensions are small)
   // so that the loads and stores use a scalar base and one vector offset.
-  const char* Gb = reinterpret_cast<const char*>(G);
+  const global_ptr<const char> Gb = (global_ptr<const char>)reinterpret_cast<const char*>(G);
   const unsigned ldg8 = 8u * (unsigned)ldg;
-  char* Rb = reinterpret_cast<char*>(R);
+  const global_ptr<char> Rb = (global_ptr<char>)reinterpret_cast<char*>(R);
   const unsigned ldr8 = 8u * (unsigned)ldr;
   const int q0 = 4 * lk;  // R stores: each lane writes rows q0 .. q0 + 3 of one column
   // Four consecutive rows (row0 ..) of column col of R; rows past d dropped.
   auto store4 = [&](int row0, int col, double v0, double v1, double v2, double v3) {
     if (col >= d) return;
-    double* dst =
-        reinterpret_cast<double*>(Rb + (8u * (unsigned)row0 + __umul24((unsigned)col, ldr8)));
+    const global_ptr<double> dst =
+        (global_ptr<double>)(Rb + (8u * (unsigned)row0 + __umul24((unsigned)col, ldr8)));
     if (row0 + 3 < d) {
-      *reinterpret_cast<double2_a8*>(dst) = double2_a8{v0, v1};
-      *reinterpret_cast<double2_a8*>(dst + 2) = double2_a8{v2, v3};
+      *(global_ptr<double2_a8>)dst = double2_a8{v0, v1};
+      *(global_ptr<double2_a8>)(dst + 2) = double2_a8{v2, v3};
     } else {
       if (row0 < d) dst[0] = v0;
       if (row0 + 1 < d) dst[1] = v1;
@@ -204,7 +204,7 @@ __device__ __forceinline__ void chol_tile_wave(
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const unsigned gcol = (unsigned)min(16 * Jt + acc_row_f64(lane, r), d - 1);
-        acc[s][r] = *reinterpret_cast<const double*>(Gb + (grow8 + __umul24(gcol, ldg8)));
+        acc[s][r] = *(global_ptr<const double>)(Gb + (grow8 + __umul24(gcol, ldg8)));
       }
     }
   }
@@ -459,7 +459,7 @@ __device__ __forceinline__ void trsm_body(const TX* X, int64_t rows, int d, int6
   // X block -> LDS: lane (li, lk) takes row r0 + li of columns lk, lk + 4, ...
   {
     const bool rowok = r0 + li < rows;
-    const TX* xr = X + (rowok ? r0 + li : r0);
+    const global_ptr<const TX> xr = (global_ptr<const TX>)X + (rowok ? r0 + li : r0);
     for (int c0 = 0; c0 < dp; c0 += 4 * XC) {
       double xv[XC];
 #pragma unroll
@@ -543,7 +543,7 @@ __device__ __forceinline__ void trsm_body(const TX* X, int64_t rows, int d, int6
   }
   // Q block -> Qx
   if (r0 + li < rows) {
-    TO* qr = Qx + r0 + li;
+    const global_ptr<TO> qr = (global_ptr<TO>)Qx + r0 + li;
     for (int c = lk; c < d; c += 4) qr[(int64_t)c * ldq] = (TO)Qw[li * lq + c];
   }
 }

@@ -19,6 +19,14 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ int acc_row_f64(int lane, int r) { return (lane >> 4) + 4 * r; }
 __device__ __forceinline__ int acc_row_f32(int lane, int r) { return 4 * (lane >> 4) + r; }
 
+// A pointer read from memory (a grouped launch's descriptor) is generic, so
+// the compiler accesses it with FLAT instructions, which count on lgkmcnt as
+// well as vmcnt: every wait for an LDS read then also waits for all
+// outstanding global loads.  Accesses through a global-address-space
+// pointer (the memory is device memory) are global instructions.
+template <typename T>
+using global_ptr = __attribute__((address_space(1))) T*;
+
 // 16 bytes per lane from base + voffset + soffset (bytes) into LDS at lds +
 // 16 lane, by the buffer form of the direct load: base and nbytes (the
 // readable extent from base; reads past it return zeros) are wave-uniform,
