@@ -147,28 +147,31 @@ __global__ __launch_bounds__(64 * waves16(WN), 1) void gemm16_kernel(
   // Wave w loads blocks q = w + NW u: column block q / 2 = NW u / 2 + w / 2,
   // step q % 2 = w % 2 (NW is even).  Each block has a buffer resource whose
   // base is that wave-uniform part of the address; the lane adds its column
-  // r and row group g (voffset), the tile its k0 (soffset).  The buffer
-  // form of the direct load is counted on vmcnt alone, so the fragment
-  // reads below wait for their own LDS reads only (the global form, being
-  // FLAT-encoded, is also counted on lgkmcnt and makes the compiler wait
-  // for every outstanding LDS read before each fragment is used).
-  // Offsets are 32-bit: the launcher bounds ldb.  Columns past N (the
-  // ragged last tile and the pad blocks) are read from the panel's slack
-  // columns (kGemm16PanelSlack) and never stored.
+  // 16 bytes at position 16 lane (voffset), the tile its k-tile (soffset):
+  // the panel is packed (convert_panel16_kernel), so each direct load moves
+  // one contiguous 1 KB block.  The buffer form of the direct load is
+  // counted on vmcnt alone, so the fragment reads below wait for their own
+  // LDS reads only (the global form, being FLAT-encoded, is also counted on
+  // lgkmcnt and makes the compiler wait for every outstanding LDS read
+  // before each fragment is used).  Offsets are 32-bit: the launcher
+  // bounds the panel's size.  Blocks past N (the ragged last tile and the
+  // pad blocks) are read from the panel's slack blocks (kGemm16PanelSlack
+  // columns, zeros) and never stored: the last one read is at most
+  // N / 16 + NQW NW / 2 - 1.
   static_assert(NW % 2 == 0, "waves per workgroup must be even");
-  static_assert(16 * (NQW * NW / 2) <= 16 * WN + kGemm16PanelSlack, "panel slack too small");
+  static_assert(16 * (NQW * NW / 2) <= kGemm16PanelSlack, "panel slack too small");
   const int wv = __builtin_amdgcn_readfirstlane(wave);
+  const int64_t nb = (N + 15) / 16 + kGemm16PanelSlack / 16;  // column blocks of the panel
+  const int64_t pbytes = ldb / BK * nb * 2048;                // the whole panel
   const T16* qbase[NQW];
   int qbytes[NQW];
 #pragma unroll
   for (int u = 0; u < NQW; ++u) {
-    const int64_t col = j0 + 16 * (NW / 2 * u + (wv >> 1));
-    qbase[u] = B + col * ldb + 8 * (wv & 1);
-    // bytes of the panel (N + kGemm16PanelSlack columns) from the base on
-    qbytes[u] = (int)std::min<int64_t>(((N + kGemm16PanelSlack - col) * ldb - 8 * (wv & 1)) * 2,
-                                       0x7fffffff);
+    const int64_t blk = (j0 / 16 + NW / 2 * u + (wv >> 1)) * 2 + (wv & 1);
+    qbase[u] = B + blk * 512;
+    qbytes[u] = (int)std::min<int64_t>(pbytes - blk * 1024, 0x7fffffff);
   }
-  const int voff = (int)((r16 * ldb + 16 * grp) * 2);
+  const int voff = 16 * lane;
 
   float4_t acc[WM][WN];
 #pragma unroll
@@ -183,7 +186,8 @@ __global__ __launch_bounds__(64 * waves16(WN), 1) void gemm16_kernel(
     const int64_t k0 = kbeg + t * BK;
 #pragma unroll
     for (int u = 0; u < NQW; ++u)
-      buffer_load_lds16(qbase[u], qbytes[u], voff, (int)(k0 * 2), bs + (u * NW + wave) * BLK);
+      buffer_load_lds16(qbase[u], qbytes[u], voff, (int)(k0 / BK * nb * 2048),
+                        bs + (u * NW + wave) * BLK);
 #pragma unroll
     for (int a = 0; a < WM; ++a) {
       dst[a][0] = *(const v8*)(arow[a] + 16 * k0);
@@ -305,23 +309,59 @@ __global__ __launch_bounds__(64 * waves16(WN), 1) void gemm16_kernel(
   }
 }
 
-// X (rows x d fp32, ldx) -> X16 (rows x d, ldy), rounded to nearest even;
-// rows [rows, ldy) of X16 are set to zero (contraction padding).  If Ylo is
-// given it receives the rounded residual x - x16 (exact in fp32) the same way.
+// X (rows x d fp32, ldx) -> X16, rounded to nearest even, in the packed
+// panel layout gemm16_kernel loads: for each 64-deep k-tile kt, column
+// block b (of nb = panel16_blocks(d)) and MFMA step s, 512 consecutive
+// elements with lane L = 16 g + r's fragment (k = 64 kt + 16 g + 8 s ..
+// + 7 of column 16 b + r) at 8 L -- the 1 KB a wave's direct load moves to
+// LDS in one piece.  k past rows (up to kp, a multiple of 64) and columns
+// past d (the slack blocks) are zeros.  If Ylo is given it receives the
+// rounded residual x - x16 (exact in fp32) the same way.  One thread per
+// lane position of both steps: 16 consecutive k of one column read (64
+// contiguous bytes, as four 16-byte loads where X's alignment allows),
+// two 16-byte pieces written.
 template <typename T16>
 __global__ __launch_bounds__(256) void convert_panel16_kernel(const float* __restrict__ X,
                                                               int64_t rows, int64_t d,
                                                               int64_t ldx, T16* __restrict__ Y,
-                                                              int64_t ldy,
+                                                              int64_t kp, int64_t nb,
                                                               T16* __restrict__ Ylo) {
-  const int64_t total = ldy * d;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = idx % ldy, j = idx / ldy;
-    const float x = i < rows ? X[i + j * ldx] : 0.0f;
-    const T16 hi = to16(x, (T16*)nullptr);
-    Y[idx] = hi;
-    if (Ylo) Ylo[idx] = to16(x - (float)hi, (T16*)nullptr);
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+  typedef T16 t16x8 __attribute__((ext_vector_type(8)));
+  const bool vec = ((((uintptr_t)X) & 15) == 0) && ((ldx & 3) == 0);
+  const int64_t units = kp / k16BK * nb * 64;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < units;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    const int L = (int)(u & 63);
+    const int64_t rest = u >> 6, b = rest % nb, kt = rest / nb;
+    const int64_t k0 = kt * k16BK + 16 * (L >> 4), col = 16 * b + (L & 15);
+    float x[16];
+    if (col < d && vec && k0 + 15 < rows) {
+      const float4* src = (const float4*)(X + k0 + col * ldx);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float4 v = src[q];
+        x[4 * q] = v.x;
+        x[4 * q + 1] = v.y;
+        x[4 * q + 2] = v.z;
+        x[4 * q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) x[e] = (col < d && k0 + e < rows) ? X[k0 + e + col * ldx] : 0.0f;
+    }
+    const int64_t o = (kt * nb + b) * 1024 + 8 * L;  // step 0; step 1 at + 512
+#pragma unroll
+    for (int st = 0; st < 2; ++st) {
+      t16x8 hi, lo;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        hi[e] = to16(x[8 * st + e], (T16*)nullptr);
+        lo[e] = to16(x[8 * st + e] - (float)hi[e], (T16*)nullptr);
+      }
+      *(u32x4*)(Y + o + 512 * st) = __builtin_bit_cast(u32x4, hi);
+      if (Ylo) *(u32x4*)(Ylo + o + 512 * st) = __builtin_bit_cast(u32x4, lo);
+    }
   }
 }
 
@@ -581,12 +621,12 @@ static hipError_t gemm16_typed(const Gemm16Args& g, hipStream_t st) {
   if (!direct && (g.partial == nullptr ||
                   g.partial_bytes < (size_t)slabs * (size_t)strideS * sizeof(float)))
     return hipErrorInvalidValue;
-  // whole 16-byte fragment loads over the zero-padded contraction (A packed
-  // with its contraction padded to the tile depth); the residual copies
-  // share the layouts of A and B; the panel's
-  // buffer offsets (about 32 ldb bytes at most) fit in 31 bits
-  if (g.lda != pad16(g.K) || g.ldb < pad16(g.K) || (g.ldb % 8) != 0 ||
-      g.ldb >= ((int64_t)1 << 26) ||
+  // whole 16-byte fragment loads over the zero-padded contraction (A and
+  // the panel packed, contractions padded to the tile depth); the residual
+  // copies share the layouts of A and B; the panel's buffer offsets fit in
+  // 31 bits
+  if (g.lda != pad16(g.K) || g.ldb < pad16(g.K) || (g.ldb % k16BK) != 0 ||
+      (int64_t)gemm16_panel_bytes(g.ldb, g.N) >= ((int64_t)1 << 31) ||
       (((uintptr_t)g.A | (uintptr_t)g.B | (uintptr_t)g.A2 | (uintptr_t)g.B2) & 15) != 0 ||
       ((g.A2 == nullptr) != (g.B2 == nullptr)) || (g.A2 && g.f16))
     return hipErrorInvalidValue;
@@ -615,18 +655,27 @@ size_t gemm16_packed_bytes(int64_t rows, int64_t K) {
   return (size_t)((rows + k16BK - 1) / k16BK * k16BK) * (size_t)pad16(K) * 2;
 }
 
+int64_t panel16_blocks(int64_t d) { return (d + 15) / 16 + kGemm16PanelSlack / 16; }
+
+size_t gemm16_panel_bytes(int64_t K, int64_t d) {
+  return (size_t)(pad16(K) / k16BK) * (size_t)panel16_blocks(d) * 1024 * 2;
+}
+
 hipError_t launch_convert_panel16(const float* X, int64_t rows, int64_t d, int64_t ldx, void* Y,
                                   int64_t ldy, bool f16, hipStream_t st, void* Ylo) {
   if (rows <= 0 || d <= 0) return hipSuccess;
-  if (ldy < pad16(rows) || ldy % k16BK != 0) return hipErrorInvalidValue;
-  const int64_t total = ldy * d;
-  const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
+  if (ldy < pad16(rows) || ldy % k16BK != 0 ||
+      ((((uintptr_t)Y) | ((uintptr_t)Ylo)) & 15) != 0)
+    return hipErrorInvalidValue;
+  const int64_t nb = panel16_blocks(d);
+  const int64_t units = ldy / k16BK * nb * 64;
+  const unsigned blocks = (unsigned)std::min<int64_t>((units + 255) / 256, 8192);
   if (f16)
     hipLaunchKernelGGL(convert_panel16_kernel<_Float16>, dim3(blocks), dim3(256), 0, st, X, rows,
-                       d, ldx, (_Float16*)Y, ldy, (_Float16*)Ylo);
+                       d, ldx, (_Float16*)Y, ldy, nb, (_Float16*)Ylo);
   else
     hipLaunchKernelGGL(convert_panel16_kernel<__bf16>, dim3(blocks), dim3(256), 0, st, X, rows, d,
-                       ldx, (__bf16*)Y, ldy, (__bf16*)Ylo);
+                       ldx, (__bf16*)Y, ldy, nb, (__bf16*)Ylo);
   return hipGetLastError();
 }
 

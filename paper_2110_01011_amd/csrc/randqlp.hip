@@ -91,7 +91,7 @@ struct Layout {
   size_t m1, m2, n1, n2, part, part_bytes, G, R[4], Racc[2], Rfin, dinv, colf, scal, flags,
       chs, tsub, tsr, a16, at16, p16, a16lo, p16lo, amax, total;
   int64_t ld16, ldt16;  // leading dimensions of the 16-bit copies of A and A^T
-  int64_t ldp16;        // leading dimension of the 16-bit copy of a panel
+  int64_t ldp16;        // contraction extent of the packed 16-bit copy of a panel
   // predictor and error judge (randqlp_factor_auto only)
   size_t y64, g64, feat, mlp, cls, jd, sums, sres, rerr;
   size_t part2, part2_bytes;  // split-K scratch of the predictor's products
@@ -173,7 +173,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
     L.a16 = take(gemm16_packed_bytes(n, m));
     L.at16 = take(gemm16_packed_bytes(m, n));
     L.ldp16 = gemm16_ld(std::max(m, n));
-    L.p16 = take((size_t)L.ldp16 * (d + kGemm16PanelSlack) * 2);
+    L.p16 = take(gemm16_panel_bytes(L.ldp16, d));
     L.amax = take(16);  // max |a| of the fp16 form's scale
   } else {
     L.ld16 = L.ldt16 = L.ldp16 = 0;
@@ -181,7 +181,7 @@ Layout make_layout(int64_t m, int64_t n, int64_t d, Dtype dt, bool mixed = false
   }
   if (mixed && split) {
     L.a16lo = take(gemm16_packed_bytes(n, m));
-    L.p16lo = take((size_t)L.ldp16 * (d + kGemm16PanelSlack) * 2);
+    L.p16lo = take(gemm16_panel_bytes(L.ldp16, d));
   } else {
     L.a16lo = L.p16lo = 0;
   }
@@ -1624,7 +1624,7 @@ rqlp_status randqlp_gemm(int trans_a, const void* A, int64_t m, int64_t n, int64
     const size_t bytes_op = trans_a ? gemm16_packed_bytes(n, m) : gemm16_packed_bytes(m, n);
     const size_t off_a = 0, off_at = align_up(gemm16_packed_bytes(n, m));
     const size_t off_x = off_at + align_up(gemm16_packed_bytes(m, n));
-    const size_t xbytes = (size_t)ldx16 * (d + kGemm16PanelSlack) * 2;
+    const size_t xbytes = gemm16_panel_bytes(ldx16, d);
     const size_t off_alo = off_x + align_up(xbytes);
     const size_t off_xlo = off_alo + (split ? align_up(bytes_op) : 0);
     const size_t off_p = off_xlo + (split ? align_up(xbytes) : 0);

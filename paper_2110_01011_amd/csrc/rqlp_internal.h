@@ -94,15 +94,16 @@ size_t gemm_partial_bytes(int trans_a, int64_t M, int64_t N, int64_t K, Dtype in
 
 // Precision form: C (M x N fp32) = A16 B16, A16 (M x K) a 16-bit copy in the
 // packed layout launch_convert16 writes (lda = gemm16_ld(K)), B16 (K x N) a
-// 16-bit panel with the contraction index contiguous (B16[k + j*ldb]);
+// 16-bit panel in the packed layout launch_convert_panel16 writes (ldb = its
+// contraction extent, a multiple of 64 >= gemm16_ld(K));
 // split-K partials in `partial` (fixed-order reduction).  With A2 and B2
 // (bf16 only): the rounding residuals of A and B in the layouts of A and B,
 // and C = A16 B16 + A16 B2 + A2 B16 (split bf16 product).
 struct Gemm16Args {
   bool f16;  // false: bf16, true: fp16
   const void* A; int64_t lda;  // 16-bit, packed, lda == gemm16_ld(K), 16-byte aligned
-  const void* B; int64_t ldb;  // 16-bit panel, contraction-contiguous, ldb % 8 == 0,
-                               // kGemm16PanelSlack readable columns past N
+  const void* B; int64_t ldb;  // 16-bit packed panel (launch_convert_panel16 with d = N),
+                               // ldb its contraction extent
   float* C; int64_t ldc;
   const void* A2 = nullptr;  // residual of A (lda), or null
   const void* B2 = nullptr;  // residual of the panel (ldb), or null
@@ -113,9 +114,13 @@ struct Gemm16Args {
   void* ev_end = nullptr;
 };
 hipError_t launch_gemm16(const Gemm16Args& g, hipStream_t st);
-// Columns past N of the panel (and of its residual) that the 16-bit product
-// kernel reads without bounds checks; their values never reach C.
+// Columns past N of the packed panel (and of its residual), zeros, that the
+// 16-bit product kernel reads without bounds checks; their values never
+// reach C.
 constexpr int64_t kGemm16PanelSlack = 320;
+// Bytes of a packed 16-bit panel with contraction K and d columns (slack
+// included).
+size_t gemm16_panel_bytes(int64_t K, int64_t d);
 size_t gemm16_partial_bytes(int64_t M, int64_t N, int64_t K, bool f16, int nseg = 1);
 // Leading dimension of a 16-bit operand with contraction length K: K rounded
 // up to the kernel's tile depth; the padding must hold zeros.
@@ -123,9 +128,12 @@ int64_t gemm16_ld(int64_t K);
 // Bytes of a packed 16-bit operand with `rows` rows and contraction K (rows
 // rounded up to 64, K to gemm16_ld(K)).
 size_t gemm16_packed_bytes(int64_t rows, int64_t K);
-// X (rows x d fp32, ldx) -> Y (rows x d, 16-bit, ldy), nearest even; ldy a
-// multiple of the tile depth >= gemm16_ld(rows); rows [rows, ldy) zeroed.
-// Ylo (optional, same layout): the rounded residual x - y.
+// X (rows x d fp32, ldx) -> Y, 16-bit, nearest even, in the packed panel
+// layout of the 16-bit product kernel: contraction extent ldy (a multiple of
+// the tile depth >= gemm16_ld(rows)), d columns plus kGemm16PanelSlack,
+// gemm16_panel_bytes(ldy, d) bytes, 16-byte aligned; k past rows and the
+// slack columns are zeros.  Ylo (optional, same layout): the rounded
+// residual x - y.
 hipError_t launch_convert_panel16(const float* X, int64_t rows, int64_t d, int64_t ldx, void* Y,
                                   int64_t ldy, bool f16, hipStream_t st, void* Ylo = nullptr);
 // A (m x n fp32) -> packed 16-bit copies A16 (rows: A's n columns,
