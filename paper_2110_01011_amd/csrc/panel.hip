@@ -66,23 +66,31 @@ __device__ __forceinline__ int tile_wave_idx(int wave) { return wave < 4 ? wave 
 // pivot work (scheduling fences keep the two apart), so the LDS latency is
 // off the chain.  The wave's own LDS accesses complete in order, so no wait
 // separates the write and the reads.  The updates of an entry thus arrive
-// in a fixed order that differs from k order (rounding level only).  A dependent pivot (<=
-// tol_dep of the column's original diagonal, or non-finite) gives a zero
-// column of L and a zero row of X.  The pivot tests are evaluated after the
-// chain: flags go to *sflag, the per-column dependence marks to colf (LDS).
-__device__ __forceinline__ void factor_diag_tile(double (*dg)[17], double (*dgi)[17],
-                                                 double (*bc)[16], const double* odiag, int J,
-                                                 int d, double tol_dep, double tol_warn,
-                                                 int* colf, int* sflag) {
+// in a fixed order that differs from k order (rounding level only).  A
+// dependent pivot (<= tol_dep of the column's original diagonal, or
+// non-finite) gives a zero column of L and a zero row of X.  The pivot
+// tests are evaluated after the chain: flags go to *sflag, the per-column
+// dependence marks to colf (LDS).  The tile comes in registers (a, from
+// load_diag_rows), read by the caller ahead of the barrier it waits at.
+__device__ __forceinline__ void load_diag_rows(const double (*dg)[17], double (&a)[16]) {
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15;
+  const bool rowlane = lane < 16;
+#pragma unroll
+  for (int c = 0; c < 16; ++c) a[c] = rowlane ? dg[i][c] : ((c == i) ? 1.0 : 0.0);
+}
+
+__device__ __forceinline__ void factor_diag_tile(double (&a)[16], double (*dg)[17],
+                                                 double (*dgi)[17], double (*bc)[16],
+                                                 const double* odiag, int J, int d,
+                                                 double tol_dep, double tol_warn, int* colf,
+                                                 int* sflag) {
   const int lane = threadIdx.x & 63;
   const int i = lane & 15;
   const bool rowlane = lane < 16;
   const double orig = odiag[16 * J + i];
   const double thr = tol_dep * orig;
   double mypiv = 0.0;
-  double a[16];
-#pragma unroll
-  for (int c = 0; c < 16; ++c) a[c] = rowlane ? dg[i][c] : ((c == i) ? 1.0 : 0.0);
   // 1 / sqrt(p) where p passes the pivot test, else 0 (NaN and dependent
   // pivots included)
   auto rinv = [&](double p) {
@@ -350,8 +358,11 @@ __device__ __forceinline__ void cholesky_body(
     while (__hip_atomic_load(&ready, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < 0)
       __builtin_amdgcn_s_sleep(1);
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    double a[16];  // the next diagonal tile's rows
+    load_diag_rows(dg2[0], a);
     for (int J = 0; J < nt; ++J) {
-      factor_diag_tile(dg2[J & 1], dgi_all[J], bc, odiag, J, d, tol_dep, tol_warn, colf, &sflag);
+      factor_diag_tile(a, dg2[J & 1], dgi_all[J], bc, odiag, J, d, tol_dep, tol_warn, colf,
+                       &sflag);
       __syncthreads();  // L_JJ and its inverse are ready; tiles (J+1, J), (J+1, J+1) stashed
       if (J + 1 < nt) {
         // Lookahead: L_{J+1,J}^T = L_JJ^{-1} T_{J+1,J}, then tile (J+1, J+1)
@@ -378,6 +389,7 @@ __device__ __forceinline__ void cholesky_body(
 #pragma unroll
         for (int r = 0; r < 4; ++r) dn[li][acc_row_f64(lane, r)] = c[r];
         wave_sync_lds();
+        load_diag_rows(dn, a);  // before the barrier: only this wave wrote dn
       }
       __syncthreads();  // panel J is ready
     }
