@@ -9,25 +9,27 @@
 namespace rqlp {
 namespace {
 
-// Precision form: C (fp32) = sum_k A16(i, k) B16[k + j ldb] with both
-// operands 16-bit (bf16 or fp16), fp32 accumulation on the 16x16x32 MFMA.
+// Precision form: C (fp32) = sum_k A16(i, k) B16(k, j) with both operands
+// 16-bit (bf16 or fp16), fp32 accumulation on the 16x16x32 MFMA.
 // A16 is the one-time rounded copy of A (or of A^T) in a packed layout
 // (convert16_kernel): for each 16-row block and 64-deep k-tile one 2 KB
 // chunk, k-tiles of a block consecutive, and within a chunk element
 // (r, k) at 512 ((k % 16) / 8) + 8 (16 (k / 16) + r) + k % 8 -- exactly the
 // two 16-byte fragments lane 16 (k / 16) + r loads, so each fragment load
 // of a wave is 1 KB contiguous and a block's k-chunk streams through DRAM
-// pages in order.  B16 is the rounded panel (convert_panel16_kernel),
-// contiguous along the contraction.  Both are zero-padded along the
-// contraction to a multiple of 64 (k16BK), so every tile is whole and the
-// main loop carries no bounds checks; rows >= M and columns >= N read a
-// clamped (valid) block or padding column and are never stored.
+// pages in order.  B16 is the rounded panel (convert_panel16_kernel), also
+// packed: each 64-deep k-tile as 1 KB blocks in the order the direct loads
+// below move them to LDS.  Both are zero-padded along the contraction to a
+// multiple of 64 (k16BK), so every tile is whole and the main loop carries
+// no bounds checks; rows >= M and columns >= N read a clamped (valid) block
+// or a zero slack block of the panel and are never stored.
 //
 // Workgroup tile (32 WAVES) x (16 WN): the waves are stacked along M, each
 // owning 32 rows (two 16-row blocks) and all 16 WN columns.  A rows belong to
 // a single wave, so A fragments go from HBM straight into registers (one
 // 16-byte load per lane, block and MFMA k-step, two tiles ahead); the panel
-// tile, shared by the waves, is staged through LDS.  Within a 64-deep tile,
+// tile, shared by the waves, goes to a ring of three LDS slots by direct
+// loads.  Results leave as 16-byte stores.  Within a 64-deep tile,
 // MFMA k-step s takes, for lane group g = lane / 16, the tile rows 16 g +
 // 8 s + [0, 8): the same permutation of k for both operands, so the sum is
 // unchanged.
