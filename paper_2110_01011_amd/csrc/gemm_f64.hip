@@ -35,6 +35,13 @@ namespace {
 // registers instead, with zeros past the end.  Rows past M and columns past N read clamped in-bounds data whose
 // results are never stored.
 constexpr int kStrWaves = 8;
+
+// Linear workgroup id L of T -> work item, such that the ids one of the 8
+// XCDs receives (those congruent mod 8) map to one contiguous range.
+__device__ __forceinline__ uint32_t xcd_item(uint32_t L, uint32_t T) {
+  const uint32_t x = L % 8, j = L / 8, per = T / 8, rem = T % 8;
+  return (x < rem) ? x * (per + 1) + j : rem * (per + 1) + (x - rem) * per + j;
+}
 template <int WN>
 constexpr int str_tile_doubles() { return (4 * WN + 1) * 128; }
 
@@ -52,8 +59,20 @@ __global__ __launch_bounds__(64 * kStrWaves) void gemm_stream_f64_kernel(
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int r16 = lane & 15, g = lane >> 4;
-  const int64_t i0 = (int64_t)blockIdx.x * BM, j0 = (int64_t)blockIdx.y * BN;
-  const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+  // The dispatcher hands workgroups to the 8 XCDs in turn by linear id, and
+  // each XCD has its own L2.  The work item of linear id L is renumbered so
+  // that the ids one XCD receives form one contiguous run of (column tile,
+  // row tile, split) items, column tile fastest: the workgroups of one XCD
+  // then need one or two splits' slabs of the panel (not all of it) and
+  // read each row block of A side by side.
+  // (uniform values: kept in scalar registers for the buffer offsets)
+  const uint32_t nx = gridDim.x, ny = gridDim.y, T = nx * ny * gridDim.z;
+  const uint32_t w = xcd_item(blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z), T);
+  const int64_t tile_n = __builtin_amdgcn_readfirstlane(w % ny);
+  const int64_t tile_m = __builtin_amdgcn_readfirstlane((w / ny) % nx);
+  const int64_t split = __builtin_amdgcn_readfirstlane(w / (nx * ny));
+  const int64_t i0 = tile_m * BM, j0 = tile_n * BN;
+  const int64_t kbeg = split * kchunk;
   const int64_t kend = (kbeg + kchunk < K) ? kbeg + kchunk : K;
   const int64_t nt = (kend > kbeg) ? (kend - kbeg + BK - 1) / BK : 0;
 
@@ -254,7 +273,7 @@ __global__ __launch_bounds__(64 * kStrWaves) void gemm_stream_f64_kernel(
     if (t < nt) compute(ra0, Bs0);
   }
 
-  double* Cs = C + (int64_t)blockIdx.z * strideS;
+  double* Cs = C + split * strideS;
 #pragma unroll
   for (int b = 0; b < WN; ++b) {
     const int64_t col = j0 + b * 16 + r16;
