@@ -68,7 +68,7 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // Eigenvalues of the symmetric 64 x 64 G (column-major, ldg) in one
 // workgroup: Householder reduction to tridiagonal form (62 reflections,
 // each a reduction for the vector, a symmetric matrix-vector product and a
-// rank-2 update on the trailing block in LDS, all on one wave), then
+// rank-2 update, the 64 columns shared by the four waves), then
 // bisection with Sturm
 // counts, four threads per eigenvalue (the quad for eigenvalue i finds the
 // i-th smallest, so the order comes for free; each round cuts its interval
@@ -101,7 +101,6 @@ __global__ __launch_bounds__(kFeatThreads) void features_kernel(const double* __
                                                                  int64_t ldg, int k,
                                                                  float* __restrict__ feat) {
   __shared__ double a[kNs][kNs + 1];
-  __shared__ double v[kNs], pw[kNs];
   __shared__ double dg[kNs], eo2[kNs];
   __shared__ double lam[kNs];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -110,65 +109,87 @@ __global__ __launch_bounds__(kFeatThreads) void features_kernel(const double* __
     a[i][j] = G[i + (int64_t)j * ldg];
   }
   __syncthreads();
-  // Householder reduction to tridiagonal form by wave 0 alone (no workgroup
-  // barriers).  Lane i keeps row i of A in registers; step kk reflects rows
-  // r0 = kk + 1 .. 63 of column kk: v = x - alpha e_r0 with
+  // Householder reduction to tridiagonal form by the four waves together:
+  // lane i of wave w keeps A[i][16 w .. 16 w + 15] in registers.  Step kk
+  // reflects rows r0 = kk + 1 .. 63 of column kk: v = x - alpha e_r0 with
   // alpha = -sign(x_r0) ||x||, beta = 2 / v^T v, p = beta A v,
   // w = p - (beta / 2) (p^T v) v, A -= v w^T + w v^T.  v and w vanish
   // outside rows r0 .., so the full-width update leaves the finished part
-  // alone.  Column kk comes from row kk (symmetry) through LDS.  The diagonal
-  // entry a[kk][kk] is final after step kk; the new off-diagonal entry is
-  // alpha.
-  if (wave == 0) {
-    double ar[kNs];
+  // alone.  The wave holding column kk puts it in LDS (barrier); every wave
+  // then forms v (the reductions over the 64 lanes give every wave the same
+  // values), its share of A v over its 16 columns goes to LDS (barrier),
+  // and each wave adds the four shares in the same order and updates its
+  // columns.  The diagonal entry a[kk][kk] is final after step kk; the new
+  // off-diagonal entry is alpha.  (One wave alone spent about 5000 cycles a
+  // step, mostly on its 192 fused multiply-adds per lane.)
+  __shared__ double xcol[2][kNs];         // column kk, by step parity
+  __shared__ double part[2][4][kNs];      // the waves' shares of A v
+  __shared__ double wcol[4][kNs];         // w, one copy per wave
+  static_assert(kFeatThreads == 4 * kNs, "four waves of 64 lanes");
+  {
+    constexpr int CW = kNs / 4;  // columns per wave
+    double ar[CW];
 #pragma unroll
-    for (int j = 0; j < kNs; ++j) ar[j] = a[lane][j];
+    for (int jj = 0; jj < CW; ++jj) ar[jj] = a[lane][CW * wave + jj];
     for (int kk = 0; kk < kNs - 2; ++kk) {
-      const int r0 = kk + 1;
-      if (lane == kk) {
+      const int r0 = kk + 1, par = kk & 1;
+      if (wave == kk / CW) {
+        const int oc = kk % CW;
+        double c = 0.0;
 #pragma unroll
-        for (int j = 0; j < kNs; ++j) pw[j] = ar[j];
+        for (int jj = 0; jj < CW; ++jj) c = (jj == oc) ? ar[jj] : c;
+        xcol[par][lane] = c;
       }
-      wave_sync_lds();
+      __syncthreads();
+      const double* xb = xcol[par];
       const bool mine = lane >= r0;
-      const double x = mine ? pw[lane] : 0.0;
+      const double x = mine ? xb[lane] : 0.0;
       const double ss = wave_sum_d(x * x);
-      const double x0 = readlane_d(x, r0);
+      const double x0 = xb[r0];
       const double nrm = sqrt(ss);
       const double alpha = x0 >= 0.0 ? -nrm : nrm;
       const double vv = lane == r0 ? x0 - alpha : x;
       const double v2 = wave_sum_d(vv * vv);
       const double beta = v2 > 0.0 ? 2.0 / v2 : 0.0;
-      if (lane == 0) {
-        dg[kk] = pw[kk];
+      if (tid == 0) {
+        dg[kk] = xb[kk];
         const double o = v2 > 0.0 ? alpha : x0;
         eo2[kk] = o * o;
       }
-      wave_sync_lds();
-      v[lane] = vv;
-      wave_sync_lds();
+      double vc[CW];
+#pragma unroll
+      for (int jj = 0; jj < CW; ++jj) {
+        const int j = CW * wave + jj;
+        vc[jj] = j < r0 ? 0.0 : (j == r0 ? x0 - alpha : xb[j]);
+      }
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-      for (int j = 0; j < kNs; j += 4) {
-        s0 = fma(ar[j], v[j], s0);
-        s1 = fma(ar[j + 1], v[j + 1], s1);
-        s2 = fma(ar[j + 2], v[j + 2], s2);
-        s3 = fma(ar[j + 3], v[j + 3], s3);
+      for (int jj = 0; jj < CW; jj += 4) {
+        s0 = fma(ar[jj], vc[jj], s0);
+        s1 = fma(ar[jj + 1], vc[jj + 1], s1);
+        s2 = fma(ar[jj + 2], vc[jj + 2], s2);
+        s3 = fma(ar[jj + 3], vc[jj + 3], s3);
       }
-      const double pp = mine ? beta * ((s0 + s1) + (s2 + s3)) : 0.0;
+      part[par][wave][lane] = (s0 + s1) + (s2 + s3);
+      __syncthreads();
+      const double pf = (part[par][0][lane] + part[par][1][lane]) +
+                        (part[par][2][lane] + part[par][3][lane]);
+      const double pp = mine ? beta * pf : 0.0;
       const double pv = wave_sum_d(pp * vv);
       const double wv = pp - 0.5 * beta * pv * vv;
-      pw[lane] = wv;
+      wcol[wave][lane] = wv;
       wave_sync_lds();
 #pragma unroll
-      for (int j = 0; j < kNs; ++j) ar[j] -= vv * pw[j] + wv * v[j];
+      for (int jj = 0; jj < CW; ++jj) ar[jj] -= vv * wcol[wave][CW * wave + jj] + wv * vc[jj];
       wave_sync_lds();
     }
-    if (lane == kNs - 2) dg[kNs - 2] = ar[kNs - 2];
-    if (lane == kNs - 1) {
-      dg[kNs - 1] = ar[kNs - 1];
-      eo2[kNs - 2] = ar[kNs - 2] * ar[kNs - 2];
-      eo2[kNs - 1] = 0.0;
+    if (wave == 3) {
+      if (lane == kNs - 2) dg[kNs - 2] = ar[CW - 2];
+      if (lane == kNs - 1) {
+        dg[kNs - 1] = ar[CW - 1];
+        eo2[kNs - 2] = ar[CW - 2] * ar[CW - 2];
+        eo2[kNs - 1] = 0.0;
+      }
     }
   }
   __syncthreads();
