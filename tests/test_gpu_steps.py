@@ -36,7 +36,11 @@ def test_gaussian_matches_oracle(rq, m, d, seed, sid):
 
 
 SHAPES = [(1000, 700, 25), (333, 517, 210), (64, 64, 1), (2000, 50, 130), (5, 7, 3),
-          (129, 1100, 17), (4000, 3000, 210)]
+          (129, 1100, 17), (4000, 3000, 210),
+          # one row tile, so many k splits of a few 32-deep tiles each (and
+          # a ragged tail), with every MFMA block of the tile full (the
+          # products whose loads are issued among the MFMAs)
+          (70, 300, 210), (97, 3000, 33)]
 
 
 @pytest.mark.parametrize("m,n,d", SHAPES)
