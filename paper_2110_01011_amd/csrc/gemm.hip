@@ -454,7 +454,10 @@ Plan make_plan(int trans_a, int64_t M, int64_t N, int64_t K, bool gram, Dtype in
   }
   p.tiles_m = gram ? (M + kGramBM - 1) / kGramBM : (M + kBM - 1) / kBM;
   const int64_t max_s = std::max<int64_t>(1, K / (kBK * 8));
-  if (!gram && max_s > 1 && in_t == out_t) {
+  // (an fp32 product with fewer rows than one remainder tile, such as the
+  // d x d product Q^T Z, keeps the 64-row tiles below)
+  const bool small_f32 = in_t == DT_F32 && M < 16 * kRemWavesM * rem_wm<float>();
+  if (!gram && max_s > 1 && in_t == out_t && !small_f32) {
     // A-streaming product: MFMA blocks plus vector-ALU columns, as few N
     // tiles (of at most 16 x 16 + 4 columns) as possible.
     const int64_t wmax = 16 * kRemMaxWN + kRemV;
