@@ -98,7 +98,10 @@ def test_gemm_f64_layouts(rq, case):
     assert np.all(np.abs(C - ref) <= bound)
 
 
-@pytest.mark.parametrize("m,n,d", [(1000, 700, 25), (333, 517, 210), (5, 7, 3)])
+@pytest.mark.parametrize("m,n,d", [(1000, 700, 25), (333, 517, 210), (5, 7, 3),
+                                   # fewer rows of op(A) than one remainder tile with a
+                                   # long contraction (the judge's d x d product Q^T Z)
+                                   (4000, 210, 210), (2000, 100, 40)])
 @pytest.mark.parametrize("trans", [1, 0])
 def test_gemm_f32_within_rounding_bound(rq, m, n, d, trans):
     import torch
