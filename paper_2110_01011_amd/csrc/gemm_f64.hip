@@ -47,10 +47,19 @@ __device__ __forceinline__ double buffer_load_f64(const void* base, int nbytes, 
 // results are never stored.
 constexpr int kStrWaves = 8;
 
-// Linear workgroup id L of T -> work item, such that the ids one of the 8
-// XCDs receives (those congruent mod 8) map to one contiguous range.
-__device__ __forceinline__ uint32_t xcd_item(uint32_t L, uint32_t T) {
+// Linear workgroup id L of T -> work item (split-major, S splits of T / S
+// items), such that the ids one of the 8 XCDs receives (those congruent mod
+// 8) map to one contiguous range.  When S divides 8, XCD x takes items of
+// split x % S only (the XCDs x = s, s + S, ... share split s in turn; their
+// counts add up to T / S exactly), so each XCD's L2 holds one panel slab.
+__device__ __forceinline__ uint32_t xcd_item(uint32_t L, uint32_t T, uint32_t S) {
   const uint32_t x = L % 8, j = L / 8, per = T / 8, rem = T % 8;
+  if (8 % S == 0) {
+    const uint32_t s = x % S;
+    uint32_t off = 0;
+    for (uint32_t y = s; y < x; y += S) off += per + (y < rem ? 1u : 0u);
+    return s * (T / S) + off + j;
+  }
   return (x < rem) ? x * (per + 1) + j : rem * (per + 1) + (x - rem) * per + j;
 }
 template <int WN>
@@ -74,11 +83,12 @@ __global__ __launch_bounds__(64 * kStrWaves) void gemm_stream_f64_kernel(
   // each XCD has its own L2.  The work item of linear id L is renumbered so
   // that the ids one XCD receives form one contiguous run of (column tile,
   // row tile, split) items, column tile fastest: the workgroups of one XCD
-  // then need one or two splits' slabs of the panel (not all of it) and
-  // read each row block of A side by side.
+  // then need one split's slab of the panel (one or two when the split
+  // count does not divide 8), not all of it, and read each row block of A
+  // side by side.
   // (uniform values: kept in scalar registers for the buffer offsets)
   const uint32_t nx = gridDim.x, ny = gridDim.y, T = nx * ny * gridDim.z;
-  const uint32_t w = xcd_item(blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z), T);
+  const uint32_t w = xcd_item(blockIdx.x + nx * (blockIdx.y + ny * blockIdx.z), T, gridDim.z);
   const int64_t tile_n = __builtin_amdgcn_readfirstlane(w % ny);
   const int64_t tile_m = __builtin_amdgcn_readfirstlane((w / ny) % nx);
   const int64_t split = __builtin_amdgcn_readfirstlane(w / (nx * ny));
