@@ -478,13 +478,15 @@ __global__ __launch_bounds__(512) void cholesky_grouped_kernel(const GroupChol* 
 // start of each block.  Q leaves LDS at the end, so no global access waits
 // inside the block loop.  X and Qx may be the same array (a wave reads all
 // of its rows before it writes any).
-template <typename TX, typename TO>
+// B: k-steps per batch of B fragments; TL: the type the row block is kept
+// in (LDS), double by default.
+template <typename TX, typename TO, int B = 16, typename TL = double>
 __device__ __forceinline__ void trsm_body(const TX* X, int64_t rows, int d, int64_t ldx,
                                           const double* __restrict__ R, int64_t ldr,
                                           const double* __restrict__ dinv, TO* Qx, int64_t ldq,
                                           const int64_t r0) {
-  extern __shared__ double Qw[];
-  constexpr int B = 16;   // k-steps per batch of B fragments
+  extern __shared__ double lds_raw[];
+  TL* const Qw = reinterpret_cast<TL*>(lds_raw);
   constexpr int XC = 16;  // X values per lane per load round
   const int nt = (d + 15) / 16, dp = nt * 16, lq = dp + 1;
   const int lane = threadIdx.x;
@@ -503,7 +505,7 @@ __device__ __forceinline__ void trsm_body(const TX* X, int64_t rows, int d, int6
 #pragma unroll
       for (int u = 0; u < XC; ++u) {
         const int c = c0 + lk + 4 * u;
-        if (c < dp) Qw[li * lq + c] = xv[u];
+        if (c < dp) Qw[li * lq + c] = (TL)xv[u];
       }
     }
   }
@@ -539,7 +541,7 @@ __device__ __forceinline__ void trsm_body(const TX* X, int64_t rows, int d, int6
     if (J + 1 < nt) load_inv(J + 1, tn);
     double4_t acc0, acc1 = {0, 0, 0, 0}, acc2 = {0, 0, 0, 0}, acc3 = {0, 0, 0, 0};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) acc0[r] = Qw[acc_row_f64(lane, r) * lq + kk + li];
+    for (int r = 0; r < 4; ++r) acc0[r] = (double)Qw[acc_row_f64(lane, r) * lq + kk + li];
     for (int base = 0; base < nk; base += B) {
       if (base + B < nk)
         load_batch(J, base + B, bn);
@@ -547,7 +549,8 @@ __device__ __forceinline__ void trsm_body(const TX* X, int64_t rows, int d, int6
         load_batch(J + 1, 0, bn);
       double ac[B];
 #pragma unroll
-      for (int q = 0; q < B; ++q) ac[q] = (base + q < nk) ? Qw[li * lq + (base + q) * 4 + lk] : 0.0;
+      for (int q = 0; q < B; ++q)
+        ac[q] = (base + q < nk) ? (double)Qw[li * lq + (base + q) * 4 + lk] : 0.0;
 #pragma unroll
       for (int q = 0; q < B; q += 4) {
         acc0 = mma64(-ac[q], bc[q], acc0);
@@ -562,14 +565,15 @@ __device__ __forceinline__ void trsm_body(const TX* X, int64_t rows, int d, int6
     acc2 += acc3;
     acc0 += acc2;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Qw[acc_row_f64(lane, r) * lq + kk + li] = acc0[r];
+    for (int r = 0; r < 4; ++r) Qw[acc_row_f64(lane, r) * lq + kk + li] = (TL)acc0[r];
     wave_sync_lds();
     double4_t res = {0, 0, 0, 0};
 #pragma unroll
-    for (int q4 = 0; q4 < 4; ++q4) res = mma64(Qw[li * lq + kk + q4 * 4 + lk], tb[q4], res);
+    for (int q4 = 0; q4 < 4; ++q4)
+      res = mma64((double)Qw[li * lq + kk + q4 * 4 + lk], tb[q4], res);
     wave_sync_lds();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Qw[acc_row_f64(lane, r) * lq + kk + li] = res[r];
+    for (int r = 0; r < 4; ++r) Qw[acc_row_f64(lane, r) * lq + kk + li] = (TL)res[r];
     wave_sync_lds();
 #pragma unroll
     for (int q4 = 0; q4 < 4; ++q4) tb[q4] = tn[q4];
@@ -763,13 +767,17 @@ __global__ __launch_bounds__(64) void trsm_kernel(const TX* X, int64_t rows, int
 }
 
 // Grouped form: workgroup b solves rows 16 bmap[b].y.. of problem bmap[b].x.
+// The fp32 form keeps its row block in LDS in fp32 (its output precision)
+// and loads R in batches of 8 k-steps: half the LDS and fewer registers, so
+// three waves fit per SIMD instead of two.
 template <typename T>
 __global__ __launch_bounds__(64) void trsm_grouped_kernel(const GroupTrsm* __restrict__ descs,
                                                           const int2* __restrict__ bmap) {
   const int2 b = bmap[blockIdx.x];
   const GroupTrsm t = descs[b.x];
-  trsm_body<T, T>((const T*)t.X, t.rows, t.d, t.ldx, t.R, t.ldr, t.dinv, (T*)t.Qx, t.ldq,
-                  (int64_t)b.y * 16);
+  constexpr bool f32 = sizeof(T) == 4;
+  trsm_body<T, T, f32 ? 8 : 16, T>((const T*)t.X, t.rows, t.d, t.ldx, t.R, t.ldr, t.dinv,
+                                   (T*)t.Qx, t.ldq, (int64_t)b.y * 16);
 }
 
 // Second Cholesky QR pass to first order.  For a nearly orthonormal Q1 the
@@ -1091,7 +1099,7 @@ hipError_t launch_trsm_grouped(Dtype dt, const GroupTrsm* descs, const int2* bma
                                int64_t nblocks, int dmax, hipStream_t st) {
   if (nblocks <= 0) return hipSuccess;
   const int dp = (dmax + 15) / 16 * 16;
-  const size_t lds = (size_t)16 * (dp + 1) * sizeof(double);
+  const size_t lds = (size_t)16 * (dp + 1) * (dt == DT_F64 ? sizeof(double) : sizeof(float));
   if (dt == DT_F64)
     hipLaunchKernelGGL(trsm_grouped_kernel<double>, dim3((unsigned)nblocks), dim3(64), lds, st,
                        descs, bmap);
