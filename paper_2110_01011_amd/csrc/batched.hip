@@ -158,7 +158,7 @@ ProdSet prod_set(std::vector<char>& buf, const std::vector<GroupGemm>& descs, in
   ps.wn = wn;
   if (wn == kRemSet) {
     ps.rem = true;
-    for (int c : {2, 4, 6, 9, 13}) {
+    for (int c : kRemClasses) {
       std::vector<int4> map;
       for (size_t i = 0; i < descs.size(); ++i)
         if (grouped_rem_class(descs[i].N) == c)

@@ -672,9 +672,9 @@ int grouped_wn_round(int wn) { return wn <= 1 ? 1 : wn <= 2 ? 2 : wn <= 4 ? 4 : 
 
 // Remainder-layout classes of the grouped products: 16 wn + 4 columns.
 int grouped_rem_class(int64_t d) {
-  for (int c : {2, 4, 6, 9, 13})
+  for (int c : kRemClasses)
     if (d <= 16 * c + 4) return c;
-  return 13;
+  return kRemClasses[sizeof(kRemClasses) / sizeof(kRemClasses[0]) - 1];
 }
 
 void gemm_rem_grouped_blocks(const GroupGemm& g, int idx, int wn, Dtype dt,
@@ -697,8 +697,12 @@ void rem_grouped_wn(int wn, const GroupGemm* descs, const int4* bmap, int64_t nb
                     hipStream_t st) {
   switch (wn) {
     case 2: run_rem_grouped<T, TA, 2>(descs, bmap, nblocks, st); break;
+    case 3: run_rem_grouped<T, TA, 3>(descs, bmap, nblocks, st); break;
     case 4: run_rem_grouped<T, TA, 4>(descs, bmap, nblocks, st); break;
+    case 5: run_rem_grouped<T, TA, 5>(descs, bmap, nblocks, st); break;
     case 6: run_rem_grouped<T, TA, 6>(descs, bmap, nblocks, st); break;
+    case 7: run_rem_grouped<T, TA, 7>(descs, bmap, nblocks, st); break;
+    case 8: run_rem_grouped<T, TA, 8>(descs, bmap, nblocks, st); break;
     case 9: run_rem_grouped<T, TA, 9>(descs, bmap, nblocks, st); break;
     default: run_rem_grouped<T, TA, 13>(descs, bmap, nblocks, st); break;
   }

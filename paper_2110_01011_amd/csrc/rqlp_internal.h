@@ -283,7 +283,10 @@ struct GroupGemm {
 void gemm_grouped_blocks(const GroupGemm& g, int idx, bool gram, int wn, std::vector<int4>& out);
 int grouped_wn_round(int wn);
 // The remainder layout (16 wn MFMA columns + 4 vector-ALU columns per tile):
-// class width for a product of width d, block list, and launch.
+// class width for a product of width d, block list, and launch.  A product
+// takes the narrowest class that covers d (classes one block apart up to 9,
+// so little of the tile is padding).
+constexpr int kRemClasses[] = {2, 3, 4, 5, 6, 7, 8, 9, 13};
 int grouped_rem_class(int64_t d);
 void gemm_rem_grouped_blocks(const GroupGemm& g, int idx, int wn, Dtype dt,
                              std::vector<int4>& out);
